@@ -1,0 +1,213 @@
+"""Python access to the CPU oracle (oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: the plain, slow reference of the hybrid-symplectic step that the HIP
+library is checked against. Only tests, the smoke check and the benchmark's CPU baseline use it;
+the library never imports it. Arrays are float64 numpy arrays with positions/velocities as
+(n, 3) and masses as (n,); parameters are a dict with G, m0, dt, n1, n2, f_in.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.cpp")
+
+BUILD_CMD = ["g++", "-O2", "-mfma", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+             "-o", _SO, _SRC, "-lquadmath"]
+
+
+def build():
+    subprocess.run(BUILD_CMD, check=True)
+
+
+def _lib():
+    global _L
+    try:
+        return _L
+    except NameError:
+        pass
+    if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        build()
+    L = ctypes.CDLL(_SO)
+    P = ctypes.c_void_p
+    I = ctypes.c_int64
+    D = ctypes.c_double
+    sig = {
+        "or_thresholds": (None, [I, P, P, P, P, P, P, P]),
+        "or_changeover": (None, [D, P, P]),
+        "or_changeover_q": (None, [D, P, P]),
+        "or_kick_acc": (None, [I, P, P, P, P, P, P, P, P, P]),
+        "or_kick_acc_ld": (None, [I, P, P, P, P, P, P, P]),
+        "or_kick_acc_q": (None, [I, P, P, P, P, P, P, P]),
+        "or_kick_acc_rows": (None, [I, P, P, P, P, P, P, I, P, P, P]),
+        "or_encounters": (I, [I, P, P, P, I, P]),
+        "or_jump": (None, [I, P, P, P, P, D]),
+        "or_drift": (ctypes.c_int, [I, P, P, P, D, P]),
+        "or_drift_q": (ctypes.c_int, [I, P, P, P, D]),
+        "or_step": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P]),
+        "or_step_jvp": (ctypes.c_int, [I, P, P, P, P, P, P, P, ctypes.c_int, P, P, P, P]),
+        "or_energy": (None, [I, P, P, P, P, P, P, P, P]),
+        "or_num_threads": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _L = L
+    return L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _prm(p):
+    return np.array([p["G"], p["m0"], p["dt"], p["n1"], p["n2"], p["f_in"]], dtype=np.float64)
+
+
+def num_threads():
+    return _lib().or_num_threads()
+
+
+def thresholds(x, v, m, p):
+    """rc, H, V per body (critical radius and exact-predicate thresholds)."""
+    x = _f64(x); v = _f64(v); m = _f64(m)
+    n = m.shape[0]
+    rc, H, V = np.empty(n), np.empty(n), np.empty(n)
+    _lib().or_thresholds(n, _p(x), _p(v), _p(m), _p(_prm(p)), _p(rc), _p(H), _p(V))
+    return rc, H, V
+
+
+def changeover(y, quad=False):
+    K, d = ctypes.c_double(), ctypes.c_double()
+    f = _lib().or_changeover_q if quad else _lib().or_changeover
+    f(float(y), ctypes.byref(K), ctypes.byref(d))
+    return K.value, d.value
+
+
+def kick_acc(x, m, thr, p, precision="f64"):
+    """H_B accelerations. Returns (acc, acc_ce, l1) for f64; acc only for 'ld' / 'quad'."""
+    x = _f64(x); m = _f64(m)
+    rc, H, V = (_f64(t) for t in thr)
+    n = m.shape[0]
+    acc = np.empty((n, 3))
+    if precision == "f64":
+        ce = np.empty((n, 3)); l1 = np.empty(n)
+        _lib().or_kick_acc(n, _p(x), _p(m), _p(rc), _p(H), _p(V), _p(_prm(p)), _p(acc), _p(ce), _p(l1))
+        return acc, ce, l1
+    f = {"ld": _lib().or_kick_acc_ld, "quad": _lib().or_kick_acc_q}[precision]
+    f(n, _p(x), _p(m), _p(rc), _p(H), _p(V), _p(_prm(p)), _p(acc))
+    return acc
+
+
+def kick_acc_rows(x, m, thr, p, rows):
+    """Accelerations (and l1 scale) of the listed bodies only."""
+    x = _f64(x); m = _f64(m)
+    rc, H, V = (_f64(t) for t in thr)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    k = rows.shape[0]
+    acc = np.empty((k, 3)); l1 = np.empty(k)
+    _lib().or_kick_acc_rows(m.shape[0], _p(x), _p(m), _p(rc), _p(H), _p(V), _p(_prm(p)), k,
+                            _p(rows), _p(acc), _p(l1))
+    return acc, l1
+
+
+def encounters(x, thr, cap=None):
+    """Close pairs (i<j) sorted by (i, j) as an (count, 2) int32 array."""
+    x = _f64(x)
+    rc, H, V = (_f64(t) for t in thr)
+    n = x.shape[0]
+    if cap is None:
+        cnt = _lib().or_encounters(n, _p(x), _p(H), _p(V), 0, None)
+        cap = cnt
+    pairs = np.empty((max(cap, 1), 2), dtype=np.int32)
+    cnt = _lib().or_encounters(n, _p(x), _p(H), _p(V), cap, _p(pairs))
+    return pairs[:min(cnt, cap)].copy()
+
+
+def jump(x, v, m, p, h):
+    x = _f64(x).copy(); v = _f64(v); m = _f64(m)
+    _lib().or_jump(m.shape[0], _p(x), _p(v), _p(m), _p(_prm(p)), h)
+    return x
+
+
+def drift(x, v, p, h, quad=False):
+    x = _f64(x).copy(); v = _f64(v).copy()
+    n = x.shape[0]
+    if quad:
+        st = _lib().or_drift_q(n, _p(x), _p(v), _p(_prm(p)), h)
+        return x, v, st
+    status = np.zeros(n, dtype=np.uint32)
+    _lib().or_drift(n, _p(x), _p(v), _p(_prm(p)), h, _p(status))
+    return x, v, status
+
+
+def step(x, v, m, p, nsteps, thr=None):
+    """nsteps full steps; thresholds from the initial state unless given."""
+    x = _f64(x).copy(); v = _f64(v).copy(); m = _f64(m)
+    if thr is None:
+        rc = H = V = None
+    else:
+        rc, H, V = (_f64(t) for t in thr)
+    st = _lib().or_step(m.shape[0], _p(x), _p(v), _p(m), _p(_prm(p)), nsteps, _p(rc), _p(H), _p(V))
+    return x, v, st
+
+
+def step_jvp(x, v, m, p, nsteps, dx=None, dv=None, dm=None):
+    x = _f64(x); v = _f64(v); m = _f64(m)
+    n = m.shape[0]
+    xo, vo, dxo, dvo = (np.empty((n, 3)) for _ in range(4))
+    dx = None if dx is None else _f64(dx)
+    dv = None if dv is None else _f64(dv)
+    dm = None if dm is None else _f64(dm)
+    st = _lib().or_step_jvp(n, _p(x), _p(v), _p(m), _p(dx), _p(dv), _p(dm), _p(_prm(p)), nsteps,
+                            _p(xo), _p(vo), _p(dxo), _p(dvo))
+    return xo, vo, dxo, dvo, st
+
+
+def energy(x, v, m, p, thr):
+    """dict E, Eprime, L (3,), P (3,)."""
+    x = _f64(x); v = _f64(v); m = _f64(m)
+    rc, H, V = (_f64(t) for t in thr)
+    out = np.empty(8)
+    _lib().or_energy(m.shape[0], _p(x), _p(v), _p(m), _p(_prm(p)), _p(rc), _p(H), _p(V), _p(out))
+    return {"E": out[0], "Eprime": out[1], "L": out[2:5].copy(), "P": out[5:8].copy()}
+
+
+def grad_loss_jvp(x, v, m, p, nsteps, target):
+    """Gradient of L = sum |x(T) - target|^2 w.r.t. (x0, v0, m) by one JVP per input direction."""
+    n = m.shape[0]
+    gx = np.zeros((n, 3)); gv = np.zeros((n, 3)); gm = np.zeros(n)
+    zero3 = np.zeros((n, 3)); zero1 = np.zeros(n)
+    for kind in ("x", "v", "m"):
+        for i in range(n):
+            for c in (range(3) if kind != "m" else [0]):
+                d3 = zero3.copy(); d1 = zero1.copy()
+                if kind == "m":
+                    d1[i] = 1.0
+                else:
+                    d3[i, c] = 1.0
+                xo, vo, dxo, dvo, _ = step_jvp(x, v, m, p, nsteps,
+                                               dx=d3 if kind == "x" else None,
+                                               dv=d3 if kind == "v" else None,
+                                               dm=d1 if kind == "m" else None)
+                g = float(2.0 * ((xo - target) * dxo).sum())
+                if kind == "x":
+                    gx[i, c] = g
+                elif kind == "v":
+                    gv[i, c] = g
+                else:
+                    gm[i] = g
+    return gx, gv, gm

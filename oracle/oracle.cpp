@@ -1,0 +1,560 @@
+// Plain CPU oracle of the hybrid-symplectic planetesimal step (democratic heliocentric
+// coordinates, H = H_A + H_B + H_C; Grimm & Stadel, "Terrestrial planet formation in the era
+// of GPU computing", section "The hybrid symplectic integrator", equations Ha, Hb, Hc, rcrit).
+//
+// TEST INFRASTRUCTURE ONLY. This file is the slow, obviously-correct reference that the HIP
+// library is checked against. Only the test suite, the smoke check and the benchmark's CPU
+// baseline may load it; the library never does. It shares no code, header or constant with
+// the HIP path.
+//
+// Arithmetic: binary64 with round-to-nearest, no fast-math, no contraction (-ffp-contract=off);
+// fma only where written. Every routine is a template over the scalar type so that the same
+// definition also runs in long double, __float128 (accuracy pins) and forward-mode dual numbers
+// (gradient reference). Sums over bodies run in ascending index order with Neumaier's
+// compensated summation (Neumaier 1974) for binary64, plain summation otherwise.
+//
+// Readings of points the paper leaves open (each is listed in the design notes):
+//  * K(r): the changeover of Chambers (1999), the paper cited for the rcrit equation:
+//    y = (r - f_in rc)/((1 - f_in) rc) clamped to [0,1], K = y^2/(2y^2 - 2y + 1), f_in = 0.1.
+//  * The kick is the gradient of H_B with rc held fixed: w = K/r^3 - K'(r)/r^2.
+//  * rc_i = max(n1 R_Hill,i, n2 dt |v_i|), R_Hill,i = |x_i| (m_i/(3 m0))^(1/3); pair radius
+//    rc_ij = max(rc_i, rc_j); rc is computed once from the state at the start of a call and held.
+//  * Encounter predicate, exactly in binary64: with d = x_j - x_i and
+//    r2 = fma(dz,dz,fma(dy,dy,dx*dx)), the pair is close iff
+//    (r2*r2)*r2 < max(H_i,H_j) or r2 < max(V_i,V_j), where
+//    H_i = cH*((r2_i*r2_i)*r2_i)*(mu_i*mu_i), cH = ((n1*n1*n1)*(n1*n1*n1))/9, mu_i = m_i/m0,
+//    V_i = cV*vv_i, cV = (n2*dt)*(n2*dt), vv_i = fma(vz,vz,fma(vy,vy,vx*vx)).
+//    In real arithmetic this is r_ij < max(rc_i, rc_j).
+//  * Step: B(dt/2) C(dt/2) A(dt) C(dt/2) B(dt/2) (operator order of the democratic heliocentric
+//    method the paper cites); A is the Kepler drift about mu = G m0; the [1-K] part of H_A is not
+//    integrated here.
+//  * Kepler drift: f and g functions with the eccentric-anomaly difference form of Kepler's
+//    equation (elliptic) or its hyperbolic analogue, solved by safeguarded Newton iteration in
+//    long double.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <cstdio>
+#include <vector>
+#include <algorithm>
+#include <quadmath.h>
+#include <omp.h>
+
+namespace orc {
+
+// ---------------------------------------------------------------- scalar types and math
+template <class B> struct Dual {
+  B v, d;
+  Dual() : v(0), d(0) {}
+  Dual(double a) : v(a), d(0) {}
+  Dual(B a, B b) : v(a), d(b) {}
+};
+template <class B> Dual<B> operator+(Dual<B> a, Dual<B> b) { return {a.v + b.v, a.d + b.d}; }
+template <class B> Dual<B> operator-(Dual<B> a, Dual<B> b) { return {a.v - b.v, a.d - b.d}; }
+template <class B> Dual<B> operator-(Dual<B> a) { return {-a.v, -a.d}; }
+template <class B> Dual<B> operator*(Dual<B> a, Dual<B> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class B> Dual<B> operator/(Dual<B> a, Dual<B> b) {
+  B q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+template <class B> Dual<B> &operator+=(Dual<B> &a, Dual<B> b) { a = a + b; return a; }
+template <class B> Dual<B> &operator-=(Dual<B> &a, Dual<B> b) { a = a - b; return a; }
+template <class B> Dual<B> &operator*=(Dual<B> &a, Dual<B> b) { a = a * b; return a; }
+template <class B> Dual<B> operator+(Dual<B> a, double b) { return a + Dual<B>(b); }
+template <class B> Dual<B> operator-(Dual<B> a, double b) { return a - Dual<B>(b); }
+template <class B> Dual<B> operator*(Dual<B> a, double b) { return a * Dual<B>(b); }
+template <class B> Dual<B> operator/(Dual<B> a, double b) { return a / Dual<B>(b); }
+template <class B> Dual<B> operator+(double a, Dual<B> b) { return Dual<B>(a) + b; }
+template <class B> Dual<B> operator-(double a, Dual<B> b) { return Dual<B>(a) - b; }
+template <class B> Dual<B> operator*(double a, Dual<B> b) { return Dual<B>(a) * b; }
+template <class B> Dual<B> operator/(double a, Dual<B> b) { return Dual<B>(a) / b; }
+
+typedef Dual<double> dual;
+typedef __float128 quad;
+
+inline double val(double a) { return a; }
+inline double val(long double a) { return (double)a; }
+inline double val(quad a) { return (double)a; }
+template <class B> inline double val(Dual<B> a) { return (double)a.v; }
+
+inline double msqrt(double a) { return std::sqrt(a); }
+inline long double msqrt(long double a) { return sqrtl(a); }
+inline quad msqrt(quad a) { return sqrtq(a); }
+inline double mcbrt(double a) { return std::cbrt(a); }
+inline long double mcbrt(long double a) { return cbrtl(a); }
+inline quad mcbrt(quad a) { return cbrtq(a); }
+inline double msin(double a) { return std::sin(a); }
+inline long double msin(long double a) { return sinl(a); }
+inline quad msin(quad a) { return sinq(a); }
+inline double mcos(double a) { return std::cos(a); }
+inline long double mcos(long double a) { return cosl(a); }
+inline quad mcos(quad a) { return cosq(a); }
+inline double msinh(double a) { return std::sinh(a); }
+inline long double msinh(long double a) { return sinhl(a); }
+inline quad msinh(quad a) { return sinhq(a); }
+inline double mcosh(double a) { return std::cosh(a); }
+inline long double mcosh(long double a) { return coshl(a); }
+inline quad mcosh(quad a) { return coshq(a); }
+template <class B> Dual<B> msqrt(Dual<B> a) { B s = msqrt(a.v); return {s, a.d / (B(2) * s)}; }
+template <class B> Dual<B> mcbrt(Dual<B> a) { B c = mcbrt(a.v); return {c, a.d / (B(3) * c * c)}; }
+template <class B> Dual<B> msin(Dual<B> a) { return {msin(a.v), a.d * mcos(a.v)}; }
+template <class B> Dual<B> mcos(Dual<B> a) { return {mcos(a.v), -a.d * msin(a.v)}; }
+template <class B> Dual<B> msinh(Dual<B> a) { return {msinh(a.v), a.d * mcosh(a.v)}; }
+template <class B> Dual<B> mcosh(Dual<B> a) { return {mcosh(a.v), a.d * msinh(a.v)}; }
+// fma: exact single rounding where the type has one; for duals the product rule.
+inline double mfma(double a, double b, double c) { return std::fma(a, b, c); }
+inline long double mfma(long double a, long double b, long double c) { return fmal(a, b, c); }
+inline quad mfma(quad a, quad b, quad c) { return fmaq(a, b, c); }
+template <class B> Dual<B> mfma(Dual<B> a, Dual<B> b, Dual<B> c) { return a * b + c; }
+
+template <class T> inline T mabs(T a) { return val(a) < 0 ? T(0) - a : a; }
+template <class T> inline T mmax(T a, T b) { return val(a) >= val(b) ? a : b; }
+template <class T> inline T mmin(T a, T b) { return val(a) <= val(b) ? a : b; }
+template <class T> inline double teps() { return 2.220446049250313e-16; }
+template <> inline double teps<long double>() { return 1.0842021724855044e-19; }
+template <> inline double teps<quad>() { return 1.925929944387236e-34; }
+
+// Compensated sum (Neumaier 1974) for binary64; plain sum for any other type.
+template <class T> struct Acc {
+  T s = T(0);
+  void add(T x) { s = s + x; }
+  T get() const { return s; }
+};
+template <> struct Acc<double> {
+  double s = 0, c = 0;
+  void add(double x) {
+    double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+  }
+  double get() const { return s + c; }
+};
+
+// ---------------------------------------------------------------- parameters
+struct Params { double G, m0, dt, n1, n2, f_in; };
+
+// ---------------------------------------------------------------- critical radius (eq. rcrit)
+// Per body: rc_i (used by the changeover), and the exact-predicate thresholds H_i, V_i.
+// Always binary64: the thresholds are fixed parameters of the kick, not differentiated.
+static void thresholds(int64_t n, const double *x, const double *v, const double *m,
+                       const Params &p, double *rc, double *H, double *V) {
+  const double cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
+  const double t = p.n2 * p.dt;
+  const double cV = t * t;
+  for (int64_t i = 0; i < n; i++) {
+    const double *xi = x + 3 * i, *vi = v + 3 * i;
+    double r2 = std::fma(xi[2], xi[2], std::fma(xi[1], xi[1], xi[0] * xi[0]));
+    double mu = m[i] / p.m0;
+    double vv = std::fma(vi[2], vi[2], std::fma(vi[1], vi[1], vi[0] * vi[0]));
+    H[i] = (cH * ((r2 * r2) * r2)) * (mu * mu);
+    V[i] = cV * vv;
+    double rhill = std::sqrt(r2) * std::cbrt(mu / 3.0);
+    rc[i] = std::max(p.n1 * rhill, t * std::sqrt(vv));
+  }
+}
+
+// Exact binary64 encounter predicate on the positions' binary64 values.
+static inline bool close_pair(const double *xi, const double *xj, double Hi, double Hj,
+                              double Vi, double Vj, double *r2out) {
+  double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
+  double r2 = std::fma(dz, dz, std::fma(dy, dy, dx * dx));
+  *r2out = r2;
+  return ((r2 * r2) * r2 < std::max(Hi, Hj)) || (r2 < std::max(Vi, Vj));
+}
+
+// ---------------------------------------------------------------- changeover K(y)
+template <class T> static void changeover(T y, T *K, T *dKdy) {
+  if (val(y) <= 0) { *K = T(0); *dKdy = T(0); return; }
+  if (val(y) >= 1) { *K = T(1); *dKdy = T(0); return; }
+  T D = T(2) * y * y - T(2) * y + T(1);
+  *K = y * y / D;
+  *dKdy = T(2) * y * (T(1) - y) / (D * D);
+}
+
+// Pair weight w(r) such that the H_B acceleration of i due to j is G m_j w d, d = x_j - x_i.
+template <class T> static T pair_weight(T r2, bool close, double rcij, double f_in) {
+  T r = msqrt(r2);
+  T r3 = r2 * r;
+  if (!close) return T(1) / r3;
+  T y = (r - T(f_in * rcij)) / T((1.0 - f_in) * rcij);
+  T K, dKdy;
+  changeover(y, &K, &dKdy);
+  T dKdr = dKdy / T((1.0 - f_in) * rcij);
+  return K / r3 - dKdr / r2;
+}
+
+// ---------------------------------------------------------------- H_B kick (eq. Hb)
+// acc[i] = G sum_{j != i} m_j w_ij (x_j - x_i); acc_ce = the complementary [1-K] part, so that
+// acc + acc_ce is the plain Newtonian pull of the other planetesimals; l1[i] =
+// G sum_j m_j |w_ij| r_ij, the scale used for relative-error statements.
+template <class T>
+static void kick_acc(int64_t n, const T *x, const T *m, const double *rc, const double *H,
+                     const double *V, const Params &p, T *acc, T *acc_ce, double *l1) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; i++) {
+    double xi_d[3] = {val(x[3 * i]), val(x[3 * i + 1]), val(x[3 * i + 2])};
+    Acc<T> a[3], ace[3];
+    double l1s = 0;
+    for (int64_t j = 0; j < n; j++) {
+      if (j == i) continue;
+      double xj_d[3] = {val(x[3 * j]), val(x[3 * j + 1]), val(x[3 * j + 2])};
+      double r2d;
+      bool close = close_pair(xi_d, xj_d, H[i], H[j], V[i], V[j], &r2d);
+      T d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+      T r2 = mfma(d[2], d[2], mfma(d[1], d[1], d[0] * d[0]));
+      T w = pair_weight(r2, close, std::max(rc[i], rc[j]), p.f_in);
+      T s = T(p.G) * m[j] * w;
+      for (int k = 0; k < 3; k++) a[k].add(s * d[k]);
+      if (close) {
+        T sn = T(p.G) * m[j] / (r2 * msqrt(r2));
+        for (int k = 0; k < 3; k++) ace[k].add((sn - s) * d[k]);
+      }
+      l1s += p.G * val(m[j]) * std::fabs(val(w)) * std::sqrt(val(r2));
+    }
+    for (int k = 0; k < 3; k++) {
+      acc[3 * i + k] = a[k].get();
+      if (acc_ce) acc_ce[3 * i + k] = ace[k].get();
+    }
+    if (l1) l1[i] = l1s;
+  }
+}
+
+// ---------------------------------------------------------------- encounter list
+// All close pairs (i < j), in ascending (i, j) order. Returns the true count; writes at most cap.
+static int64_t encounters(int64_t n, const double *x, const double *H, const double *V,
+                          int64_t cap, int32_t *pairs) {
+  std::vector<std::vector<int32_t>> rows(n);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; i++)
+    for (int64_t j = i + 1; j < n; j++) {
+      double r2;
+      if (close_pair(x + 3 * i, x + 3 * j, H[i], H[j], V[i], V[j], &r2)) rows[i].push_back((int32_t)j);
+    }
+  int64_t c = 0;
+  for (int64_t i = 0; i < n; i++)
+    for (int32_t j : rows[i]) {
+      if (c < cap) { pairs[2 * c] = (int32_t)i; pairs[2 * c + 1] = j; }
+      c++;
+    }
+  return c;
+}
+
+// ---------------------------------------------------------------- H_C jump (eq. Hc)
+template <class T> static void jump(int64_t n, T *x, const T *v, const T *m, const Params &p, T h) {
+  Acc<T> P[3];
+  for (int64_t j = 0; j < n; j++)
+    for (int k = 0; k < 3; k++) P[k].add(m[j] * v[3 * j + k]);
+  T s[3];
+  for (int k = 0; k < 3; k++) s[k] = h * (P[k].get() / T(p.m0));
+  for (int64_t i = 0; i < n; i++)
+    for (int k = 0; k < 3; k++) x[3 * i + k] = x[3 * i + k] + s[k];
+}
+
+// ---------------------------------------------------------------- H_A Kepler drift (eq. Ha)
+// Advances (x, v) of one body along its two-body orbit about mu for time dt with the f and g
+// functions. Returns 0, or 1 if the anomaly iteration did not converge, 2 for an orbit so close
+// to parabolic that neither branch applies.
+template <class T> static int kepler(T *x, T *v, double mu_d, double dt_d) {
+  T mu = T(mu_d), dt = T(dt_d);
+  T r0 = msqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  T v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  T u = x[0] * v[0] + x[1] * v[1] + x[2] * v[2];
+  T alpha = T(2) / r0 - v2 / mu;  // 1/a
+  double ar = val(alpha) * val(r0);
+  if (std::fabs(ar) < 1e-10) return 2;
+  const double tol = 8 * teps<T>();
+  T f, g, fd, gd;
+  int status = 0;
+  if (val(alpha) > 0) {
+    T a = T(1) / alpha;
+    T n = msqrt(mu * alpha * alpha * alpha);
+    T c = T(1) - r0 * alpha;        // e cos E0
+    T s = u / msqrt(mu * a);        // e sin E0
+    T M = n * dt;
+    auto F = [&](T E) { return E - c * msin(E) + s * (T(1) - mcos(E)) - M; };
+    auto Fp = [&](T E) { return T(1) - c * mcos(E) + s * msin(E); };
+    // root bracket: |c sin E - s (1 - cos E)| <= |c| + 2|s| < 3 for e < 1
+    T lo = M - T(3), hi = M + T(3), E = M;
+    int it = 0;
+    for (; it < 200; it++) {
+      T Fx = F(E);
+      if (val(Fx) > 0) hi = E; else lo = E;
+      T En = E - Fx / Fp(E);
+      if (!(val(En) > val(lo) && val(En) < val(hi))) En = (lo + hi) * 0.5;
+      double step = std::fabs(val(En - E));
+      E = En;
+      if (step <= tol * (1 + std::fabs(val(E)))) break;
+    }
+    if (it == 200) status = 1;
+    for (int k = 0; k < 2; k++) E = E - F(E) / Fp(E);  // carries exact implicit derivatives
+    T sE = msin(E), cE = mcos(E);
+    T hs = msin(E * 0.5);
+    T omc = T(2) * hs * hs;  // 1 - cos E
+    T r = a * (T(1) - c * cE + s * sE);
+    f = T(1) - (a / r0) * omc;
+    g = dt - (E - sE) / n;
+    fd = T(0) - msqrt(mu * a) * sE / (r * r0);
+    gd = T(1) - (a / r) * omc;
+  } else {
+    T A = T(0) - T(1) / alpha;  // |a|
+    T n = msqrt(mu / (A * A * A));
+    T c = T(1) + r0 / A;            // e cosh H0
+    T s = u / msqrt(mu * A);        // e sinh H0
+    T M = n * dt;
+    auto F = [&](T H) { return c * msinh(H) + s * (mcosh(H) - T(1)) - H - M; };
+    auto Fp = [&](T H) { return c * mcosh(H) + s * msinh(H) - T(1); };
+    T lo = T(0), hi = T(0);
+    if (val(M) >= 0) { hi = T(1); while (val(F(hi)) < 0) hi = hi * 2.0; }
+    else { lo = T(-1); while (val(F(lo)) > 0) lo = lo * 2.0; }
+    T H = (lo + hi) * 0.5;
+    int it = 0;
+    for (; it < 400; it++) {
+      T Fx = F(H);
+      if (val(Fx) > 0) hi = H; else lo = H;
+      T Hn = H - Fx / Fp(H);
+      if (!(val(Hn) > val(lo) && val(Hn) < val(hi))) Hn = (lo + hi) * 0.5;
+      double step = std::fabs(val(Hn - H));
+      H = Hn;
+      if (step <= tol * (1 + std::fabs(val(H)))) break;
+    }
+    if (it == 400) status = 1;
+    for (int k = 0; k < 2; k++) H = H - F(H) / Fp(H);
+    T sH = msinh(H), cH = mcosh(H);
+    T r = A * (c * cH + s * sH - T(1));
+    f = T(1) - (A / r0) * (cH - T(1));
+    g = dt - (sH - H) / n;
+    fd = T(0) - msqrt(mu * A) * sH / (r * r0);
+    gd = T(1) - (A / r) * (cH - T(1));
+  }
+  T xn[3], vn[3];
+  for (int k = 0; k < 3; k++) {
+    xn[k] = f * x[k] + g * v[k];
+    vn[k] = fd * x[k] + gd * v[k];
+  }
+  for (int k = 0; k < 3; k++) { x[k] = xn[k]; v[k] = vn[k]; }
+  return status;
+}
+
+// Drift of all bodies. binary64 states are advanced in long double and rounded once.
+template <class T> static int drift_all(int64_t n, T *x, T *v, const Params &p, double h, uint32_t *st) {
+  int worst = 0;
+  for (int64_t i = 0; i < n; i++) {
+    int s = kepler<T>(x + 3 * i, v + 3 * i, p.G * p.m0, h);
+    if (st) st[i] = (uint32_t)s;
+    worst = std::max(worst, s);
+  }
+  return worst;
+}
+template <> int drift_all<double>(int64_t n, double *x, double *v, const Params &p, double h, uint32_t *st) {
+  int worst = 0;
+  for (int64_t i = 0; i < n; i++) {
+    long double xl[3], vl[3];
+    for (int k = 0; k < 3; k++) { xl[k] = x[3 * i + k]; vl[k] = v[3 * i + k]; }
+    int s = kepler<long double>(xl, vl, p.G * p.m0, h);
+    for (int k = 0; k < 3; k++) { x[3 * i + k] = (double)xl[k]; v[3 * i + k] = (double)vl[k]; }
+    if (st) st[i] = (uint32_t)s;
+    worst = std::max(worst, s);
+  }
+  return worst;
+}
+
+// ---------------------------------------------------------------- one call of nsteps steps
+// B(h) C(h) A(dt) C(h) B(h) per step, h = dt/2, thresholds from the state at call start.
+template <class T>
+static int steps(int64_t n, T *x, T *v, const T *m, const Params &p, int nsteps,
+                 const double *rc, const double *H, const double *V) {
+  std::vector<T> acc(3 * n);
+  T h = T(0.5 * p.dt);
+  int worst = 0;
+  for (int s = 0; s < nsteps; s++) {
+    kick_acc<T>(n, x, m, rc, H, V, p, acc.data(), nullptr, nullptr);
+    for (int64_t i = 0; i < 3 * n; i++) v[i] = v[i] + h * acc[i];
+    jump<T>(n, x, v, m, p, h);
+    worst = std::max(worst, drift_all<T>(n, x, v, p, p.dt, nullptr));
+    jump<T>(n, x, v, m, p, h);
+    kick_acc<T>(n, x, m, rc, H, V, p, acc.data(), nullptr, nullptr);
+    for (int64_t i = 0; i < 3 * n; i++) v[i] = v[i] + h * acc[i];
+  }
+  return worst;
+}
+
+static void vals(int64_t n3, const dual *a, double *out) { for (int64_t i = 0; i < n3; i++) out[i] = a[i].v; }
+
+}  // namespace orc
+
+using namespace orc;
+
+// ================================================================ C entry points
+extern "C" {
+
+// Parameter block shared by all calls: G, m0, dt, n1, n2, f_in.
+void or_thresholds(int64_t n, const double *x, const double *v, const double *m,
+                   const double *prm, double *rc, double *H, double *V) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  thresholds(n, x, v, m, p, rc, H, V);
+}
+
+void or_changeover(double y, double *K, double *dKdy) { changeover<double>(y, K, dKdy); }
+void or_changeover_q(double y, double *K, double *dKdy) {
+  quad k, d;
+  changeover<quad>(quad(y), &k, &d);
+  *K = (double)k; *dKdy = (double)d;
+}
+
+void or_kick_acc(int64_t n, const double *x, const double *m, const double *rc, const double *H,
+                 const double *V, const double *prm, double *acc, double *acc_ce, double *l1) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  kick_acc<double>(n, x, m, rc, H, V, p, acc, acc_ce, l1);
+}
+
+// The same sum in long double / __float128, rounded to binary64 at the end (accuracy pins).
+void or_kick_acc_ld(int64_t n, const double *x, const double *m, const double *rc, const double *H,
+                    const double *V, const double *prm, double *acc) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<long double> xl(x, x + 3 * n), ml(m, m + n), al(3 * n);
+  kick_acc<long double>(n, xl.data(), ml.data(), rc, H, V, p, al.data(), nullptr, nullptr);
+  for (int64_t i = 0; i < 3 * n; i++) acc[i] = (double)al[i];
+}
+void or_kick_acc_q(int64_t n, const double *x, const double *m, const double *rc, const double *H,
+                   const double *V, const double *prm, double *acc) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<quad> xq(3 * n), mq(n), aq(3 * n);
+  for (int64_t i = 0; i < 3 * n; i++) xq[i] = x[i];
+  for (int64_t i = 0; i < n; i++) mq[i] = m[i];
+  kick_acc<quad>(n, xq.data(), mq.data(), rc, H, V, p, aq.data(), nullptr, nullptr);
+  for (int64_t i = 0; i < 3 * n; i++) acc[i] = (double)aq[i];
+}
+
+// Accelerations of a subset of bodies (rows idx[0..k)) against all n bodies: lets a test check
+// sampled outputs of a large system one by one.
+void or_kick_acc_rows(int64_t n, const double *x, const double *m, const double *rc, const double *H,
+                      const double *V, const double *prm, int64_t k, const int64_t *idx,
+                      double *acc, double *l1) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < k; q++) {
+    int64_t i = idx[q];
+    Acc<double> a[3];
+    double l1s = 0;
+    for (int64_t j = 0; j < n; j++) {
+      if (j == i) continue;
+      double r2d;
+      bool close = close_pair(x + 3 * i, x + 3 * j, H[i], H[j], V[i], V[j], &r2d);
+      double d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+      double w = pair_weight<double>(r2d, close, std::max(rc[i], rc[j]), p.f_in);
+      double s = p.G * m[j] * w;
+      for (int c = 0; c < 3; c++) a[c].add(s * d[c]);
+      l1s += p.G * m[j] * std::fabs(w) * std::sqrt(r2d);
+    }
+    for (int c = 0; c < 3; c++) acc[3 * q + c] = a[c].get();
+    if (l1) l1[q] = l1s;
+  }
+}
+
+int64_t or_encounters(int64_t n, const double *x, const double *H, const double *V, int64_t cap,
+                      int32_t *pairs) {
+  return encounters(n, x, H, V, cap, pairs);
+}
+
+void or_jump(int64_t n, double *x, const double *v, const double *m, const double *prm, double h) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  jump<double>(n, x, v, m, p, h);
+}
+
+int or_drift(int64_t n, double *x, double *v, const double *prm, double h, uint32_t *status) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  return drift_all<double>(n, x, v, p, h, status);
+}
+
+// Kepler drift carried out in __float128 (accuracy pin of the long double drift).
+int or_drift_q(int64_t n, double *x, double *v, const double *prm, double h) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  int worst = 0;
+  for (int64_t i = 0; i < n; i++) {
+    quad xq[3], vq[3];
+    for (int k = 0; k < 3; k++) { xq[k] = x[3 * i + k]; vq[k] = v[3 * i + k]; }
+    worst = std::max(worst, kepler<quad>(xq, vq, p.G * p.m0, h));
+    for (int k = 0; k < 3; k++) { x[3 * i + k] = (double)xq[k]; v[3 * i + k] = (double)vq[k]; }
+  }
+  return worst;
+}
+
+// nsteps full steps. If rc/H/V are NULL they are computed from the initial state.
+int or_step(int64_t n, double *x, double *v, const double *m, const double *prm, int nsteps,
+            const double *rc_in, const double *H_in, const double *V_in) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<double> rc(n), H(n), V(n);
+  if (rc_in && H_in && V_in) {
+    std::copy(rc_in, rc_in + n, rc.begin()); std::copy(H_in, H_in + n, H.begin());
+    std::copy(V_in, V_in + n, V.begin());
+  } else {
+    thresholds(n, x, v, m, p, rc.data(), H.data(), V.data());
+  }
+  return steps<double>(n, x, v, m, p, nsteps, rc.data(), H.data(), V.data());
+}
+
+// Forward-mode derivative (JVP) of nsteps steps in the direction (dx, dv, dm), thresholds held
+// fixed at their values from the undisturbed initial state. Outputs the final state and its
+// directional derivative.
+int or_step_jvp(int64_t n, const double *x, const double *v, const double *m, const double *dx,
+                const double *dv, const double *dm, const double *prm, int nsteps,
+                double *x_out, double *v_out, double *dx_out, double *dv_out) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<double> rc(n), H(n), V(n);
+  thresholds(n, x, v, m, p, rc.data(), H.data(), V.data());
+  std::vector<dual> X(3 * n), Vv(3 * n), M(n);
+  for (int64_t i = 0; i < 3 * n; i++) { X[i] = dual(x[i], dx ? dx[i] : 0.0); Vv[i] = dual(v[i], dv ? dv[i] : 0.0); }
+  for (int64_t i = 0; i < n; i++) M[i] = dual(m[i], dm ? dm[i] : 0.0);
+  int st = steps<dual>(n, X.data(), Vv.data(), M.data(), p, nsteps, rc.data(), H.data(), V.data());
+  vals(3 * n, X.data(), x_out);
+  vals(3 * n, Vv.data(), v_out);
+  for (int64_t i = 0; i < 3 * n; i++) { dx_out[i] = X[i].d; dv_out[i] = Vv[i].d; }
+  return st;
+}
+
+// Diagnostics: E (full Newtonian), Eprime (pair term weighted by K, the quantity the
+// hot-path step conserves), angular momentum L and total momentum P (barycentric velocities).
+void or_energy(int64_t n, const double *x, const double *v, const double *m, const double *prm,
+               const double *rc, const double *H, const double *V, double *out /*E, E', L[3], P[3]*/) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  Acc<double> kin, sun, pairN, pairK, L[3], P[3];
+  for (int64_t i = 0; i < n; i++) {
+    const double *xi = x + 3 * i, *vi = v + 3 * i;
+    kin.add(0.5 * m[i] * (vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]));
+    sun.add(-p.G * p.m0 * m[i] / std::sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]));
+    L[0].add(m[i] * (xi[1] * vi[2] - xi[2] * vi[1]));
+    L[1].add(m[i] * (xi[2] * vi[0] - xi[0] * vi[2]));
+    L[2].add(m[i] * (xi[0] * vi[1] - xi[1] * vi[0]));
+    for (int k = 0; k < 3; k++) P[k].add(m[i] * vi[k]);
+  }
+  std::vector<double> eN(n), eK(n);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; i++) {
+    Acc<double> aN, aK;
+    for (int64_t j = i + 1; j < n; j++) {
+      double r2;
+      bool close = close_pair(x + 3 * i, x + 3 * j, H[i], H[j], V[i], V[j], &r2);
+      double r = std::sqrt(r2);
+      double e = -p.G * m[i] * m[j] / r;
+      aN.add(e);
+      double K = 1, dK;
+      if (close) {
+        double rcij = std::max(rc[i], rc[j]);
+        changeover<double>((r - p.f_in * rcij) / ((1 - p.f_in) * rcij), &K, &dK);
+      }
+      aK.add(e * K);
+    }
+    eN[i] = aN.get();
+    eK[i] = aK.get();
+  }
+  for (int64_t i = 0; i < n; i++) { pairN.add(eN[i]); pairK.add(eK[i]); }
+  double Pv[3] = {P[0].get(), P[1].get(), P[2].get()};
+  double hc = (Pv[0] * Pv[0] + Pv[1] * Pv[1] + Pv[2] * Pv[2]) / (2 * p.m0);
+  out[0] = kin.get() + sun.get() + pairN.get() + hc;
+  out[1] = kin.get() + sun.get() + pairK.get() + hc;
+  for (int k = 0; k < 3; k++) { out[2 + k] = L[k].get(); out[5 + k] = Pv[k]; }
+}
+
+int or_num_threads(void) { return omp_get_max_threads(); }
+
+}  // extern "C"

@@ -1,0 +1,392 @@
+"""Pins of the CPU oracle against closed forms, invariants and independent references.
+
+Each test names the passage of the paper it follows (Grimm & Stadel, section "The hybrid
+symplectic integrator": equations Ha, Hb, Hc and rcrit) and pins the oracle to something other
+than itself: hand-derived closed forms, a textbook Newtonian sum, Kepler's equation solved from
+orbital elements, finite differences of the oracle's own potential, and conservation laws.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import diskgen
+import oracle
+
+
+def P(**kw):
+    p = dict(diskgen.PARAMS)
+    p.update(kw)
+    return p
+
+
+def newtonian(x, m, G=1.0):
+    """Textbook pairwise Newtonian accelerations (brute force, numpy)."""
+    d = x[None, :, :] - x[:, None, :]           # d[i, j] = x_j - x_i
+    r2 = (d * d).sum(-1)
+    np.fill_diagonal(r2, np.inf)
+    return G * (m[None, :, None] * d / r2[..., None] ** 1.5).sum(1)
+
+
+def no_close(x, v, m, p):
+    """Thresholds with every pair far (n1 = n2 = 0): the K = 1 regime."""
+    return oracle.thresholds(x, v, m, P(n1=0.0, n2=0.0))
+
+
+# ------------------------------------------------------------------ changeover K (eq. Hb)
+def test_changeover_endpoints_and_symmetry():
+    for y, K in [(0.0, 0.0), (1.0, 1.0), (0.5, 0.5), (-3.0, 0.0), (7.0, 1.0)]:
+        assert oracle.changeover(y)[0] == K
+    assert oracle.changeover(0.0)[1] == 0.0 and oracle.changeover(1.0)[1] == 0.0
+    for y in np.linspace(0.01, 0.99, 37):
+        K, d = oracle.changeover(y)
+        K2, _ = oracle.changeover(1.0 - y)
+        assert abs(K + K2 - 1.0) < 4e-16
+        h = 1e-6
+        fd = (oracle.changeover(y + h)[0] - oracle.changeover(y - h)[0]) / (2 * h)
+        assert abs(fd - d) < 1e-9
+        assert d > 0
+
+
+def test_changeover_quad_agrees():
+    for y in np.linspace(0.0, 1.0, 21):
+        assert abs(oracle.changeover(y)[0] - oracle.changeover(y, quad=True)[0]) < 4e-16
+
+
+# ------------------------------------------------------------------ kick, K = 1 regime
+def test_two_body_closed_form(params):
+    x = np.array([[1.0, 0.0, 0.0], [1.0, 3.0, 4.0]])
+    m = np.array([2e-3, 5e-3])
+    v = np.zeros((2, 3))
+    acc, ce, _ = oracle.kick_acc(x, m, no_close(x, v, m, params), params)
+    np.testing.assert_allclose(acc[0], 5e-3 * np.array([0.0, 3.0, 4.0]) / 125.0, rtol=1e-15)
+    np.testing.assert_allclose(acc[1], -2e-3 * np.array([0.0, 3.0, 4.0]) / 125.0, rtol=1e-15)
+    assert np.all(ce == 0)
+
+
+def test_triangle_and_square_closed_form(params):
+    s, m0 = 0.7, 1e-3
+    c = np.array([2.0, -1.0, 0.5])
+    tri = np.array([[0, 0, 0], [s, 0, 0], [s / 2, s * math.sqrt(3) / 2, 0]], float) + c
+    m = np.full(3, m0)
+    acc, _, _ = oracle.kick_acc(tri, m, no_close(tri, 0 * tri, m, params), params)
+    cen = tri.mean(0)
+    for i in range(3):
+        u = (cen - tri[i]) / np.linalg.norm(cen - tri[i])
+        np.testing.assert_allclose(acc[i], math.sqrt(3) * m0 / s ** 2 * u, rtol=2e-15, atol=1e-20)
+    sq = np.array([[0, 0, 0], [s, 0, 0], [s, s, 0], [0, s, 0]], float) + c
+    m = np.full(4, m0)
+    acc, _, _ = oracle.kick_acc(sq, m, no_close(sq, 0 * sq, m, params), params)
+    cen = sq.mean(0)
+    for i in range(4):
+        u = (cen - sq[i]) / np.linalg.norm(cen - sq[i])
+        np.testing.assert_allclose(acc[i], (math.sqrt(2) + 0.5) * m0 / s ** 2 * u, rtol=2e-15, atol=1e-20)
+
+
+def test_far_field_equals_textbook_newton(params):
+    d = diskgen.workload("disk2048", n=256)
+    thr = no_close(d["x"], d["v"], d["m"], params)
+    acc, ce, l1 = oracle.kick_acc(d["x"], d["m"], thr, params)
+    ref = newtonian(d["x"], d["m"])
+    err = np.abs(acc - ref).max(1) / l1
+    assert err.max() < 1e-14
+    assert np.all(ce == 0)
+
+
+# ------------------------------------------------------------------ kick with changeover
+def _cluster(params, seed=3):
+    """Five bodies with separations spread over [0, rc]: every pair in the changeover zone."""
+    rng = np.random.default_rng(seed)
+    x = np.array([1.0, 0.0, 0.0]) + 0.02 * rng.standard_normal((5, 3))
+    v = np.array([0.0, 1.0, 0.0]) + 0.05 * rng.standard_normal((5, 3))
+    m = rng.uniform(1e-4, 1e-3, 5)
+    return x, v, m
+
+
+def test_kick_is_gradient_of_changeover_potential(params):
+    """m_i a_i = -dU_B/dx_i with U_B = -sum G m_i m_j K/r (eq. Hb), by central differences of the
+    oracle's K-weighted energy E' minus the star term."""
+    x, v, m = _cluster(params)
+    thr = oracle.thresholds(x, v, m, params)
+    rc = thr[0]
+    acc, ce, _ = oracle.kick_acc(x, m, thr, params)
+    r = np.linalg.norm(x[:, None] - x[None], axis=-1)
+    rcij = np.maximum(rc[:, None], rc[None])
+    iu = np.triu_indices(5, 1)
+    y = (r[iu] - 0.1 * rcij[iu]) / (0.9 * rcij[iu])
+    assert np.any((y > 0) & (y < 1)), "fixture must exercise the changeover"
+    h = 1e-7
+    for i in range(5):
+        for c in range(3):
+            xp = x.copy(); xp[i, c] += h
+            xn = x.copy(); xn[i, c] -= h
+            Ep = oracle.energy(xp, v, m, params, thr)["Eprime"]
+            En = oracle.energy(xn, v, m, params, thr)["Eprime"]
+            dE = (Ep - En) / (2 * h)
+            star = params["G"] * params["m0"] * m[i] * x[i, c] / np.linalg.norm(x[i]) ** 3
+            force = -(dE - star)
+            assert abs(force - m[i] * acc[i, c]) < 1e-6 * abs(m[i] * np.abs(acc[i]).max())
+
+
+def test_split_sums_to_newton(params):
+    """a^B + a^CE equals the plain Newtonian pull."""
+    x, v, m = _cluster(params)
+    thr = oracle.thresholds(x, v, m, params)
+    acc, ce, l1 = oracle.kick_acc(x, m, thr, params)
+    ref = newtonian(x, m)
+    assert np.abs(acc + ce - ref).max() <= 1e-14 * np.abs(ref).max()
+    assert np.abs(ce).max() > 0
+
+
+def test_newton_third_law_and_permutation(params):
+    d = diskgen.workload("disk2048", n=512)
+    thr = oracle.thresholds(d["x"], d["v"], d["m"], params)
+    acc, ce, l1 = oracle.kick_acc(d["x"], d["m"], thr, params)
+    mom = (d["m"][:, None] * acc).sum(0)
+    assert np.abs(mom).max() <= 1e-14 * (d["m"][:, None] * np.abs(acc)).sum()
+    perm = np.random.default_rng(0).permutation(512)
+    thr_p = tuple(t[perm] for t in thr)
+    acc_p, _, _ = oracle.kick_acc(d["x"][perm], d["m"][perm], thr_p, params)
+    err = np.abs(acc_p - acc[perm]).max(1) / l1[perm]
+    assert err.max() < 1e-15
+
+
+def test_f64_within_bound_of_quad(params):
+    d = diskgen.workload("disk2048", n=512)
+    thr = oracle.thresholds(d["x"], d["v"], d["m"], params)
+    acc, _, l1 = oracle.kick_acc(d["x"], d["m"], thr, params)
+    aq = oracle.kick_acc(d["x"], d["m"], thr, params, "quad")
+    al = oracle.kick_acc(d["x"], d["m"], thr, params, "ld")
+    assert (np.abs(acc - aq).max(1) / l1).max() < 1e-15
+    assert (np.abs(al - aq).max(1) / l1).max() < 2.3e-16   # both rounded once to binary64
+
+
+# ------------------------------------------------------------------ critical radius (eq. rcrit)
+def test_rcrit_definition(params):
+    d = diskgen.workload("disk2048", n=64)
+    rc, H, V = oracle.thresholds(d["x"], d["v"], d["m"], params)
+    r = np.linalg.norm(d["x"], axis=1)
+    rhill = r * np.cbrt(d["m"] / (3 * params["m0"]))
+    vel = np.linalg.norm(d["v"], axis=1)
+    ref = np.maximum(3 * rhill, 0.4 * params["dt"] * vel)
+    np.testing.assert_allclose(rc, ref, rtol=1e-15)
+    np.testing.assert_allclose(H, (3 * rhill) ** 6, rtol=1e-14)
+    np.testing.assert_allclose(V, (0.4 * params["dt"] * vel) ** 2, rtol=1e-15)
+
+
+# ------------------------------------------------------------------ encounter list
+def test_encounters_match_real_arithmetic_definition(params):
+    d = diskgen.workload("disk2048")
+    thr = oracle.thresholds(d["x"], d["v"], d["m"], params)
+    pairs = oracle.encounters(d["x"], thr)
+    x = d["x"]
+    r = np.sqrt(((x[:, None] - x[None]) ** 2).sum(-1))
+    rcij = np.maximum(thr[0][:, None], thr[0][None])
+    iu = np.triu_indices(len(x), 1)
+    ratio = r[iu] / rcij[iu]
+    assert np.all(np.abs(ratio - 1) > 1e-9), "no pair sits on the threshold"
+    ref = np.stack([iu[0][ratio < 1], iu[1][ratio < 1]], 1)
+    assert len(pairs) > 50
+    np.testing.assert_array_equal(pairs, ref)
+
+
+def test_encounters_hand_placed(params):
+    """Pairs at rc (1 +- 1e-9): inside flagged, outside not; m = 0 leaves only the velocity term."""
+    base = np.array([1.0, 0.0, 0.0])
+    vel = np.array([0.0, 1.0, 0.0])
+    pts, vs = [], []
+    for k in range(4):
+        pts.append(base + np.array([0, 0, 10.0 * k]))
+        vs.append(vel)
+    x = np.array(pts)
+    v = np.array(vs)
+    m = np.zeros(4)
+    rc, H, V = oracle.thresholds(x, v, m, params)
+    assert np.all(H == 0)
+    rcv = 0.4 * params["dt"]
+    np.testing.assert_allclose(rc, rcv, rtol=1e-15)
+    # partner bodies along y at distances rc(1-1e-9) and rc(1+1e-9)
+    x2 = np.concatenate([x, x + np.array([[0, rcv * (1 - 1e-9), 0]] * 2 + [[0, rcv * (1 + 1e-9), 0]] * 2)])
+    v2 = np.concatenate([v, v])
+    m2 = np.zeros(8)
+    thr2 = oracle.thresholds(x2, v2, m2, params)
+    pairs = oracle.encounters(x2, thr2)
+    np.testing.assert_array_equal(pairs, np.array([[0, 4], [1, 5]]))
+
+
+# ------------------------------------------------------------------ jump (eq. Hc)
+def test_jump_hand_values(params):
+    x = np.array([[1.0, 2.0, 3.0], [-1.0, 0.5, 0.0]])
+    v = np.array([[0.1, 0.0, -0.2], [0.3, 0.4, 0.0]])
+    m = np.array([0.5, 0.25])
+    h = 0.125
+    Ptot = np.array([0.5 * 0.1 + 0.25 * 0.3, 0.25 * 0.4, 0.5 * -0.2])
+    xo = oracle.jump(x, v, m, P(m0=2.0), h)
+    np.testing.assert_allclose(xo, x + h * Ptot / 2.0, rtol=0, atol=1e-16)
+
+
+# ------------------------------------------------------------------ Kepler drift (eq. Ha)
+def _orbit_state(a, e, inc, node, argp, M, mu):
+    x, v = diskgen.elements_to_cartesian(np.atleast_1d(a), np.atleast_1d(e), np.atleast_1d(inc),
+                                         np.atleast_1d(node), np.atleast_1d(argp), np.atleast_1d(M),
+                                         np.atleast_1d(mu))
+    return x, v
+
+
+def test_drift_circular_rotation(params):
+    r, mu = 1.3, params["G"] * params["m0"]
+    n = math.sqrt(mu / r ** 3)
+    x = np.array([[r, 0.0, 0.0]])
+    v = np.array([[0.0, r * n, 0.0]])
+    t = 0.731
+    xo, vo, st = oracle.drift(x, v, params, t)
+    ref = r * np.array([math.cos(n * t), math.sin(n * t), 0.0])
+    np.testing.assert_allclose(xo[0], ref, atol=2e-15)
+    np.testing.assert_allclose(vo[0], r * n * np.array([-math.sin(n * t), math.cos(n * t), 0.0]), atol=2e-15)
+    assert st[0] == 0
+
+
+@pytest.mark.parametrize("e", [0.0, 0.05, 0.3, 0.7, 0.95])
+def test_drift_matches_kepler_equation_from_elements(params, e):
+    mu = params["G"] * params["m0"]
+    a, inc, node, argp, M0 = 1.7, 0.3, 1.1, 2.2, 0.4
+    n = math.sqrt(mu / a ** 3)
+    x0, v0 = _orbit_state(a, e, inc, node, argp, M0, mu)
+    for t in (0.1032, -0.77, 3.0, 25.0):
+        xt, vt = _orbit_state(a, e, inc, node, argp, M0 + n * t, mu)
+        xo, vo, st = oracle.drift(x0, v0, params, t)
+        assert st[0] == 0
+        np.testing.assert_allclose(xo, xt, rtol=0, atol=2e-13 * a / (1 - e))
+        np.testing.assert_allclose(vo, vt, rtol=0, atol=2e-13 * math.sqrt(mu / a) / (1 - e))
+
+
+def test_drift_hyperbolic_and_invariants(params):
+    mu = params["G"] * params["m0"]
+    x = np.array([[0.8, 0.1, -0.05]])
+    v = np.array([[0.3, 1.9, 0.2]])           # v^2 > 2 mu / r: unbound
+    assert (v ** 2).sum() > 2 * mu / np.linalg.norm(x)
+
+    def inv(x, v):
+        r = np.linalg.norm(x)
+        L = np.cross(x, v)
+        E = 0.5 * (v * v).sum() - mu / r
+        A = np.cross(v, L) - mu * x / r       # Laplace-Runge-Lenz
+        return E, L, A
+
+    E0, L0, A0 = inv(x[0], v[0])
+    for t in (0.05, 0.5, 3.0, -0.4):
+        xo, vo, st = oracle.drift(x, v, params, t)
+        assert st[0] == 0
+        E1, L1, A1 = inv(xo[0], vo[0])
+        assert abs(E1 - E0) < 1e-14 * abs(E0) + 1e-15
+        np.testing.assert_allclose(L1, L0, atol=1e-14)
+        np.testing.assert_allclose(A1, A0, atol=1e-13)
+        xb, vb, _ = oracle.drift(xo, vo, params, -t)
+        np.testing.assert_allclose(xb, x, atol=1e-13)
+        np.testing.assert_allclose(vb, v, atol=1e-13)
+
+
+def test_drift_one_period_and_quad(params):
+    mu = params["G"] * params["m0"]
+    d = diskgen.workload("disk2048", n=64)
+    xo, vo, st = oracle.drift(d["x"], d["v"], params, 0.1032)
+    xq, vq, stq = oracle.drift(d["x"], d["v"], params, 0.1032, quad=True)
+    assert stq == 0 and np.all(st == 0)
+    assert np.abs(xo - xq).max() < 4e-16 * 4 and np.abs(vo - vq).max() < 4e-16 * 2
+    x, v = d["x"][:1], d["v"][:1]
+    r = np.linalg.norm(x); a = 1 / (2 / r - (v ** 2).sum() / mu)
+    T = 2 * math.pi * math.sqrt(a ** 3 / mu)
+    xp, vp, _ = oracle.drift(x, v, params, T)
+    np.testing.assert_allclose(xp, x, atol=1e-13)
+    np.testing.assert_allclose(vp, v, atol=1e-13)
+
+
+# ------------------------------------------------------------------ full step
+def test_step_massless_is_pure_kepler(params):
+    """All masses zero: kicks and jumps vanish and the step is the exact Kepler flow."""
+    mu = params["G"] * params["m0"]
+    a = np.array([0.6, 1.0, 2.5]); e = np.array([0.0, 0.1, 0.4]); inc = np.array([0.0, 0.2, 0.05])
+    node = np.array([0.3, 1.0, 2.0]); argp = np.array([0.1, 0.5, 4.0]); M0 = np.array([0.0, 1.0, 2.0])
+    x0, v0 = diskgen.elements_to_cartesian(a, e, inc, node, argp, M0, np.full(3, mu))
+    m = np.zeros(3)
+    k = 7
+    xo, vo, st = oracle.step(x0, v0, m, params, k)
+    n = np.sqrt(mu / a ** 3)
+    xt, vt = diskgen.elements_to_cartesian(a, e, inc, node, argp, M0 + n * k * params["dt"], np.full(3, mu))
+    np.testing.assert_allclose(xo, xt, atol=1e-13)
+    np.testing.assert_allclose(vo, vt, atol=1e-13)
+
+
+def test_step_conserves_angular_momentum_and_Eprime(params):
+    d = diskgen.workload("disk2048", n=256)
+    thr = oracle.thresholds(d["x"], d["v"], d["m"], params)
+    e0 = oracle.energy(d["x"], d["v"], d["m"], params, thr)
+    x, v, st = oracle.step(d["x"], d["v"], d["m"], params, 20, thr=thr)
+    e1 = oracle.energy(x, v, d["m"], params, thr)
+    assert np.abs(e1["L"] - e0["L"]).max() < 1e-13 * np.abs(e0["L"]).max()
+    assert abs(e1["Eprime"] - e0["Eprime"]) < 1e-9 * abs(e0["Eprime"])
+
+
+def test_step_energy_error_scales_as_dt_squared(params):
+    """Second-order splitting: the K-weighted energy error drops about 4x when dt halves."""
+    x, v, m = _cluster(params, seed=5)
+    x = x + np.array([0.0, 0.0, 0.0]); m = m * 0.1
+    thr = oracle.thresholds(x, v, m, params)
+    e0 = oracle.energy(x, v, m, params, thr)["Eprime"]
+    errs = []
+    for div in (1, 2):
+        p = P(dt=params["dt"] / div)
+        xs, vs = x.copy(), v.copy()
+        worst = 0.0
+        for _ in range(8 * div):
+            xs, vs, _ = oracle.step(xs, vs, m, p, 1, thr=thr)
+            worst = max(worst, abs(oracle.energy(xs, vs, m, p, thr)["Eprime"] - e0))
+        errs.append(worst)
+    ratio = errs[0] / errs[1]
+    assert 3.0 < ratio < 5.5, (errs, ratio)
+
+
+def test_step_time_reversible(params):
+    d = diskgen.workload("disk2048", n=128)
+    thr = oracle.thresholds(d["x"], d["v"], d["m"], params)
+    x, v, _ = oracle.step(d["x"], d["v"], d["m"], params, 5, thr=thr)
+    xb, vb, _ = oracle.step(x, v, d["m"], P(dt=-params["dt"]), 5, thr=thr)
+    np.testing.assert_allclose(xb, d["x"], atol=2e-14)
+    np.testing.assert_allclose(vb, d["v"], atol=2e-14)
+
+
+# ------------------------------------------------------------------ derivatives (gradient reference)
+def test_jvp_matches_central_differences(params):
+    d = diskgen.workload("disk2048", n=24)
+    x, v, m = d["x"], d["v"], d["m"]
+    rng = np.random.default_rng(1)
+    dx = rng.standard_normal(x.shape); dv = rng.standard_normal(v.shape); dm = rng.standard_normal(m.shape) * m
+    thr = oracle.thresholds(x, v, m, params)
+    xo, vo, jx, jv, st = oracle.step_jvp(x, v, m, params, 6, dx, dv, dm)
+    eps = 1e-6
+    xp, vp, _ = oracle.step(x + eps * dx, v + eps * dv, m + eps * dm, params, 6, thr=thr)
+    xn, vn, _ = oracle.step(x - eps * dx, v - eps * dv, m - eps * dm, params, 6, thr=thr)
+    np.testing.assert_allclose(jx, (xp - xn) / (2 * eps), rtol=0, atol=1e-7 * np.abs(jx).max())
+    np.testing.assert_allclose(jv, (vp - vn) / (2 * eps), rtol=0, atol=1e-7 * np.abs(jv).max())
+    x1, v1, _ = oracle.step(x, v, m, params, 6, thr=thr)
+    np.testing.assert_allclose(xo, x1, rtol=0, atol=1e-13)   # dual path rounds differently
+
+
+def test_step_is_symplectic(params):
+    """The step's Jacobian in canonical (x, p = m v) coordinates preserves the symplectic form."""
+    x, v, m = _cluster(params, seed=7)
+    x, v, m = x[:3], v[:3], m[:3]
+    n = 3
+    J = np.zeros((6 * n, 6 * n))
+    for k in range(6 * n):
+        dx = np.zeros((n, 3)); dv = np.zeros((n, 3))
+        if k < 3 * n:
+            dx.reshape(-1)[k] = 1.0
+        else:
+            dv.reshape(-1)[k - 3 * n] = 1.0 / np.repeat(m, 3)[k - 3 * n]   # unit change of p
+        _, _, jx, jv, _ = oracle.step_jvp(x, v, m, params, 3, dx, dv, None)
+        J[:3 * n, k] = jx.reshape(-1)
+        J[3 * n:, k] = (jv * m[:, None]).reshape(-1)
+    Om = np.block([[np.zeros((3 * n, 3 * n)), np.eye(3 * n)], [-np.eye(3 * n), np.zeros((3 * n, 3 * n))]])
+    S = J.T @ Om @ J
+    assert np.abs(S - Om).max() < 1e-9 * np.abs(J).max() ** 2
