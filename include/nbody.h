@@ -1,0 +1,142 @@
+/*
+ * nbody.h - C interface of the MI355X library for the hot path of the hybrid symplectic
+ * planetesimal integrator (Grimm & Stadel, "Terrestrial planet formation in the era of GPU
+ * computing", section "The hybrid symplectic integrator").
+ *
+ * The method splits the Hamiltonian in democratic heliocentric coordinates (heliocentric
+ * positions r_i, barycentric velocities v_i) as H = H_A + H_B + H_C (equations Ha, Hb, Hc):
+ *   H_A  Kepler motion of every body about the central mass m0 (the "drift"),
+ *   H_B  the all-pairs mutual gravity weighted by a smooth changeover K(r_ij) (the "kick"),
+ *   H_C  the total-momentum term (the "jump"),
+ * and flags pairs closer than the critical radius of equation rcrit as close encounters.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: NBODY_OK (0) or a negative NBODY_E_* code; the message of the last failure
+ *     is available from nbody_last_error(ctx).
+ *   - Every array argument is a DEVICE pointer unless stated otherwise, caller-owned, aligned to
+ *     32 bytes. The library never frees caller memory; the context owns a private workspace
+ *     that grows on demand (the only allocations the library makes).
+ *   - Body arrays are row-major [n][4] binary64:
+ *        xm  = {x, y, z, m}   heliocentric position and mass,
+ *        v   = {vx, vy, vz, pad}  barycentric velocity (pad is ignored and preserved),
+ *        thr = {rc, H, V, T}  per-body critical radius and encounter thresholds (see
+ *                              nbody_rcrit).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and runs
+ *     asynchronously. Calls on one context must not overlap: they share its workspace.
+ *   - Units are the caller's; G is a parameter. Arithmetic is IEEE binary64 with
+ *     round-to-nearest-even unless the split-precision kick is selected.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBODY_OK 0
+#define NBODY_E_INVAL (-1)   /* bad argument: n <= 0, NULL where required, misalignment, bad params */
+#define NBODY_E_HIP (-2)     /* HIP runtime or launch failure */
+#define NBODY_E_NOMEM (-3)   /* workspace allocation failed */
+
+#define NBODY_PREC_F64 0     /* the kick entirely in binary64 */
+#define NBODY_PREC_SPLIT 1   /* offsets and r^2 in binary64, r^-3 in binary32, sums in binary64 */
+
+typedef struct nbody_params {
+  double G;    /* gravitational constant */
+  double m0;   /* central mass */
+  double dt;   /* full step used by nbody_step and by the velocity term of rcrit */
+  double n1;   /* Hill-radius factor of eq. rcrit (3) */
+  double n2;   /* velocity factor of eq. rcrit (0.4) */
+  double f_in; /* changeover: K = 0 below f_in * rc (0.1) */
+  int32_t precision; /* NBODY_PREC_F64 or NBODY_PREC_SPLIT, used by nbody_kick / nbody_step */
+  int32_t reserved;
+} nbody_params;
+
+typedef struct nbody_ctx nbody_ctx;
+
+/* Context: parameters, workspace, autotuning table, last error. `out` is a host pointer. */
+int nbody_create(nbody_ctx **out, const nbody_params *p);
+int nbody_destroy(nbody_ctx *ctx);
+int nbody_set_params(nbody_ctx *ctx, const nbody_params *p);
+const char *nbody_last_error(const nbody_ctx *ctx);
+const char *nbody_version(void);
+
+/*
+ * Critical radius and encounter thresholds (eq. rcrit), one row per body:
+ *   rc_i = max(n1 R_Hill,i, n2 dt |v_i|),  R_Hill,i = |x_i| (m_i / (3 m0))^(1/3),
+ *   H_i  = cH * ((r2_i*r2_i)*r2_i) * (mu_i*mu_i),  cH = ((n1*n1*n1)*(n1*n1*n1))/9, mu_i = m_i/m0,
+ *          r2_i = fma(z,z,fma(y,y,x*x))            [ = (n1 R_Hill,i)^6 ],
+ *   V_i  = cV * fma(vz,vz,fma(vy,vy,vx*vx)),  cV = (n2*dt)*(n2*dt)   [ = (n2 dt |v_i|)^2 ],
+ *   T_i  = an upper bound of every r^2 that the thresholds of body i can flag (internal).
+ * thr [n][4] is written. The step functions hold thr fixed for a whole call.
+ */
+int nbody_rcrit(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, double *thr,
+                void *stream);
+
+/*
+ * H_B kick (eq. Hb): the gradient of -sum_{i<j} G m_i m_j K(r_ij)/r_ij with rc held fixed,
+ *   a_i = G sum_{j != i} m_j w_ij (x_j - x_i),
+ *   w = 1/r^3 for pairs that are not close, w = K/r^3 - K'(r)/r^2 for close pairs, with
+ *   K(y) = y^2/(2y^2-2y+1), y = clamp((r - f_in rc_ij)/((1-f_in) rc_ij), 0, 1),
+ *   rc_ij = max(rc_i, rc_j), and "close" the exact predicate of nbody_encounters.
+ * v (in/out, may be NULL): v_i += h a_i.  acc [n][4] (may be NULL): a_i.  acc_ce [n][4] (may be
+ * NULL): the complementary close-encounter part G sum_close m_j (1/r^3 - w) (x_j - x_i), so that
+ * acc + acc_ce is the plain Newtonian pull. Precision follows params.precision.
+ */
+int nbody_kick(nbody_ctx *ctx, int64_t n, const double *xm, const double *thr, double *v, double h,
+               double *acc, double *acc_ce, void *stream);
+
+/*
+ * Close-encounter pairs (the pairs inside the critical radius, eq. rcrit): i < j with
+ *   (r2*r2)*r2 < max(H_i, H_j)  or  r2 < max(V_i, V_j),
+ *   r2 = fma(dz,dz,fma(dy,dy,dx*dx)), d = x_j - x_i,
+ * evaluated exactly in binary64 (in real arithmetic: r_ij < max(rc_i, rc_j)).
+ * pairs [cap][2] int32 receives the first min(count, cap) pairs in ascending (i, j) order;
+ * *count (device int64) receives the true number of pairs, so count > cap signals truncation.
+ */
+int nbody_encounters(nbody_ctx *ctx, int64_t n, const double *xm, const double *thr,
+                     int32_t *pairs, int64_t cap, int64_t *count, void *stream);
+
+/* H_C jump (eq. Hc): x_i += h * (P / m0) with P = sum_j m_j v_j. xm in/out, v read. */
+int nbody_jump(nbody_ctx *ctx, int64_t n, double *xm, const double *v, double h, void *stream);
+
+/*
+ * H_A drift (eq. Ha, first line): every body moves for time h along its Kepler orbit about
+ * mu = G m0 (universal-variable formulation, binary64). xm (positions) and v in/out.
+ * status [n] uint32 (may be NULL): 0, or 1 if the anomaly iteration did not converge.
+ */
+int nbody_drift(nbody_ctx *ctx, int64_t n, double *xm, double *v, double h, uint32_t *status,
+                void *stream);
+
+/*
+ * nsteps steps B(dt/2) C(dt/2) A(dt) C(dt/2) B(dt/2). thr: NULL = computed from the state at
+ * call start into the context; otherwise used as given. thr is held fixed for the call, so a
+ * call is exactly the composition of its steps and consecutive kicks at the same positions are
+ * evaluated once (v += h a applied twice). If pairs is not NULL the encounter list at the final
+ * positions is written as in nbody_encounters.
+ */
+int nbody_step(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr, int32_t nsteps,
+               int32_t *pairs, int64_t cap, int64_t *count, void *stream);
+
+/*
+ * Diagnostics (device out[8]): E (full Newtonian energy in democratic heliocentric form),
+ * E' (the pair term weighted by K: the quantity the hot-path step conserves), L[3], P[3].
+ */
+int nbody_energy(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, const double *thr,
+                 double *out, void *stream);
+
+/*
+ * Measurement helper: launches the pair kernel of nbody_kick (no velocity update, no outputs
+ * beyond the context's partial sums) `reps` times between two HIP events recorded on `stream`,
+ * waits for the second event and stores the mean duration of one launch in milliseconds in
+ * *avg_ms (a HOST pointer). Used to state the kernel's achieved fraction of peak.
+ */
+int nbody_bench_pairs(nbody_ctx *ctx, int64_t n, const double *xm, const double *thr, int32_t reps,
+                      double *avg_ms, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

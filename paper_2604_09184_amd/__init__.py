@@ -1,0 +1,223 @@
+"""Python binding of libnbody.so, the MI355X library for the hot path of the hybrid symplectic
+planetesimal integrator (changeover-weighted all-pairs kick, close-encounter detection, Kepler
+drift and momentum jump in democratic heliocentric coordinates).
+
+Argument marshalling only: every step runs in the library's HIP kernels. Tensors are float64
+CUDA (HIP) tensors of shape (n, 4), contiguous: xm = [x, y, z, m], v = [vx, vy, vz, pad],
+thr = [rc, H, V, T]. Work goes to torch's current stream. The binding raises if the library is
+not built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnbody.so")
+
+PREC_F64 = 0
+PREC_SPLIT = 1
+
+
+class NBodyError(RuntimeError):
+    pass
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("m0", ctypes.c_double), ("dt", ctypes.c_double),
+                ("n1", ctypes.c_double), ("n2", ctypes.c_double), ("f_in", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+@dataclasses.dataclass
+class Params:
+    G: float = 1.0
+    m0: float = 1.0
+    dt: float = 6.0 * 0.01720209895
+    n1: float = 3.0
+    n2: float = 0.4
+    f_in: float = 0.1
+    precision: int = PREC_F64
+
+    def c(self):
+        return _Params(self.G, self.m0, self.dt, self.n1, self.n2, self.f_in, self.precision, 0)
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_I32 = ctypes.c_int32
+
+# name -> argument types after the context pointer
+EXPORTS = {
+    "nbody_rcrit": [_I64, _P, _P, _P, _P],
+    "nbody_kick": [_I64, _P, _P, _P, _D, _P, _P, _P],
+    "nbody_encounters": [_I64, _P, _P, _P, _I64, _P, _P],
+    "nbody_jump": [_I64, _P, _P, _D, _P],
+    "nbody_drift": [_I64, _P, _P, _D, _P, _P],
+    "nbody_step": [_I64, _P, _P, _P, _I32, _P, _I64, _P, _P],
+    "nbody_energy": [_I64, _P, _P, _P, _P, _P],
+    "nbody_bench_pairs": [_I64, _P, _P, _I32, _P, _P],
+}
+OTHER_EXPORTS = ["nbody_create", "nbody_destroy", "nbody_set_params", "nbody_last_error",
+                 "nbody_version"]
+
+_lib = None
+
+
+def lib():
+    """Loads libnbody.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise NBodyError(f"{LIB_PATH} is missing: build it with paper_2604_09184_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    L.nbody_create.restype = ctypes.c_int
+    L.nbody_create.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(_Params)]
+    L.nbody_destroy.argtypes = [_P]
+    L.nbody_set_params.argtypes = [_P, ctypes.POINTER(_Params)]
+    L.nbody_last_error.restype = ctypes.c_char_p
+    L.nbody_last_error.argtypes = [_P]
+    L.nbody_version.restype = ctypes.c_char_p
+    for name, args in EXPORTS.items():
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [_P] + args
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _body(t, name):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.shape[1] == 4
+            and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape (n, 4)")
+    return t
+
+
+class Context:
+    """Owns an nbody_ctx (parameters, workspace). Calls on one context must not overlap."""
+
+    def __init__(self, params: Params | None = None):
+        self.params = params or Params()
+        self._h = _P()
+        rc = lib().nbody_create(ctypes.byref(self._h), ctypes.byref(self.params.c()))
+        if rc != 0:
+            raise NBodyError(f"nbody_create failed ({rc})")
+
+    def close(self):
+        if self._h:
+            lib().nbody_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        self.params = params
+        self._check(lib().nbody_set_params(self._h, ctypes.byref(params.c())), "nbody_set_params")
+
+    def _check(self, rc, name):
+        if rc != 0:
+            msg = lib().nbody_last_error(self._h)
+            raise NBodyError(f"{name} failed ({rc}): {msg.decode() if msg else ''}")
+
+    # ------------------------------------------------------------ entry points
+    def rcrit(self, xm, v, thr=None):
+        _body(xm, "xm"); _body(v, "v")
+        if thr is None:
+            thr = torch.empty_like(xm)
+        _body(thr, "thr")
+        self._check(lib().nbody_rcrit(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr), _stream()),
+                    "nbody_rcrit")
+        return thr
+
+    def kick(self, xm, thr, v=None, h=0.0, acc=None, acc_ce=None):
+        for t, nm in ((xm, "xm"), (thr, "thr"), (v, "v"), (acc, "acc"), (acc_ce, "acc_ce")):
+            _body(t, nm)
+        self._check(lib().nbody_kick(self._h, xm.shape[0], _ptr(xm), _ptr(thr), _ptr(v), float(h),
+                                     _ptr(acc), _ptr(acc_ce), _stream()), "nbody_kick")
+        return acc
+
+    def accelerations(self, xm, thr, with_ce=False):
+        acc = torch.empty_like(xm)
+        ce = torch.empty_like(xm) if with_ce else None
+        self.kick(xm, thr, None, 0.0, acc, ce)
+        return (acc, ce) if with_ce else acc
+
+    def encounters(self, xm, thr, cap=None):
+        """Returns (pairs (k, 2) int32 on the device, true count)."""
+        _body(xm, "xm"); _body(thr, "thr")
+        n = xm.shape[0]
+        count = torch.zeros(1, dtype=torch.int64, device=xm.device)
+        if cap is None:
+            self._check(lib().nbody_encounters(self._h, n, _ptr(xm), _ptr(thr), None, 0, _ptr(count),
+                                               _stream()), "nbody_encounters")
+            cap = int(count.item())
+        pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=xm.device)
+        self._check(lib().nbody_encounters(self._h, n, _ptr(xm), _ptr(thr), _ptr(pairs), cap,
+                                           _ptr(count), _stream()), "nbody_encounters")
+        c = int(count.item())
+        return pairs[:min(c, cap)], c
+
+    def jump(self, xm, v, h):
+        _body(xm, "xm"); _body(v, "v")
+        self._check(lib().nbody_jump(self._h, xm.shape[0], _ptr(xm), _ptr(v), float(h), _stream()),
+                    "nbody_jump")
+
+    def drift(self, xm, v, h, status=None):
+        _body(xm, "xm"); _body(v, "v")
+        self._check(lib().nbody_drift(self._h, xm.shape[0], _ptr(xm), _ptr(v), float(h), _ptr(status),
+                                      _stream()), "nbody_drift")
+        return status
+
+    def step(self, xm, v, nsteps, thr=None, pairs_cap=None):
+        """nsteps steps in place. With pairs_cap, also returns the final encounter list."""
+        _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
+        n = xm.shape[0]
+        if pairs_cap is None:
+            self._check(lib().nbody_step(self._h, n, _ptr(xm), _ptr(v), _ptr(thr), int(nsteps), None, 0,
+                                         None, _stream()), "nbody_step")
+            return None
+        count = torch.zeros(1, dtype=torch.int64, device=xm.device)
+        pairs = torch.empty((max(pairs_cap, 1), 2), dtype=torch.int32, device=xm.device)
+        self._check(lib().nbody_step(self._h, n, _ptr(xm), _ptr(v), _ptr(thr), int(nsteps), _ptr(pairs),
+                                     pairs_cap, _ptr(count), _stream()), "nbody_step")
+        c = int(count.item())
+        return pairs[:min(c, pairs_cap)], c
+
+    def energy(self, xm, v, thr):
+        out = torch.empty(8, dtype=torch.float64, device=xm.device)
+        self._check(lib().nbody_energy(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr), _ptr(out),
+                                       _stream()), "nbody_energy")
+        o = out.cpu().numpy()
+        return {"E": o[0], "Eprime": o[1], "L": o[2:5].copy(), "P": o[5:8].copy()}
+
+
+    def bench_pairs(self, xm, thr, reps=10):
+        """Mean duration (ms) of one pair-kernel launch, timed with HIP events on the stream."""
+        _body(xm, "xm"); _body(thr, "thr")
+        ms = ctypes.c_double()
+        self._check(lib().nbody_bench_pairs(self._h, xm.shape[0], _ptr(xm), _ptr(thr), int(reps),
+                                            ctypes.byref(ms), _stream()), "nbody_bench_pairs")
+        return ms.value
+
+
+def version():
+    return lib().nbody_version().decode()

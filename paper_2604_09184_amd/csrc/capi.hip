@@ -1,0 +1,351 @@
+// C-ABI of the library (declared in include/nbody.h): argument validation, context workspace,
+// launch planning and the orchestration of kick / jump / drift / encounter kernels on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/nbody.h"
+#include "internal.hpp"
+
+using namespace nbk;
+
+namespace {
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
+             B_COUNT_SCRATCH, B_NUM };
+
+}  // namespace
+
+struct nbody_ctx {
+  nbody_params p{};
+  std::string err;
+  Buf buf[B_NUM];
+  int R = 128;              // partner slots per (row, j-chunk) in the emission buffer
+  int target_waves = 8192;  // pair-kernel waves to aim for (8 per SIMD on 256 CUs)
+};
+
+namespace {
+
+int fail(nbody_ctx *c, int code, const char *fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(nbody_ctx *c, hipError_t e, const char *where) {
+  return fail(c, NBODY_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr, where)                         \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(c, e_, where); \
+  } while (0)
+
+void *ensure(nbody_ctx *c, BufId id, size_t bytes) {
+  Buf &b = c->buf[id];
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    b.p = nullptr;
+    return nullptr;
+  }
+  b.bytes = bytes;
+  return b.p;
+}
+
+bool params_ok(const nbody_params *p) {
+  return p && p->m0 > 0 && p->n1 >= 0 && p->n2 >= 0 && p->f_in >= 0 && p->f_in < 1 &&
+         (p->precision == NBODY_PREC_F64 || p->precision == NBODY_PREC_SPLIT) && p->G == p->G &&
+         p->dt == p->dt;
+}
+
+// Device pointer, aligned to 32 bytes.
+int check_dev(nbody_ctx *c, const void *ptr, const char *name, bool required) {
+  if (!ptr) return required ? fail(c, NBODY_E_INVAL, "%s is NULL", name) : NBODY_OK;
+  if ((uintptr_t)ptr & 31u) return fail(c, NBODY_E_INVAL, "%s is not 32-byte aligned", name);
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, NBODY_E_INVAL, "%s is not a HIP allocation", name);
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return fail(c, NBODY_E_INVAL, "%s is not device memory", name);
+  return NBODY_OK;
+}
+
+int check_n(nbody_ctx *c, int64_t n) {
+  if (!c) return NBODY_E_INVAL;
+  if (n <= 0 || n > (int64_t)1 << 28) return fail(c, NBODY_E_INVAL, "n = %lld out of range", (long long)n);
+  return NBODY_OK;
+}
+
+#define TRY(expr)               \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != NBODY_OK) return r_; \
+  } while (0)
+
+// j-chunking: enough waves to fill the chip, chunks of at least 128 bodies.
+void plan(const nbody_ctx *c, int n, int &S, int &chunk) {
+  const int iwaves = (n + 63) / 64;
+  int s = (c->target_waves + iwaves - 1) / iwaves;
+  const int smax = (n + 127) / 128;
+  if (s > smax) s = smax;
+  if (s < 1) s = 1;
+  chunk = (n + s - 1) / s;
+  S = (n + chunk - 1) / chunk;
+}
+
+int make_kick_args(nbody_ctx *c, int n, const double *xm, const double *thr, bool need_force,
+                   bool need_ce, bool need_emit, KickArgs &a) {
+  plan(c, n, a.nchunk, a.chunk);
+  a.xm = reinterpret_cast<const double4 *>(xm);
+  a.thr = reinterpret_cast<const double4 *>(thr);
+  a.n = n;
+  a.f_in = c->p.f_in;
+  a.R = c->R;
+  const size_t sn = (size_t)a.nchunk * n;
+  a.part = need_force ? (double4 *)ensure(c, B_PART, sn * sizeof(double4)) : nullptr;
+  a.part_ce = need_ce ? (double4 *)ensure(c, B_PART_CE, sn * sizeof(double4)) : nullptr;
+  a.cnt = need_emit ? (int *)ensure(c, B_CNT, sn * sizeof(int)) : nullptr;
+  a.rowbuf = need_emit ? (int *)ensure(c, B_ROWBUF, sn * (size_t)a.R * sizeof(int)) : nullptr;
+  if ((need_force && !a.part) || (need_ce && !a.part_ce) || (need_emit && (!a.cnt || !a.rowbuf)))
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (n = %d, chunks = %d)", n, a.nchunk);
+  return NBODY_OK;
+}
+
+int emit_list(nbody_ctx *c, const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
+              hipStream_t st) {
+  const int nb = nblocks(a.n);
+  int64_t *rowtot = (int64_t *)ensure(c, B_ROWTOT, (size_t)a.n * sizeof(int64_t));
+  int64_t *bsum = (int64_t *)ensure(c, B_BSUM, (size_t)nb * sizeof(int64_t));
+  if (!rowtot || !bsum) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (emission)");
+  HIPCHK(c, launch_emit(a, pairs, cap, count, rowtot, bsum, st), "encounter emission");
+  return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950, binary64 vector ALU)"; }
+
+int nbody_create(nbody_ctx **out, const nbody_params *p) {
+  if (!out) return NBODY_E_INVAL;
+  *out = nullptr;
+  if (!params_ok(p)) return NBODY_E_INVAL;
+  nbody_ctx *c = new (std::nothrow) nbody_ctx();
+  if (!c) return NBODY_E_NOMEM;
+  c->p = *p;
+  *out = c;
+  return NBODY_OK;
+}
+
+int nbody_destroy(nbody_ctx *c) {
+  if (!c) return NBODY_E_INVAL;
+  (void)hipDeviceSynchronize();
+  for (auto &b : c->buf)
+    if (b.p) (void)hipFree(b.p);
+  delete c;
+  return NBODY_OK;
+}
+
+int nbody_set_params(nbody_ctx *c, const nbody_params *p) {
+  if (!c) return NBODY_E_INVAL;
+  if (!params_ok(p)) return fail(c, NBODY_E_INVAL, "invalid parameters");
+  c->p = *p;
+  return NBODY_OK;
+}
+
+const char *nbody_last_error(const nbody_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int nbody_rcrit(nbody_ctx *c, int64_t n, const double *xm, const double *v, double *thr,
+                void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, thr, "thr", true));
+  const nbody_params &p = c->p;
+  const double cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
+  const double t = p.n2 * p.dt;
+  const double cV = t * t;
+  HIPCHK(c, launch_rcrit((const double4 *)xm, (const double4 *)v, (double4 *)thr, (int)n, p.m0, cH, cV,
+                         p.n1, t, (hipStream_t)stream), "rcrit");
+  return NBODY_OK;
+}
+
+int nbody_kick(nbody_ctx *c, int64_t n, const double *xm, const double *thr, double *v, double h,
+               double *acc, double *acc_ce, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, thr, "thr", true));
+  TRY(check_dev(c, v, "v", false));
+  TRY(check_dev(c, acc, "acc", false));
+  TRY(check_dev(c, acc_ce, "acc_ce", false));
+  KickArgs a;
+  TRY(make_kick_args(c, (int)n, xm, thr, true, acc_ce != nullptr, false, a));
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(c, launch_pairs(a, true, false, acc_ce != nullptr, c->p.precision == NBODY_PREC_SPLIT, st),
+         "kick pairs");
+  HIPCHK(c, launch_finalize(a.part, a.part_ce, a.nchunk, (int)n, c->p.G, h, 1, a.xm, (double4 *)v,
+                            (double4 *)acc, (double4 *)acc_ce, nullptr, st), "kick finalize");
+  return NBODY_OK;
+}
+
+int nbody_encounters(nbody_ctx *c, int64_t n, const double *xm, const double *thr, int32_t *pairs,
+                     int64_t cap, int64_t *count, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, thr, "thr", true));
+  TRY(check_dev(c, count, "count", true));
+  if (cap < 0) return fail(c, NBODY_E_INVAL, "cap < 0");
+  if (cap > 0) TRY(check_dev(c, pairs, "pairs", true));
+  KickArgs a;
+  TRY(make_kick_args(c, (int)n, xm, thr, false, false, true, a));
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(c, launch_pairs(a, false, true, false, false, st), "encounter pairs");
+  return emit_list(c, a, pairs, cap, count, st);
+}
+
+int nbody_jump(nbody_ctx *c, int64_t n, double *xm, const double *v, double h, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  const int nb = nblocks(n);
+  double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
+  if (!mom) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(c, launch_momentum((const double4 *)xm, (const double4 *)v, (int)n, mom, st), "momentum");
+  HIPCHK(c, launch_jump((double4 *)xm, mom, nb, (int)n, h, c->p.m0, st), "jump");
+  return NBODY_OK;
+}
+
+int nbody_drift(nbody_ctx *c, int64_t n, double *xm, double *v, double h, uint32_t *status,
+                void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, status, "status", false));
+  HIPCHK(c, launch_drift((double4 *)xm, (double4 *)v, (int)n, h, c->p.G * c->p.m0, status,
+                         (hipStream_t)stream), "drift");
+  return NBODY_OK;
+}
+
+int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr, int32_t nsteps,
+               int32_t *pairs, int64_t cap, int64_t *count, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, thr, "thr", false));
+  if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
+  const bool emit = count != nullptr;
+  if (emit) {
+    TRY(check_dev(c, count, "count", true));
+    if (cap < 0) return fail(c, NBODY_E_INVAL, "cap < 0");
+    if (cap > 0) TRY(check_dev(c, pairs, "pairs", true));
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const nbody_params &p = c->p;
+  const int N = (int)n;
+  const int nb = nblocks(n);
+  if (!thr) {
+    double *t = (double *)ensure(c, B_THR, (size_t)n * sizeof(double4));
+    if (!t) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (thresholds)");
+    TRY(nbody_rcrit(c, n, xm, v, t, stream));
+    thr = t;
+  }
+  double4 *momA = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
+  double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nb * sizeof(double4));
+  if (!momA || !momB) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
+  KickArgs a;
+  TRY(make_kick_args(c, N, xm, thr, true, false, emit, a));
+  const bool split = p.precision == NBODY_PREC_SPLIT;
+  const double h = 0.5 * p.dt;
+  const double mu = p.G * p.m0;
+  double4 *X = (double4 *)xm;
+  double4 *Vv = (double4 *)v;
+  if (nsteps == 0) {
+    if (emit) {
+      HIPCHK(c, launch_pairs(a, false, true, false, false, st), "step pairs");
+      return emit_list(c, a, pairs, cap, count, st);
+    }
+    return NBODY_OK;
+  }
+  HIPCHK(c, launch_pairs(a, true, false, false, split, st), "step pairs");
+  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, X, Vv, nullptr, nullptr, momA, st),
+         "step finalize");
+  for (int s = 1; s <= nsteps; ++s) {
+    HIPCHK(c, launch_jump_drift(X, Vv, momA, nb, N, h, p.dt, p.m0, mu, nullptr, momB, st), "jump+drift");
+    HIPCHK(c, launch_jump(X, momB, nb, N, h, p.m0, st), "jump");
+    const bool last = s == nsteps;
+    HIPCHK(c, launch_pairs(a, true, last && emit, false, split, st), "step pairs");
+    HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, last ? 1 : 2, X, Vv, nullptr,
+                              nullptr, momA, st), "step finalize");
+  }
+  if (emit) return emit_list(c, a, pairs, cap, count, st);
+  return NBODY_OK;
+}
+
+int nbody_energy(nbody_ctx *c, int64_t n, const double *xm, const double *v, const double *thr,
+                 double *out, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, thr, "thr", true));
+  TRY(check_dev(c, out, "out", true));
+  const int nb = nblocks(n);
+  double4 *ep = (double4 *)ensure(c, B_EPARTS, (size_t)nb * 10 * sizeof(double));
+  if (!ep) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (energy)");
+  HIPCHK(c, launch_energy((const double4 *)xm, (const double4 *)v, (const double4 *)thr, (int)n, c->p.G,
+                          c->p.m0, c->p.f_in, ep, out, (hipStream_t)stream), "energy");
+  return NBODY_OK;
+}
+
+int nbody_bench_pairs(nbody_ctx *c, int64_t n, const double *xm, const double *thr, int32_t reps,
+                      double *avg_ms, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, thr, "thr", true));
+  if (reps <= 0 || !avg_ms) return fail(c, NBODY_E_INVAL, "reps <= 0 or avg_ms NULL");
+  KickArgs a;
+  TRY(make_kick_args(c, (int)n, xm, thr, true, false, false, a));
+  hipStream_t st = (hipStream_t)stream;
+  const bool split = c->p.precision == NBODY_PREC_SPLIT;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0), "event");
+  HIPCHK(c, hipEventCreate(&e1), "event");
+  hipError_t e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_pairs(a, true, false, false, split, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "bench pairs");
+  *avg_ms = (double)ms / reps;
+  return NBODY_OK;
+}
+
+}  // extern "C"

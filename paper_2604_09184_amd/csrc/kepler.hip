@@ -1,0 +1,165 @@
+// H_A drift (eq. Ha, Kepler part) and H_C jump (eq. Hc).
+//
+// The drift advances each body on its two-body orbit about mu = G m0 with the f and g functions
+// in universal variables (Stumpff functions c_k), solved with the Laguerre-Conway iteration; one
+// body per lane, binary64 throughout. The jump shifts every position by h * P / m0; P is reduced
+// deterministically from per-workgroup partial sums by every workgroup in the same order.
+#include "internal.hpp"
+
+namespace nbk {
+using namespace nbd;
+
+// Stumpff functions c0..c3 at z: argument quartered until |z| <= 0.1, series there, then the
+// quadrupling relations c0(4z) = 2c0^2 - 1, c1(4z) = c0 c1, c2(4z) = c1^2/2,
+// c3(4z) = (c2 + c0 c3)/4.
+__device__ __forceinline__ void stumpff(double z, double &c0, double &c1, double &c2, double &c3) {
+  int k = 0;
+  while (fabs(z) > 0.1 && k < 64) {
+    z *= 0.25;
+    ++k;
+  }
+  c2 = 0.5 - z * (1.0 / 24 - z * (1.0 / 720 - z * (1.0 / 40320 - z * (1.0 / 3628800 - z * (1.0 / 479001600)))));
+  c3 = 1.0 / 6 - z * (1.0 / 120 - z * (1.0 / 5040 - z * (1.0 / 362880 - z * (1.0 / 39916800 - z * (1.0 / 6227020800.0)))));
+  c1 = 1.0 - z * c3;
+  c0 = 1.0 - z * c2;
+  for (; k > 0; --k) {
+    c3 = (c2 + c0 * c3) * 0.25;
+    c2 = 0.5 * c1 * c1;
+    c1 = c0 * c1;
+    c0 = 2.0 * c0 * c0 - 1.0;
+  }
+}
+
+// Advance (x, v) by dt on the Kepler orbit about mu. Returns 0, or 1 if not converged.
+__device__ int kepler_advance(double &x, double &y, double &z, double &vx, double &vy, double &vz,
+                              double mu, double dt) {
+  const double r0 = sqrt(x * x + y * y + z * z);
+  const double v2 = vx * vx + vy * vy + vz * vz;
+  const double u = x * vx + y * vy + z * vz;
+  const double beta = 2.0 * mu / r0 - v2;
+  double s = dt / r0;
+  double c0, c1, c2, c3;
+  int status = 1;
+  for (int it = 0; it < 40; ++it) {
+    stumpff(beta * s * s, c0, c1, c2, c3);
+    const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
+    const double F = r0 * G1 + u * G2 + mu * G3 - dt;
+    const double Fp = r0 * c0 + u * G1 + mu * G2;
+    const double Fpp = (mu - beta * r0) * G1 + u * c0;
+    const double disc = fabs(16.0 * Fp * Fp - 20.0 * F * Fpp);
+    const double den = Fp + (Fp >= 0.0 ? 1.0 : -1.0) * sqrt(disc);
+    const double ds = -5.0 * F / den;
+    s += ds;
+    if (fabs(ds) <= 1e-15 * fabs(s)) {
+      status = 0;
+      break;
+    }
+  }
+  stumpff(beta * s * s, c0, c1, c2, c3);
+  const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
+  const double r = r0 * c0 + u * G1 + mu * G2;
+  const double f = 1.0 - mu * G2 / r0;
+  const double g = dt - mu * G3;
+  const double fd = -mu * G1 / (r0 * r);
+  const double gd = 1.0 - mu * G2 / r;
+  const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
+  const double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy, nvz = fd * z + gd * vz;
+  x = nx; y = ny; z = nz;
+  vx = nvx; vy = nvy; vz = nvz;
+  return status;
+}
+
+__global__ __launch_bounds__(kBlock) void k_momentum(const double4 *__restrict__ xm,
+                                                     const double4 *__restrict__ v, int n,
+                                                     double4 *__restrict__ mom) {
+  __shared__ double lds[3 * kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double P[3] = {0.0, 0.0, 0.0};
+  if (i < n) {
+    const double m = xm[i].w;
+    const double4 q = v[i];
+    P[0] = m * q.x; P[1] = m * q.y; P[2] = m * q.z;
+  }
+  block_sum<3>(P, lds);
+  if (threadIdx.x == 0) mom[blockIdx.x] = make_double4(P[0], P[1], P[2], 0.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_jump(double4 *__restrict__ xm,
+                                                 const double4 *__restrict__ mom, int nb, int n,
+                                                 double h, double m0) {
+  __shared__ double lds[3 * kBlock];
+  double P[3];
+  momentum_total(mom, nb, P, lds);
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double sx = h * (P[0] / m0), sy = h * (P[1] / m0), sz = h * (P[2] / m0);
+  double4 p = xm[i];
+  p.x = p.x + sx; p.y = p.y + sy; p.z = p.z + sz;
+  xm[i] = p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_jump_drift(double4 *__restrict__ xm,
+                                                       double4 *__restrict__ v,
+                                                       const double4 *__restrict__ mom_in, int nb,
+                                                       int n, double hjump, double dt, double m0,
+                                                       double mu, uint32_t *__restrict__ status,
+                                                       double4 *__restrict__ mom_out) {
+  __shared__ double lds[3 * kBlock];
+  double P[3];
+  momentum_total(mom_in, nb, P, lds);
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double Q[3] = {0.0, 0.0, 0.0};
+  if (i < n) {
+    const double sx = hjump * (P[0] / m0), sy = hjump * (P[1] / m0), sz = hjump * (P[2] / m0);
+    double4 p = xm[i];
+    double4 q = v[i];
+    p.x = p.x + sx; p.y = p.y + sy; p.z = p.z + sz;
+    const int st = kepler_advance(p.x, p.y, p.z, q.x, q.y, q.z, mu, dt);
+    xm[i] = p;
+    v[i] = q;
+    if (status) status[i] |= (uint32_t)st;
+    Q[0] = p.w * q.x; Q[1] = p.w * q.y; Q[2] = p.w * q.z;
+  }
+  block_sum<3>(Q, lds);
+  if (threadIdx.x == 0) mom_out[blockIdx.x] = make_double4(Q[0], Q[1], Q[2], 0.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_drift(double4 *__restrict__ xm, double4 *__restrict__ v,
+                                                  int n, double dt, double mu,
+                                                  uint32_t *__restrict__ status) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double4 p = xm[i];
+  double4 q = v[i];
+  const int st = kepler_advance(p.x, p.y, p.z, q.x, q.y, q.z, mu, dt);
+  xm[i] = p;
+  v[i] = q;
+  if (status) status[i] = (uint32_t)st;
+}
+
+hipError_t launch_momentum(const double4 *xm, const double4 *v, int n, double4 *mom, hipStream_t st) {
+  hipLaunchKernelGGL(k_momentum, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, n, mom);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump(double4 *xm, const double4 *mom, int nb, int n, double h, double m0,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_jump, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, mom, nb, n, h, m0);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump_drift(double4 *xm, double4 *v, const double4 *mom_in, int nb, int n,
+                             double hjump, double dt, double m0, double mu, uint32_t *status,
+                             double4 *mom_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_jump_drift, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, mom_in, nb, n,
+                     hjump, dt, m0, mu, status, mom_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, uint32_t *status,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_drift, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, n, dt, mu, status);
+  return hipGetLastError();
+}
+
+}  // namespace nbk

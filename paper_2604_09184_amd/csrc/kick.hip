@@ -1,0 +1,376 @@
+// H_B kick (eq. Hb), critical radius (eq. rcrit), close-encounter list and energy diagnostics.
+//
+// Pair kernel layout: one body i per lane (64 per wave, 256 per workgroup) and a j-range per
+// workgroup row (blockIdx.y). All lanes of a wave visit the same j, so the j-body (x, y, z, m)
+// and its threshold are wave-uniform and arrive through scalar loads into SGPRs: no LDS traffic
+// and no per-lane loads inside the loop. The per-pair fast path is binary64 FMA work plus one
+// quarter-rate reciprocal-square-root seed; close-encounter handling runs only for lanes whose r^2
+// passes a conservative wave-level bound (one integer compare per pair).
+#include "internal.hpp"
+
+namespace nbk {
+using namespace nbd;
+
+// ------------------------------------------------------------------ critical radius (eq. rcrit)
+__global__ __launch_bounds__(kBlock) void k_rcrit(const double4 *__restrict__ xm,
+                                                  const double4 *__restrict__ v,
+                                                  double4 *__restrict__ thr, int n, double m0,
+                                                  double cH, double cV, double n1, double n2dt) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = xm[i];
+  const double4 q = v[i];
+  const double r2 = fma(p.z, p.z, fma(p.y, p.y, p.x * p.x));
+  const double mu = p.w / m0;
+  const double vv = fma(q.z, q.z, fma(q.y, q.y, q.x * q.x));
+  const double H = (cH * ((r2 * r2) * r2)) * (mu * mu);
+  const double V = cV * vv;
+  const double rhill = sqrt(r2) * cbrt(mu / 3.0);
+  const double a = n1 * rhill, b = n2dt * sqrt(vv);
+  const double rc = a > b ? a : b;
+  // Every r^2 that these thresholds flag lies below max(V, cbrt(H)) up to a few roundings.
+  const double c = cbrt(H);
+  const double T = (V > c ? V : c) * (1.0 + 0x1p-30);
+  thr[i] = make_double4(rc, H, V, T);
+}
+
+hipError_t launch_rcrit(const double4 *xm, const double4 *v, double4 *thr, int n, double m0,
+                        double cH, double cV, double n1, double n2dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_rcrit, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, thr, n, m0, cH, cV, n1,
+                     n2dt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ pair kernel
+// FORCE: accumulate accelerations; EMIT: record close partners j > i; CE: accumulate the
+// complementary close-encounter acceleration; SPLIT: binary32 r^-3 core.
+template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm,
+                                                  const double4 *__restrict__ thr, int n, int chunk,
+                                                  double f_in, double4 *__restrict__ part,
+                                                  double4 *__restrict__ part_ce,
+                                                  int *__restrict__ cnt, int *__restrict__ rowbuf,
+                                                  int R, double c15, double c1875) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  const double4 pi = xm[ii];
+  // wave-uniform prefilter bound: a pair (i, j) can be close only if r^2 <= max(T_i, T_j)
+  const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+  int nc = 0;
+#pragma unroll 2
+  for (int j = j0; j < j1; ++j) {
+    const double4 pj = xm[j];
+    const uint32_t tj = hiword(thr[j].w);
+    const uint32_t U = tw > tj ? tw : tj;
+    const double dx = pj.x - pi.x;
+    const double dy = pj.y - pi.y;
+    const double dz = pj.z - pi.z;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double s = 0.0;
+    if (FORCE) s = SPLIT ? m_rinv3_split(r2, pj.w) : m_rinv3(r2, pj.w, c15, c1875);
+    if (hiword(r2) <= U) {
+      if (j == ii) {
+        s = 0.0;
+      } else {
+        const double4 ti = thr[ii];
+        const double4 tq = thr[j];
+        if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
+          if (FORCE) {
+            const double sn = pj.w * close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
+            if (CE) {
+              const double ds = s - sn;
+              cx = fma(ds, dx, cx);
+              cy = fma(ds, dy, cy);
+              cz = fma(ds, dz, cz);
+            }
+            s = sn;
+          }
+          if (EMIT && j > ii) {
+            if (nc < R) rowbuf[((size_t)blockIdx.y * R + nc) * n + ii] = j;
+            ++nc;
+          }
+        }
+      }
+    }
+    if (FORCE) {
+      ax = fma(s, dx, ax);
+      ay = fma(s, dy, ay);
+      az = fma(s, dz, az);
+    }
+  }
+  if (!valid) return;
+  const size_t o = (size_t)blockIdx.y * n + i;
+  if (FORCE) part[o] = make_double4(ax, ay, az, 0.0);
+  if (CE) part_ce[o] = make_double4(cx, cy, cz, 0.0);
+  if (EMIT) cnt[o] = nc;
+}
+
+template <bool F, bool E, bool C, bool S>
+static void go(const KickArgs &a, hipStream_t st) {
+  dim3 grid(nblocks(a.n), a.nchunk);
+  hipLaunchKernelGGL((k_pairs<F, E, C, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.n, a.chunk,
+                     a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5, 1.875);
+}
+
+hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool split,
+                        hipStream_t st) {
+  if (!force) {
+    go<false, true, false, false>(a, st);
+  } else if (split) {
+    if (emit) { ce ? go<true, true, true, true>(a, st) : go<true, true, false, true>(a, st); }
+    else { ce ? go<true, false, true, true>(a, st) : go<true, false, false, true>(a, st); }
+  } else {
+    if (emit) { ce ? go<true, true, true, false>(a, st) : go<true, true, false, false>(a, st); }
+    else { ce ? go<true, false, true, false>(a, st) : go<true, false, false, false>(a, st); }
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ finalize: sum partials
+__global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__ part,
+                                                     const double4 *__restrict__ part_ce, int S,
+                                                     int n, double G, double h, int napply,
+                                                     const double4 *__restrict__ xm,
+                                                     double4 *__restrict__ v,
+                                                     double4 *__restrict__ acc,
+                                                     double4 *__restrict__ acc_ce,
+                                                     double4 *__restrict__ mom) {
+  __shared__ double lds[3 * kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double P[3] = {0.0, 0.0, 0.0};
+  if (i < n) {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const double4 p = part[(size_t)s * n + i];
+      ax += p.x; ay += p.y; az += p.z;
+    }
+    ax *= G; ay *= G; az *= G;
+    if (acc) acc[i] = make_double4(ax, ay, az, 0.0);
+    if (acc_ce) {
+      double cx = 0.0, cy = 0.0, cz = 0.0;
+      for (int s = 0; s < S; ++s) {
+        const double4 p = part_ce[(size_t)s * n + i];
+        cx += p.x; cy += p.y; cz += p.z;
+      }
+      acc_ce[i] = make_double4(G * cx, G * cy, G * cz, 0.0);
+    }
+    if (v) {
+      double4 q = v[i];
+      for (int k = 0; k < napply; ++k) {
+        q.x = q.x + h * ax;
+        q.y = q.y + h * ay;
+        q.z = q.z + h * az;
+      }
+      v[i] = q;
+      const double m = xm[i].w;
+      P[0] = m * q.x; P[1] = m * q.y; P[2] = m * q.z;
+    }
+  }
+  if (mom) {
+    block_sum<3>(P, lds);
+    if (threadIdx.x == 0) mom[blockIdx.x] = make_double4(P[0], P[1], P[2], 0.0);
+  }
+}
+
+hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, int n, double G,
+                           double h, int napply, const double4 *xm, double4 *v, double4 *acc,
+                           double4 *acc_ce, double4 *mom, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(nblocks(n)), dim3(kBlock), 0, st, part, part_ce, S, n, G, h,
+                     napply, xm, v, acc, acc_ce, mom);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ encounter list emission
+// Rows are emitted in ascending i; within a row the chunks are visited in ascending j and each
+// chunk recorded its partners in ascending j, so the list comes out sorted by (i, j) without a
+// sort. A row-chunk with more partners than the buffer holds is rescanned here.
+__global__ __launch_bounds__(kBlock) void k_rowtot(const int *__restrict__ cnt, int S, int n,
+                                                   int64_t *__restrict__ rowtot,
+                                                   int64_t *__restrict__ bsum) {
+  __shared__ int64_t lds[kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  int64_t t = 0;
+  if (i < n)
+    for (int s = 0; s < S; ++s) t += cnt[(size_t)s * n + i];
+  if (i < n) rowtot[i] = t;
+  lds[threadIdx.x] = t;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = lds[0];
+}
+
+// Exclusive scan of the block sums in one workgroup of 1024 threads; writes the total.
+__global__ __launch_bounds__(1024) void k_scan_bsum(int64_t *__restrict__ bsum, int nb,
+                                                    int64_t *__restrict__ count) {
+  __shared__ int64_t lds[1024];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = t * per, b1 = min(nb, b0 + per);
+  int64_t s = 0;
+  for (int b = b0; b < b1; ++b) s += bsum[b];
+  lds[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t add = t >= o ? lds[t - o] : 0;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  int64_t run = lds[t] - s;  // exclusive prefix of this thread's segment
+  for (int b = b0; b < b1; ++b) {
+    const int64_t x = bsum[b];
+    bsum[b] = run;
+    run += x;
+  }
+  if (t == 1023) *count = lds[1023];
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
+                                                 const double4 *__restrict__ thr, int n, int S,
+                                                 int chunk, const int *__restrict__ cnt,
+                                                 const int *__restrict__ rowbuf, int R,
+                                                 const int64_t *__restrict__ rowtot,
+                                                 const int64_t *__restrict__ boff,
+                                                 int32_t *__restrict__ pairs, int64_t cap) {
+  __shared__ int64_t lds[kBlock];
+  const int t = threadIdx.x;
+  const int i = blockIdx.x * kBlock + t;
+  const int64_t mine = i < n ? rowtot[i] : 0;
+  lds[t] = mine;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    int64_t add = t >= o ? lds[t - o] : 0;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  if (i >= n || mine == 0) return;
+  int64_t off = boff[blockIdx.x] + lds[t] - mine;
+  if (off >= cap) return;
+  for (int s = 0; s < S; ++s) {
+    const int c = cnt[(size_t)s * n + i];
+    if (c == 0) continue;
+    if (c <= R) {
+      for (int k = 0; k < c && off < cap; ++k, ++off) {
+        pairs[2 * off] = i;
+        pairs[2 * off + 1] = rowbuf[((size_t)s * R + k) * n + i];
+      }
+    } else {
+      const double4 pi = xm[i];
+      const double4 ti = thr[i];
+      const int j0 = max(i + 1, s * chunk), j1 = min(n, (s + 1) * chunk);
+      for (int j = j0; j < j1 && off < cap; ++j) {
+        const double4 pj = xm[j];
+        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const double4 tq = thr[j];
+        if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
+          pairs[2 * off] = i;
+          pairs[2 * off + 1] = j;
+          ++off;
+        }
+      }
+    }
+    if (off >= cap) return;
+  }
+}
+
+hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
+                       int64_t *rowtot, int64_t *bsum, hipStream_t st) {
+  const int nb = nblocks(a.n);
+  hipLaunchKernelGGL(k_rowtot, dim3(nb), dim3(kBlock), 0, st, a.cnt, a.nchunk, a.n, rowtot, bsum);
+  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, count);
+  if (pairs && cap > 0)
+    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kBlock), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
+                       a.cnt, a.rowbuf, a.R, rowtot, bsum, pairs, cap);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ energy diagnostics
+// Per block: kinetic, star potential, Newtonian pair potential, K-weighted pair potential,
+// angular momentum and momentum partial sums (10 doubles), then one block sums the partials.
+__global__ __launch_bounds__(kBlock) void k_energy_parts(const double4 *__restrict__ xm,
+                                                         const double4 *__restrict__ v,
+                                                         const double4 *__restrict__ thr, int n,
+                                                         double G, double m0, double f_in,
+                                                         double *__restrict__ parts) {
+  __shared__ double lds[10 * kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < n) {
+    const double4 p = xm[i];
+    const double4 q = v[i];
+    const double4 ti = thr[i];
+    double eN = 0.0, eK = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double4 pj = xm[j];
+      const double dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
+      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+      const double r = sqrt(r2);
+      const double e = pj.w / r;
+      eN += e;
+      const double4 tq = thr[j];
+      if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
+        const double rcij = ti.x > tq.x ? ti.x : tq.x;
+        double y = (r - f_in * rcij) / ((1.0 - f_in) * rcij);
+        double K = 1.0;
+        if (y <= 0.0) K = 0.0;
+        else if (y < 1.0) K = y * y / (2.0 * y * y - 2.0 * y + 1.0);
+        eK += e * K;
+      } else {
+        eK += e;
+      }
+    }
+    acc[0] = 0.5 * p.w * (q.x * q.x + q.y * q.y + q.z * q.z);
+    acc[1] = -G * m0 * p.w / sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+    acc[2] = -0.5 * G * p.w * eN;
+    acc[3] = -0.5 * G * p.w * eK;
+    acc[4] = p.w * (p.y * q.z - p.z * q.y);
+    acc[5] = p.w * (p.z * q.x - p.x * q.z);
+    acc[6] = p.w * (p.x * q.y - p.y * q.x);
+    acc[7] = p.w * q.x;
+    acc[8] = p.w * q.y;
+    acc[9] = p.w * q.z;
+  }
+  block_sum<10>(acc, lds);
+  if (threadIdx.x < 10) parts[(size_t)blockIdx.x * 10 + threadIdx.x] = acc[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_final(const double *__restrict__ parts, int nb,
+                                                         double m0, double *__restrict__ out) {
+  __shared__ double lds[10 * kBlock];
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += kBlock)
+    for (int k = 0; k < 10; ++k) acc[k] += parts[(size_t)b * 10 + k];
+  block_sum<10>(acc, lds);
+  if (threadIdx.x == 0) {
+    const double hc = (acc[7] * acc[7] + acc[8] * acc[8] + acc[9] * acc[9]) / (2.0 * m0);
+    out[0] = acc[0] + acc[1] + acc[2] + hc;
+    out[1] = acc[0] + acc[1] + acc[3] + hc;
+    for (int k = 0; k < 3; ++k) {
+      out[2 + k] = acc[4 + k];
+      out[5 + k] = acc[7 + k];
+    }
+  }
+}
+
+hipError_t launch_energy(const double4 *xm, const double4 *v, const double4 *thr, int n, double G,
+                         double m0, double f_in, double4 *eparts, double *out, hipStream_t st) {
+  const int nb = nblocks(n);
+  double *parts = reinterpret_cast<double *>(eparts);
+  hipLaunchKernelGGL(k_energy_parts, dim3(nb), dim3(kBlock), 0, st, xm, v, thr, n, G, m0, f_in,
+                     parts);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, parts, nb, m0, out);
+  return hipGetLastError();
+}
+
+}  // namespace nbk

@@ -1,0 +1,345 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Tolerances (binary64 path):
+  accelerations: |a - a_ref|_inf <= 1e-12 * max(|a_ref|_inf, l1) per body, l1 = G sum_j m_j |w_ij| r_ij
+                 (the conditioning of the sum; both sides sum in different orders);
+  encounter lists: bit-exact (the predicate is evaluated exactly in binary64 on both sides);
+  thresholds H, V: bit-exact; rc: 4 ulp (cube root of two libraries);
+  drift: 1e-14 relative per step; states after k steps: 1e-11 relative (chaotic growth over 10
+  steps of roundoff differences in the Kepler solve and summation order).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import diskgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2604_09184_amd as nb
+    nb.lib()
+    return nb
+
+
+@pytest.fixture(scope="module")
+def ctx(nb):
+    return nb.Context(nb.Params(**diskgen.PARAMS))
+
+
+DEV = "cuda:0"
+
+
+def to_dev(d):
+    xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+    return torch.tensor(xm, device=DEV), torch.tensor(v4, device=DEV)
+
+
+def acc_err(acc, oacc, l1):
+    return (np.abs(acc - oacc).max(1) / np.maximum(np.abs(oacc).max(1), l1)).max()
+
+
+def cluster_disk(n, ncl, seed=11):
+    """Disk with ncl consecutive bodies packed into a tight clump (many close pairs per row)."""
+    d = diskgen.workload("disk2048", n=n)
+    rng = np.random.default_rng(seed)
+    c0 = d["x"][0].copy()
+    d["x"][:ncl] = c0 + 0.004 * rng.standard_normal((ncl, 3))
+    d["v"][:ncl] = d["v"][0] + 1e-3 * rng.standard_normal((ncl, 3))
+    return d
+
+
+# ------------------------------------------------------------------ thresholds
+def test_rcrit_matches_oracle(ctx):
+    p = diskgen.PARAMS
+    for n in (1, 77, 2048):
+        say(f"rcrit n={n}")
+        d = diskgen.workload("disk2048", n=n)
+        X, V = to_dev(d)
+        thr = ctx.rcrit(X, V).cpu().numpy()
+        rc, H, V_ = oracle.thresholds(d["x"], d["v"], d["m"], p)
+        np.testing.assert_array_equal(thr[:, 1], H)
+        np.testing.assert_array_equal(thr[:, 2], V_)
+        np.testing.assert_allclose(thr[:, 0], rc, rtol=1e-15, atol=0)
+        assert np.all(thr[:, 3] >= np.maximum(V_, np.cbrt(H)))
+
+
+# ------------------------------------------------------------------ kick
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 255, 257, 1000, 2048])
+def test_kick_matches_oracle_ragged(ctx, n):
+    say(f"kick n={n}")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048", n=n)
+    X, V = to_dev(d)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    thr = ctx.rcrit(X, V)
+    acc, ce = ctx.accelerations(X, thr, with_ce=True)
+    oacc, oce, l1 = oracle.kick_acc(d["x"], d["m"], othr, p)
+    a = acc.cpu().numpy()[:, :3]
+    assert acc_err(a, oacc, l1) < 1e-12
+    c = ce.cpu().numpy()[:, :3]
+    assert (np.abs(c - oce).max(1) / np.maximum(l1, 1e-300)).max() < 1e-12
+
+
+def test_kick_single_body_is_zero(ctx):
+    say("kick n=1")
+    d = diskgen.workload("disk2048", n=1)
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    acc = ctx.accelerations(X, thr)
+    assert torch.all(acc == 0)
+
+
+def test_kick_close_cluster_and_velocity_update(ctx):
+    say("kick cluster n=1500 ncl=300")
+    p = diskgen.PARAMS
+    d = cluster_disk(1500, 300)
+    X, V = to_dev(d)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    thr = ctx.rcrit(X, V)
+    oacc, oce, l1 = oracle.kick_acc(d["x"], d["m"], othr, p)
+    assert np.abs(oce).max() > 0
+    acc, ce = ctx.accelerations(X, thr, with_ce=True)
+    assert acc_err(acc.cpu().numpy()[:, :3], oacc, l1) < 1e-12
+    v0 = V.clone()
+    h = 0.05
+    ctx.kick(X, thr, V, h)
+    ref = d["v"] + h * oacc
+    got = V.cpu().numpy()
+    assert np.abs(got[:, :3] - ref).max() <= 1e-12 * h * np.maximum(np.abs(oacc).max(1), l1).max() + 4e-16
+    assert torch.equal(V[:, 3], v0[:, 3])
+
+
+def test_kick_split_precision_error_bound(nb):
+    say("kick split n=2048")
+    p = diskgen.PARAMS
+    ctx_s = nb.Context(nb.Params(**p, precision=nb.PREC_SPLIT))
+    d = diskgen.workload("disk2048")
+    X, V = to_dev(d)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    thr = ctx_s.rcrit(X, V)
+    acc = ctx_s.accelerations(X, thr).cpu().numpy()[:, :3]
+    oacc, _, l1 = oracle.kick_acc(d["x"], d["m"], othr, p)
+    err = acc_err(acc, oacc, l1)
+    # binary32 r^-3: each term carries ~1e-7 relative error
+    assert err < 1e-6
+    assert err > 1e-12       # really the split path
+
+
+# ------------------------------------------------------------------ encounters
+def test_encounters_bit_exact_disk(ctx):
+    say("encounters disk2048")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = to_dev(d)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    thr = ctx.rcrit(X, V)
+    pairs, count = ctx.encounters(X, thr)
+    ref = oracle.encounters(d["x"], othr)
+    assert count == len(ref) > 100
+    np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
+
+
+def test_encounters_dense_rows_and_truncation(ctx):
+    say("encounters cluster n=16384 ncl=400")
+    p = diskgen.PARAMS
+    d = cluster_disk(16384, 400)
+    X, V = to_dev(d)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    thr = ctx.rcrit(X, V)
+    ref = oracle.encounters(d["x"], othr)
+    rows = np.bincount(ref[:, 0], minlength=16384)
+    assert rows.max() > 200          # rows beyond the per-chunk buffer take the rescan path
+    pairs, count = ctx.encounters(X, thr)
+    assert count == len(ref)
+    np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
+    cap = len(ref) // 3
+    pairs_t, count_t = ctx.encounters(X, thr, cap=cap)
+    assert count_t == len(ref)
+    np.testing.assert_array_equal(pairs_t.cpu().numpy(), ref[:cap])
+
+
+def test_encounters_none_and_empty_capacity(ctx):
+    say("encounters far bodies")
+    x = np.array([[1.0, 0, 0], [-1.0, 0, 0], [0, 2.0, 0]])
+    v = np.array([[0, 1.0, 0], [0, -1.0, 0], [-0.7, 0, 0]])
+    m = np.full(3, 1e-9)
+    X, V = to_dev({"x": x, "v": v, "m": m})
+    thr = ctx.rcrit(X, V)
+    pairs, count = ctx.encounters(X, thr, cap=0)
+    assert count == 0
+
+
+# ------------------------------------------------------------------ jump and drift
+def test_jump_matches_oracle(ctx):
+    say("jump n=1000")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048", n=1000)
+    X, V = to_dev(d)
+    ctx.jump(X, V, 0.05)
+    ox = oracle.jump(d["x"], d["v"], d["m"], p, 0.05)
+    np.testing.assert_allclose(X.cpu().numpy()[:, :3], ox, rtol=0, atol=1e-15)
+
+
+def test_drift_matches_oracle(ctx):
+    say("drift disk n=2048")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    st = torch.zeros(2048, dtype=torch.int32, device=DEV)
+    for h in (p["dt"], -0.3 * p["dt"], 7.5):
+        X, V = to_dev(d)
+        ctx.drift(X, V, h, status=st)
+        ox, ov, ost = oracle.drift(d["x"], d["v"], p, h)
+        x = X.cpu().numpy()[:, :3]; v = V.cpu().numpy()[:, :3]
+        assert int(st.abs().max()) == 0
+        tol = 2e-14 if abs(h) < 1 else 2e-13      # phase error grows with the angle swept
+        assert (np.abs(x - ox).max(1) / np.linalg.norm(ox, axis=1)).max() < tol
+        assert (np.abs(v - ov).max(1) / np.linalg.norm(ov, axis=1)).max() < tol
+        np.testing.assert_array_equal(X[:, 3].cpu().numpy(), d["m"])
+
+
+def test_drift_hyperbolic_and_closed_form(ctx):
+    say("drift special orbits")
+    p = diskgen.PARAMS
+    r, mu = 1.3, 1.0
+    n = math.sqrt(mu / r ** 3)
+    x = np.array([[r, 0.0, 0.0], [0.8, 0.1, -0.05], [0.3, 0.0, 0.0]])
+    v = np.array([[0.0, r * n, 0.0], [0.3, 1.9, 0.2], [0.0, 2.5, 0.1]])
+    X, V = to_dev({"x": x, "v": v, "m": np.zeros(3)})
+    t = 0.731
+    ctx.drift(X, V, t)
+    got = X.cpu().numpy()[:, :3]
+    np.testing.assert_allclose(got[0], r * np.array([math.cos(n * t), math.sin(n * t), 0.0]), atol=2e-15)
+    ox, ov, _ = oracle.drift(x, v, p, t)
+    np.testing.assert_allclose(got, ox, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(V.cpu().numpy()[:, :3], ov, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------------ full step
+def test_step_matches_oracle_disk2048(ctx):
+    """The small workload: N = 2048, 10 steps at dt = 6 days; state and final encounter list."""
+    say("step disk2048 x10")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    pairs, count = ctx.step(X, V, 10, thr=thr, pairs_cap=100000)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov, st = oracle.step(d["x"], d["v"], d["m"], p, 10, thr=othr)
+    x = X.cpu().numpy()[:, :3]; v = V.cpu().numpy()[:, :3]
+    ex = (np.abs(x - ox).max(1) / np.linalg.norm(ox, axis=1)).max()
+    ev = (np.abs(v - ov).max(1) / np.linalg.norm(ov, axis=1)).max()
+    say(f"  state rel err x {ex:.2e} v {ev:.2e}")
+    assert ex < 1e-11 and ev < 1e-11
+    ref = oracle.encounters(ox, othr)
+    assert count == len(ref)
+    np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
+
+
+def test_step_composition_and_determinism(ctx):
+    say("step composition n=700")
+    d = diskgen.workload("disk2048", n=700)
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    X1, V1 = X.clone(), V.clone()
+    ctx.step(X1, V1, 6, thr=thr)
+    X2, V2 = X.clone(), V.clone()
+    ctx.step(X2, V2, 2, thr=thr)
+    ctx.step(X2, V2, 4, thr=thr)
+    X3, V3 = X.clone(), V.clone()
+    ctx.step(X3, V3, 6, thr=thr)
+    torch.cuda.synchronize()
+    assert torch.equal(X1, X2) and torch.equal(V1, V2)
+    assert torch.equal(X1, X3) and torch.equal(V1, V3)
+
+
+def test_step_zero_steps_lists_pairs(ctx):
+    say("step nsteps=0")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = to_dev(d)
+    X0 = X.clone()
+    pairs, count = ctx.step(X, V, 0, pairs_cap=10000)
+    assert torch.equal(X, X0)
+    ref = oracle.encounters(d["x"], oracle.thresholds(d["x"], d["v"], d["m"], p))
+    np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
+
+
+def test_energy_matches_oracle(ctx):
+    say("energy n=2048")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    e = ctx.energy(X, V, thr)
+    oe = oracle.energy(d["x"], d["v"], d["m"], p, oracle.thresholds(d["x"], d["v"], d["m"], p))
+    assert abs(e["E"] - oe["E"]) < 1e-13 * abs(oe["E"])
+    assert abs(e["Eprime"] - oe["Eprime"]) < 1e-13 * abs(oe["Eprime"])
+    np.testing.assert_allclose(e["L"], oe["L"], rtol=1e-13)
+    scale = (d["m"][:, None] * np.abs(d["v"])).sum()
+    np.testing.assert_allclose(e["P"], oe["P"], rtol=0, atol=1e-14 * scale)
+
+
+# ------------------------------------------------------------------ full size (N = 32768)
+@pytest.fixture(scope="module")
+def big():
+    d = diskgen.workload("disk32768")
+    p = diskgen.PARAMS
+    return d, oracle.thresholds(d["x"], d["v"], d["m"], p)
+
+
+def test_full_size_kick_sampled_rows(ctx, big):
+    say("kick disk32768 sampled rows")
+    d, othr = big
+    p = diskgen.PARAMS
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    acc = ctx.accelerations(X, thr).cpu().numpy()[:, :3]
+    rows = np.random.default_rng(5).choice(len(d["m"]), 96, replace=False)
+    rows = np.concatenate([rows, [0, 1, 32767, 16384]])
+    oacc, l1 = oracle.kick_acc_rows(d["x"], d["m"], othr, p, rows)
+    err = (np.abs(acc[rows] - oacc).max(1) / np.maximum(np.abs(oacc).max(1), l1)).max()
+    say(f"  max rel err {err:.2e}")
+    assert err < 1e-12
+    mom = (d["m"][:, None] * acc).sum(0)
+    assert np.abs(mom).max() < 1e-13 * (d["m"][:, None] * np.abs(acc)).sum()
+
+
+def test_full_size_encounters(ctx, big):
+    say("encounters disk32768")
+    d, othr = big
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    pairs, count = ctx.encounters(X, thr)
+    ref = oracle.encounters(d["x"], othr)
+    say(f"  {count} pairs")
+    assert count == len(ref)
+    np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
+
+
+def test_full_size_long_run_invariants(ctx, big):
+    """1000 steps at N = 32768: angular momentum to roundoff, K-weighted energy bounded."""
+    say("step disk32768 x1000 invariants")
+    d, othr = big
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    e0 = ctx.energy(X, V, thr)
+    ctx.step(X, V, 1000, thr=thr)
+    e1 = ctx.energy(X, V, thr)
+    dL = np.abs(e1["L"] - e0["L"]).max() / np.abs(e0["L"]).max()
+    dE = abs(e1["Eprime"] - e0["Eprime"]) / abs(e0["Eprime"])
+    say(f"  dL/L {dL:.2e}  dE'/E' {dE:.2e}")
+    assert dL < 1e-11
+    assert dE < 1e-7
