@@ -128,6 +128,33 @@ int nbody_energy(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, c
                  double *out, void *stream);
 
 /*
+ * Reverse-mode derivatives (vector-Jacobian products) with the thresholds thr held fixed, for
+ * sensitivity analysis and orbit fitting. Adjoint arrays mirror the state layout:
+ * lam_x [n][4] = dL/d{x, y, z, m} and lam_v [n][4] = dL/d{vx, vy, vz, pad}; the mass adjoint
+ * accumulates in lam_x[:, 3]. All adjoint arrays are device, in/out.
+ *
+ * nbody_kick_vjp:  for v' = v + h a(x, m) at positions xm: lam_x += (d(h a)/d(x, m))^T lam_v
+ *                  (lam_v itself passes through unchanged).
+ * nbody_jump_vjp:  for x' = x + h P/m0, P = sum m_j v_j, at state (xm, v):
+ *                  lam_v_j += (h/m0) m_j sum_i lam_x_i,  lam_x_j[3] += (h/m0) v_j . sum_i lam_x_i.
+ * nbody_drift_vjp: for the drift by h from the state (xm, v) BEFORE the drift: replaces
+ *                  (lam_x[:, 0:3], lam_v[:, 0:3]) by their pull-back through the Kepler flow.
+ * nbody_step_vjp:  for nsteps steps of nbody_step starting at (xm0, v0) with thresholds thr:
+ *                  on entry (lam_x, lam_v) hold dL/d(final state) (lam_x[:, 3] any accumulated
+ *                  dL/dm); on return they hold dL/d(xm0, v0), lam_x[:, 3] having gained the mass
+ *                  derivatives of these steps. States inside the segment are recomputed from
+ *                  (xm0, v0) bit for bit; workspace grows by 2 n nsteps x 32 bytes.
+ */
+int nbody_kick_vjp(nbody_ctx *ctx, int64_t n, const double *xm, const double *thr, double h,
+                   const double *lam_v, double *lam_x, void *stream);
+int nbody_jump_vjp(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, double h,
+                   double *lam_x, double *lam_v, void *stream);
+int nbody_drift_vjp(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, double h,
+                    double *lam_x, double *lam_v, void *stream);
+int nbody_step_vjp(nbody_ctx *ctx, int64_t n, const double *xm0, const double *v0, const double *thr,
+                   int32_t nsteps, double *lam_x, double *lam_v, void *stream);
+
+/*
  * Measurement helper: launches the pair kernel of nbody_kick (no velocity update, no outputs
  * beyond the context's partial sums) `reps` times between two HIP events recorded on `stream`,
  * waits for the second event and stores the mean duration of one launch in milliseconds in

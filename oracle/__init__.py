@@ -53,6 +53,9 @@ def _lib():
         "or_step_jvp": (ctypes.c_int, [I, P, P, P, P, P, P, P, ctypes.c_int, P, P, P, P]),
         "or_energy": (None, [I, P, P, P, P, P, P, P, P]),
         "or_num_threads": (ctypes.c_int, []),
+        "or_kick_jvp": (None, [I, P, P, P, P, P, P, P, P, P]),
+        "or_drift_jvp": (None, [I, P, P, P, P, P, D, P, P]),
+        "or_jump_jvp": (None, [I, P, P, P, P, P, P, P, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -175,6 +178,32 @@ def step_jvp(x, v, m, p, nsteps, dx=None, dv=None, dm=None):
     st = _lib().or_step_jvp(n, _p(x), _p(v), _p(m), _p(dx), _p(dv), _p(dm), _p(_prm(p)), nsteps,
                             _p(xo), _p(vo), _p(dxo), _p(dvo))
     return xo, vo, dxo, dvo, st
+
+
+def kick_jvp(x, m, thr, p, dx, dm):
+    """Directional derivative of the H_B accelerations (thresholds fixed)."""
+    x = _f64(x); m = _f64(m); dx = _f64(dx); dm = _f64(dm)
+    rc, H, V = (_f64(t) for t in thr)
+    n = m.shape[0]
+    out = np.empty((n, 3))
+    _lib().or_kick_jvp(n, _p(x), _p(m), _p(dx), _p(dm), _p(rc), _p(H), _p(V), _p(_prm(p)), _p(out))
+    return out
+
+
+def drift_jvp(x, v, p, h, dx, dv):
+    x = _f64(x); v = _f64(v); dx = _f64(dx); dv = _f64(dv)
+    n = x.shape[0]
+    ox, ov = np.empty((n, 3)), np.empty((n, 3))
+    _lib().or_drift_jvp(n, _p(x), _p(v), _p(dx), _p(dv), _p(_prm(p)), h, _p(ox), _p(ov))
+    return ox, ov
+
+
+def jump_jvp(x, v, m, p, h, dx, dv, dm):
+    x = _f64(x); v = _f64(v); m = _f64(m); dx = _f64(dx); dv = _f64(dv); dm = _f64(dm)
+    n = m.shape[0]
+    out = np.empty((n, 3))
+    _lib().or_jump_jvp(n, _p(x), _p(v), _p(m), _p(dx), _p(dv), _p(dm), _p(_prm(p)), h, _p(out))
+    return out
 
 
 def energy(x, v, m, p, thr):

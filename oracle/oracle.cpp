@@ -512,6 +512,44 @@ int or_step_jvp(int64_t n, const double *x, const double *v, const double *m, co
   return st;
 }
 
+// Forward-mode derivatives of the three parts of a step, for checking reverse-mode code.
+// Kick: d(acc) for a change (dx, dm) of positions and masses (thresholds fixed).
+void or_kick_jvp(int64_t n, const double *x, const double *m, const double *dx, const double *dm,
+                 const double *rc, const double *H, const double *V, const double *prm, double *dacc) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<dual> X(3 * n), M(n), A(3 * n);
+  for (int64_t i = 0; i < 3 * n; i++) X[i] = dual(x[i], dx[i]);
+  for (int64_t i = 0; i < n; i++) M[i] = dual(m[i], dm[i]);
+  kick_acc<dual>(n, X.data(), M.data(), rc, H, V, p, A.data(), nullptr, nullptr);
+  for (int64_t i = 0; i < 3 * n; i++) dacc[i] = A[i].d;
+}
+
+// Drift by h: d(x', v') for a change (dx, dv) of the state before the drift.
+void or_drift_jvp(int64_t n, const double *x, const double *v, const double *dx, const double *dv,
+                  const double *prm, double h, double *dx_out, double *dv_out) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  for (int64_t i = 0; i < n; i++) {
+    Dual<long double> X[3], W[3];
+    for (int k = 0; k < 3; k++) {
+      X[k] = Dual<long double>((long double)x[3 * i + k], (long double)dx[3 * i + k]);
+      W[k] = Dual<long double>((long double)v[3 * i + k], (long double)dv[3 * i + k]);
+    }
+    kepler<Dual<long double>>(X, W, p.G * p.m0, h);
+    for (int k = 0; k < 3; k++) { dx_out[3 * i + k] = (double)X[k].d; dv_out[3 * i + k] = (double)W[k].d; }
+  }
+}
+
+// Jump by h: d(x') for a change (dx, dv, dm).
+void or_jump_jvp(int64_t n, const double *x, const double *v, const double *m, const double *dx,
+                 const double *dv, const double *dm, const double *prm, double h, double *dx_out) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<dual> X(3 * n), W(3 * n), M(n);
+  for (int64_t i = 0; i < 3 * n; i++) { X[i] = dual(x[i], dx[i]); W[i] = dual(v[i], dv[i]); }
+  for (int64_t i = 0; i < n; i++) M[i] = dual(m[i], dm[i]);
+  jump<dual>(n, X.data(), W.data(), M.data(), p, dual(h));
+  for (int64_t i = 0; i < 3 * n; i++) dx_out[i] = X[i].d;
+}
+
 // Diagnostics: E (full Newtonian), Eprime (pair term weighted by K, the quantity the
 // hot-path step conserves), angular momentum L and total momentum P (barycentric velocities).
 void or_energy(int64_t n, const double *x, const double *v, const double *m, const double *prm,

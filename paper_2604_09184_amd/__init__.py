@@ -61,6 +61,10 @@ EXPORTS = {
     "nbody_step": [_I64, _P, _P, _P, _I32, _P, _I64, _P, _P],
     "nbody_energy": [_I64, _P, _P, _P, _P, _P],
     "nbody_bench_pairs": [_I64, _P, _P, _I32, _P, _P],
+    "nbody_kick_vjp": [_I64, _P, _P, _D, _P, _P, _P],
+    "nbody_jump_vjp": [_I64, _P, _P, _D, _P, _P, _P],
+    "nbody_drift_vjp": [_I64, _P, _P, _D, _P, _P, _P],
+    "nbody_step_vjp": [_I64, _P, _P, _P, _I32, _P, _P, _P],
 }
 OTHER_EXPORTS = ["nbody_create", "nbody_destroy", "nbody_set_params", "nbody_last_error",
                  "nbody_version"]
@@ -217,6 +221,32 @@ class Context:
         self._check(lib().nbody_bench_pairs(self._h, xm.shape[0], _ptr(xm), _ptr(thr), int(reps),
                                             ctypes.byref(ms), _stream()), "nbody_bench_pairs")
         return ms.value
+
+
+    # ------------------------------------------------------------ reverse mode
+    def kick_vjp(self, xm, thr, h, lam_v, lam_x):
+        for t, nm in ((xm, "xm"), (thr, "thr"), (lam_v, "lam_v"), (lam_x, "lam_x")):
+            _body(t, nm)
+        self._check(lib().nbody_kick_vjp(self._h, xm.shape[0], _ptr(xm), _ptr(thr), float(h), _ptr(lam_v),
+                                         _ptr(lam_x), _stream()), "nbody_kick_vjp")
+
+    def jump_vjp(self, xm, v, h, lam_x, lam_v):
+        for t, nm in ((xm, "xm"), (v, "v"), (lam_x, "lam_x"), (lam_v, "lam_v")):
+            _body(t, nm)
+        self._check(lib().nbody_jump_vjp(self._h, xm.shape[0], _ptr(xm), _ptr(v), float(h), _ptr(lam_x),
+                                         _ptr(lam_v), _stream()), "nbody_jump_vjp")
+
+    def drift_vjp(self, xm, v, h, lam_x, lam_v):
+        for t, nm in ((xm, "xm"), (v, "v"), (lam_x, "lam_x"), (lam_v, "lam_v")):
+            _body(t, nm)
+        self._check(lib().nbody_drift_vjp(self._h, xm.shape[0], _ptr(xm), _ptr(v), float(h), _ptr(lam_x),
+                                          _ptr(lam_v), _stream()), "nbody_drift_vjp")
+
+    def step_vjp(self, xm0, v0, thr, nsteps, lam_x, lam_v):
+        for t, nm in ((xm0, "xm0"), (v0, "v0"), (thr, "thr"), (lam_x, "lam_x"), (lam_v, "lam_v")):
+            _body(t, nm)
+        self._check(lib().nbody_step_vjp(self._h, xm0.shape[0], _ptr(xm0), _ptr(v0), _ptr(thr), int(nsteps),
+                                         _ptr(lam_x), _ptr(lam_v), _stream()), "nbody_step_vjp")
 
 
 def version():

@@ -21,7 +21,7 @@ struct Buf {
 };
 
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
-             B_COUNT_SCRATCH, B_NUM };
+             B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_NUM };
 
 }  // namespace
 
@@ -142,6 +142,54 @@ int emit_list(nbody_ctx *c, const KickArgs &a, int32_t *pairs, int64_t cap, int6
   int64_t *bsum = (int64_t *)ensure(c, B_BSUM, (size_t)nb * sizeof(int64_t));
   if (!rowtot || !bsum) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (emission)");
   HIPCHK(c, launch_emit(a, pairs, cap, count, rowtot, bsum, st), "encounter emission");
+  return NBODY_OK;
+}
+
+// lam += VJP of the kick v' = v + h a(x) at positions xm (adds to lam_x, including dL/dm).
+int kick_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *thr, const double4 *lam_v, double h,
+             double4 *lam_x, hipStream_t st) {
+  KickArgs a;
+  TRY(make_kick_args(c, n, (const double *)xm, (const double *)thr, true, false, false, a));
+  double4 *la = (double4 *)ensure(c, B_LAMA, (size_t)n * sizeof(double4));
+  if (!la) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint)");
+  HIPCHK(c, launch_kick_vjp(xm, thr, lam_v, h, c->p.G, c->p.f_in, n, a.nchunk, a.chunk, la, a.part, lam_x, st),
+         "kick vjp");
+  return NBODY_OK;
+}
+
+int jump_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *v, double h, double4 *lam_x,
+             double4 *lam_v, hipStream_t st) {
+  double4 *parts = (double4 *)ensure(c, B_LSUM, (size_t)nblocks(n) * sizeof(double4));
+  if (!parts) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint)");
+  HIPCHK(c, launch_jump_vjp(xm, v, h, c->p.m0, n, parts, lam_x, lam_v, st), "jump vjp");
+  return NBODY_OK;
+}
+
+// One step B C A C B of (X, V) in place with unmerged kicks; optionally keeps the velocity after
+// the first kick (V1), the position before the drift (X1) and the velocity after the drift (V2).
+int one_step(nbody_ctx *c, int n, double4 *X, double4 *V, const double4 *thr, double4 *X1, double4 *V1,
+             double4 *V2, hipStream_t st) {
+  const nbody_params &p = c->p;
+  const double h = 0.5 * p.dt;
+  const int nb = nblocks(n);
+  const size_t bytes = (size_t)n * sizeof(double4);
+  double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
+  if (!mom) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
+  KickArgs a;
+  TRY(make_kick_args(c, n, (const double *)X, (const double *)thr, true, false, false, a));
+  HIPCHK(c, launch_pairs(a, true, false, false, p.precision == NBODY_PREC_SPLIT, st), "pairs");
+  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, n, p.G, h, 1, X, V, nullptr, nullptr, mom, st),
+         "finalize");
+  if (V1) HIPCHK(c, hipMemcpyAsync(V1, V, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  HIPCHK(c, launch_jump(X, mom, nb, n, h, p.m0, st), "jump");
+  if (X1) HIPCHK(c, hipMemcpyAsync(X1, X, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  HIPCHK(c, launch_drift(X, V, n, p.dt, p.G * p.m0, nullptr, st), "drift");
+  if (V2) HIPCHK(c, hipMemcpyAsync(V2, V, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  HIPCHK(c, launch_momentum(X, V, n, mom, st), "momentum");
+  HIPCHK(c, launch_jump(X, mom, nb, n, h, p.m0, st), "jump");
+  HIPCHK(c, launch_pairs(a, true, false, false, p.precision == NBODY_PREC_SPLIT, st), "pairs");
+  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, n, p.G, h, 1, X, V, nullptr, nullptr, nullptr, st),
+         "finalize");
   return NBODY_OK;
 }
 
@@ -319,6 +367,85 @@ int nbody_energy(nbody_ctx *c, int64_t n, const double *xm, const double *v, con
   if (!ep) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (energy)");
   HIPCHK(c, launch_energy((const double4 *)xm, (const double4 *)v, (const double4 *)thr, (int)n, c->p.G,
                           c->p.m0, c->p.f_in, ep, out, (hipStream_t)stream), "energy");
+  return NBODY_OK;
+}
+
+int nbody_kick_vjp(nbody_ctx *c, int64_t n, const double *xm, const double *thr, double h,
+                   const double *lam_v, double *lam_x, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, thr, "thr", true));
+  TRY(check_dev(c, lam_v, "lam_v", true));
+  TRY(check_dev(c, lam_x, "lam_x", true));
+  return kick_vjp(c, (int)n, (const double4 *)xm, (const double4 *)thr, (const double4 *)lam_v, h,
+                  (double4 *)lam_x, (hipStream_t)stream);
+}
+
+int nbody_jump_vjp(nbody_ctx *c, int64_t n, const double *xm, const double *v, double h, double *lam_x,
+                   double *lam_v, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, lam_x, "lam_x", true));
+  TRY(check_dev(c, lam_v, "lam_v", true));
+  return jump_vjp(c, (int)n, (const double4 *)xm, (const double4 *)v, h, (double4 *)lam_x, (double4 *)lam_v,
+                  (hipStream_t)stream);
+}
+
+int nbody_drift_vjp(nbody_ctx *c, int64_t n, const double *xm, const double *v, double h, double *lam_x,
+                    double *lam_v, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, lam_x, "lam_x", true));
+  TRY(check_dev(c, lam_v, "lam_v", true));
+  HIPCHK(c, launch_drift_vjp((const double4 *)xm, (const double4 *)v, (int)n, h, c->p.G * c->p.m0,
+                             (double4 *)lam_x, (double4 *)lam_v, (hipStream_t)stream), "drift vjp");
+  return NBODY_OK;
+}
+
+int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0, const double *thr,
+                   int32_t nsteps, double *lam_x, double *lam_v, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm0, "xm0", true));
+  TRY(check_dev(c, v0, "v0", true));
+  TRY(check_dev(c, thr, "thr", true));
+  TRY(check_dev(c, lam_x, "lam_x", true));
+  TRY(check_dev(c, lam_v, "lam_v", true));
+  if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
+  if (nsteps == 0) return NBODY_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int N = (int)n;
+  const size_t bytes = (size_t)n * sizeof(double4);
+  double4 *S = (double4 *)ensure(c, B_ADJ_STATES, 2 * bytes * (size_t)nsteps);
+  double4 *XA = (double4 *)ensure(c, B_XA, bytes);
+  double4 *VA = (double4 *)ensure(c, B_VA, bytes);
+  double4 *X1 = (double4 *)ensure(c, B_X1, bytes);
+  double4 *V1 = (double4 *)ensure(c, B_V1, bytes);
+  double4 *V2 = (double4 *)ensure(c, B_V2, bytes);
+  if (!S || !XA || !VA || !X1 || !V1 || !V2) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint states)");
+  const double4 *T = (const double4 *)thr;
+  const double h = 0.5 * c->p.dt;
+  // states at the start of every step of the segment
+  HIPCHK(c, hipMemcpyAsync(S, xm0, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  HIPCHK(c, hipMemcpyAsync(S + N, v0, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    double4 *Xs = S + (size_t)2 * s * N, *Xn = S + (size_t)2 * (s + 1) * N;
+    HIPCHK(c, hipMemcpyAsync(Xn, Xs, 2 * bytes, hipMemcpyDeviceToDevice, st), "copy");
+    TRY(one_step(c, N, Xn, Xn + N, T, nullptr, nullptr, nullptr, st));
+  }
+  double4 *LX = (double4 *)lam_x, *LV = (double4 *)lam_v;
+  for (int s = nsteps - 1; s >= 0; --s) {
+    const double4 *Xs = S + (size_t)2 * s * N;
+    HIPCHK(c, hipMemcpyAsync(XA, Xs, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    HIPCHK(c, hipMemcpyAsync(VA, Xs + N, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    TRY(one_step(c, N, XA, VA, T, X1, V1, V2, st));
+    TRY(kick_vjp(c, N, XA, T, LV, h, LX, st));          // second half kick at x_{s+1}
+    TRY(jump_vjp(c, N, XA, V2, h, LX, LV, st));          // jump after the drift
+    HIPCHK(c, launch_drift_vjp(X1, V1, N, c->p.dt, c->p.G * c->p.m0, LX, LV, st), "drift vjp");
+    TRY(jump_vjp(c, N, X1, V1, h, LX, LV, st));          // jump before the drift
+    TRY(kick_vjp(c, N, Xs, T, LV, h, LX, st));           // first half kick at x_s
+  }
   return NBODY_OK;
 }
 

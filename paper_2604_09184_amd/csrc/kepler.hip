@@ -5,69 +5,10 @@
 // body per lane, binary64 throughout. The jump shifts every position by h * P / m0; P is reduced
 // deterministically from per-workgroup partial sums by every workgroup in the same order.
 #include "internal.hpp"
+#include "kepler_core.hpp"
 
 namespace nbk {
 using namespace nbd;
-
-// Stumpff functions c0..c3 at z: argument quartered until |z| <= 0.1, series there, then the
-// quadrupling relations c0(4z) = 2c0^2 - 1, c1(4z) = c0 c1, c2(4z) = c1^2/2,
-// c3(4z) = (c2 + c0 c3)/4.
-__device__ __forceinline__ void stumpff(double z, double &c0, double &c1, double &c2, double &c3) {
-  int k = 0;
-  while (fabs(z) > 0.1 && k < 64) {
-    z *= 0.25;
-    ++k;
-  }
-  c2 = 0.5 - z * (1.0 / 24 - z * (1.0 / 720 - z * (1.0 / 40320 - z * (1.0 / 3628800 - z * (1.0 / 479001600)))));
-  c3 = 1.0 / 6 - z * (1.0 / 120 - z * (1.0 / 5040 - z * (1.0 / 362880 - z * (1.0 / 39916800 - z * (1.0 / 6227020800.0)))));
-  c1 = 1.0 - z * c3;
-  c0 = 1.0 - z * c2;
-  for (; k > 0; --k) {
-    c3 = (c2 + c0 * c3) * 0.25;
-    c2 = 0.5 * c1 * c1;
-    c1 = c0 * c1;
-    c0 = 2.0 * c0 * c0 - 1.0;
-  }
-}
-
-// Advance (x, v) by dt on the Kepler orbit about mu. Returns 0, or 1 if not converged.
-__device__ int kepler_advance(double &x, double &y, double &z, double &vx, double &vy, double &vz,
-                              double mu, double dt) {
-  const double r0 = sqrt(x * x + y * y + z * z);
-  const double v2 = vx * vx + vy * vy + vz * vz;
-  const double u = x * vx + y * vy + z * vz;
-  const double beta = 2.0 * mu / r0 - v2;
-  double s = dt / r0;
-  double c0, c1, c2, c3;
-  int status = 1;
-  for (int it = 0; it < 40; ++it) {
-    stumpff(beta * s * s, c0, c1, c2, c3);
-    const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
-    const double F = r0 * G1 + u * G2 + mu * G3 - dt;
-    const double Fp = r0 * c0 + u * G1 + mu * G2;
-    const double Fpp = (mu - beta * r0) * G1 + u * c0;
-    const double disc = fabs(16.0 * Fp * Fp - 20.0 * F * Fpp);
-    const double den = Fp + (Fp >= 0.0 ? 1.0 : -1.0) * sqrt(disc);
-    const double ds = -5.0 * F / den;
-    s += ds;
-    if (fabs(ds) <= 1e-15 * fabs(s)) {
-      status = 0;
-      break;
-    }
-  }
-  stumpff(beta * s * s, c0, c1, c2, c3);
-  const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
-  const double r = r0 * c0 + u * G1 + mu * G2;
-  const double f = 1.0 - mu * G2 / r0;
-  const double g = dt - mu * G3;
-  const double fd = -mu * G1 / (r0 * r);
-  const double gd = 1.0 - mu * G2 / r;
-  const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
-  const double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy, nvz = fd * z + gd * vz;
-  x = nx; y = ny; z = nz;
-  vx = nvx; vy = nvy; vz = nvz;
-  return status;
-}
 
 __global__ __launch_bounds__(kBlock) void k_momentum(const double4 *__restrict__ xm,
                                                      const double4 *__restrict__ v, int n,
