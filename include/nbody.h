@@ -128,6 +128,31 @@ int nbody_energy(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, c
                  double *out, void *stream);
 
 /*
+ * Batched ensembles: nsys independent systems, each a central mass m0 with its own bodies, all
+ * advanced by nsteps steps of nbody_step (thresholds from each system's initial state, binary64)
+ * in ONE persistent launch. System s occupies rows offs[s] .. offs[s+1]-1 of xm and v; offs is a
+ * HOST array of nsys+1 int64 with offs[0] = 0 and 1 <= offs[s+1]-offs[s] <= 2048. npairs
+ * (device uint64 [nsys], may be NULL) receives each system's number of close pairs at its final
+ * positions. Workgroups take systems largest first; the tile used for a system (one workgroup or
+ * one wave per system, one or two bodies per lane) comes from the context's table of size
+ * classes (N <= 64, 128, 256, 512, 1024, 2048). The call returns when the work is complete.
+ */
+int nbody_step_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, double *xm, double *v,
+                       int32_t nsteps, uint64_t *npairs, void *stream);
+
+/*
+ * Autotuner of the batched tiles: for every size class present in the ensemble, times nsteps
+ * steps of that class's systems (on scratch copies; xm and v are not modified) with each
+ * admissible tile and stores the fastest in the context. Tile codes: bit 0 = one wave per system,
+ * bit 1 = two bodies per lane. get/set read or replace the table (host array of 6 codes); get
+ * returns the number of classes.
+ */
+int nbody_autotune_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, const double *xm,
+                           const double *v, int32_t nsteps, void *stream);
+int nbody_get_batched_tiles(const nbody_ctx *ctx, int32_t *tiles, int32_t n);
+int nbody_set_batched_tiles(nbody_ctx *ctx, const int32_t *tiles, int32_t n);
+
+/*
  * Reverse-mode derivatives (vector-Jacobian products) with the thresholds thr held fixed, for
  * sensitivity analysis and orbit fitting. Adjoint arrays mirror the state layout:
  * lam_x [n][4] = dL/d{x, y, z, m} and lam_v [n][4] = dL/d{vx, vy, vz, pad}; the mass adjoint

@@ -65,6 +65,10 @@ EXPORTS = {
     "nbody_jump_vjp": [_I64, _P, _P, _D, _P, _P, _P],
     "nbody_drift_vjp": [_I64, _P, _P, _D, _P, _P, _P],
     "nbody_step_vjp": [_I64, _P, _P, _P, _I32, _P, _P, _P],
+    "nbody_step_batched": [_I32, _P, _P, _P, _I32, _P, _P],
+    "nbody_autotune_batched": [_I32, _P, _P, _P, _I32, _P],
+    "nbody_get_batched_tiles": [_P, _I32],
+    "nbody_set_batched_tiles": [_P, _I32],
 }
 OTHER_EXPORTS = ["nbody_create", "nbody_destroy", "nbody_set_params", "nbody_last_error",
                  "nbody_version"]
@@ -247,6 +251,42 @@ class Context:
             _body(t, nm)
         self._check(lib().nbody_step_vjp(self._h, xm0.shape[0], _ptr(xm0), _ptr(v0), _ptr(thr), int(nsteps),
                                          _ptr(lam_x), _ptr(lam_v), _stream()), "nbody_step_vjp")
+
+
+    # ------------------------------------------------------------ batched ensembles
+    @staticmethod
+    def _offs(offs):
+        import numpy as np
+        o = np.ascontiguousarray(offs, dtype=np.int64)
+        return o, o.ctypes.data
+
+    def step_batched(self, offs, xm, v, nsteps, count_pairs=False):
+        """Advances every system in place; offs is a host int64 sequence of length nsys + 1."""
+        _body(xm, "xm"); _body(v, "v")
+        o, op = self._offs(offs)
+        nsys = len(o) - 1
+        npairs = torch.zeros(nsys, dtype=torch.int64, device=xm.device) if count_pairs else None
+        self._check(lib().nbody_step_batched(self._h, nsys, op, _ptr(xm), _ptr(v), int(nsteps), _ptr(npairs),
+                                             _stream()), "nbody_step_batched")
+        return npairs
+
+    def autotune_batched(self, offs, xm, v, nsteps=3):
+        _body(xm, "xm"); _body(v, "v")
+        o, op = self._offs(offs)
+        self._check(lib().nbody_autotune_batched(self._h, len(o) - 1, op, _ptr(xm), _ptr(v), int(nsteps),
+                                                 _stream()), "nbody_autotune_batched")
+        return self.batched_tiles()
+
+    def batched_tiles(self):
+        t = (ctypes.c_int32 * 6)()
+        n = lib().nbody_get_batched_tiles(self._h, t, 6)
+        if n < 0:
+            raise NBodyError("nbody_get_batched_tiles failed")
+        return list(t)[:n]
+
+    def set_batched_tiles(self, tiles):
+        t = (ctypes.c_int32 * len(tiles))(*tiles)
+        self._check(lib().nbody_set_batched_tiles(self._h, t, len(tiles)), "nbody_set_batched_tiles")
 
 
 def version():

@@ -3,10 +3,13 @@
 // caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <numeric>
 #include <string>
+#include <vector>
 
 #include "../../include/nbody.h"
 #include "internal.hpp"
@@ -21,7 +24,8 @@ struct Buf {
 };
 
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
-             B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_NUM };
+             B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_B_OFFS, B_B_ORDER,
+             B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_T_OFFS, B_T_ORDER, B_NUM };
 
 }  // namespace
 
@@ -31,6 +35,13 @@ struct nbody_ctx {
   Buf buf[B_NUM];
   int R = 128;              // partner slots per (row, j-chunk) in the emission buffer
   int target_waves = 8192;  // pair-kernel waves to aim for (8 per SIMD on 256 CUs)
+  // batched tiles per size class (bit 0: wave tile, bit 1: two bodies per lane); -1 = untuned
+  int32_t tiles[nbk::kBuckets] = {1, 1, 1, 3, 2, 2};
+  bool tuned = false;
+  std::vector<int64_t> h_offs;   // host staging kept alive across asynchronous copies
+  std::vector<int32_t> h_order;
+  std::vector<int64_t> h_toffs;
+  std::vector<int32_t> h_torder;
 };
 
 namespace {
@@ -190,6 +201,72 @@ int one_step(nbody_ctx *c, int n, double4 *X, double4 *V, const double4 *thr, do
   HIPCHK(c, launch_pairs(a, true, false, false, p.precision == NBODY_PREC_SPLIT, st), "pairs");
   HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, n, p.G, h, 1, X, V, nullptr, nullptr, nullptr, st),
          "finalize");
+  return NBODY_OK;
+}
+
+// ------------------------------------------------------------------ batched ensembles
+int size_class_host(int64_t n) {
+  int b = 0;
+  while (b < kBuckets - 1 && n > (int64_t(64) << b)) ++b;
+  return b;
+}
+
+int check_offs(nbody_ctx *c, int32_t nsys, const int64_t *offs) {
+  if (nsys <= 0 || !offs) return fail(c, NBODY_E_INVAL, "nsys <= 0 or offs NULL");
+  if (offs[0] != 0) return fail(c, NBODY_E_INVAL, "offs[0] must be 0");
+  for (int32_t s = 0; s < nsys; ++s) {
+    const int64_t n = offs[s + 1] - offs[s];
+    if (n < 1 || n > batched_max_group_n())
+      return fail(c, NBODY_E_INVAL, "system %d has %lld bodies (1..%d supported)", s, (long long)n,
+                  batched_max_group_n());
+  }
+  return NBODY_OK;
+}
+
+int grid_size(nbody_ctx *c, int *grid) {
+  int dev = 0, per = 0;
+  hipDeviceProp_t prop;
+  HIPCHK(c, hipGetDevice(&dev), "device");
+  HIPCHK(c, hipGetDeviceProperties(&prop, dev), "device properties");
+  HIPCHK(c, batched_occupancy(&per), "occupancy");
+  if (per < 1) per = 1;
+  *grid = prop.multiProcessorCount * per;
+  return NBODY_OK;
+}
+
+// Launches the persistent kernel over systems `ids` (host) laid out by host offsets `offs`.
+int run_batched(nbody_ctx *c, int32_t nsys, std::vector<int64_t> &h_offs, std::vector<int32_t> &h_order,
+                BufId b_offs, BufId b_order, double4 *xm, double4 *v, int32_t nsteps, int forced,
+                unsigned long long *npairs, hipStream_t st) {
+  const int64_t total = h_offs[nsys];
+  int64_t *d_offs = (int64_t *)ensure(c, b_offs, (size_t)(nsys + 1) * sizeof(int64_t));
+  int32_t *d_order = (int32_t *)ensure(c, b_order, (size_t)nsys * sizeof(int32_t));
+  int32_t *d_cfg = (int32_t *)ensure(c, B_B_CFG, kBuckets * sizeof(int32_t));
+  double4 *d_thr = (double4 *)ensure(c, B_B_THR, (size_t)total * sizeof(double4));
+  unsigned *d_q = (unsigned *)ensure(c, B_B_QUEUE, 256);
+  if (!d_offs || !d_order || !d_cfg || !d_thr || !d_q)
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (batched)");
+  h_order.resize(nsys);
+  std::iota(h_order.begin(), h_order.end(), 0);
+  std::stable_sort(h_order.begin(), h_order.end(), [&](int32_t a, int32_t b) {
+    return h_offs[a + 1] - h_offs[a] > h_offs[b + 1] - h_offs[b];
+  });
+  HIPCHK(c, hipMemcpyAsync(d_offs, h_offs.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+  HIPCHK(c, hipMemcpyAsync(d_order, h_order.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+  HIPCHK(c, hipMemcpyAsync(d_cfg, c->tiles, kBuckets * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+  BatchLaunch b;
+  b.offs = d_offs; b.order = d_order; b.cfg = d_cfg; b.nsys = nsys; b.nsteps = nsteps; b.forced = forced;
+  TRY(grid_size(c, &b.grid));
+  b.xm = xm; b.v = v; b.thr = d_thr; b.npairs = npairs; b.queue = d_q;
+  const nbody_params &p = c->p;
+  b.G = p.G; b.m0 = p.m0; b.dt = p.dt; b.f_in = p.f_in;
+  b.cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
+  b.n2dt = p.n2 * p.dt;
+  b.cV = b.n2dt * b.n2dt;
+  b.n1 = p.n1;
+  HIPCHK(c, launch_batched(b, st), "batched launch");
+  // the host staging vectors must outlive the copies above
+  HIPCHK(c, hipStreamSynchronize(st), "batched sync");
   return NBODY_OK;
 }
 
@@ -446,6 +523,95 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
     TRY(jump_vjp(c, N, X1, V1, h, LX, LV, st));          // jump before the drift
     TRY(kick_vjp(c, N, Xs, T, LV, h, LX, st));           // first half kick at x_s
   }
+  return NBODY_OK;
+}
+
+int nbody_step_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, double *xm, double *v,
+                       int32_t nsteps, uint64_t *npairs, void *stream) {
+  if (!c) return NBODY_E_INVAL;
+  TRY(check_offs(c, nsys, offs));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, npairs, "npairs", false));
+  if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
+  if (c->p.precision != NBODY_PREC_F64) return fail(c, NBODY_E_INVAL, "batched ensembles run in binary64");
+  c->h_offs.assign(offs, offs + nsys + 1);
+  return run_batched(c, nsys, c->h_offs, c->h_order, B_B_OFFS, B_B_ORDER, (double4 *)xm, (double4 *)v,
+                     nsteps, -1, (unsigned long long *)npairs, (hipStream_t)stream);
+}
+
+int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, const double *xm,
+                           const double *v, int32_t nsteps, void *stream) {
+  if (!c) return NBODY_E_INVAL;
+  TRY(check_offs(c, nsys, offs));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  if (nsteps < 1) return fail(c, NBODY_E_INVAL, "nsteps < 1");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0), "event");
+  HIPCHK(c, hipEventCreate(&e1), "event");
+  int rc = NBODY_OK;
+  for (int b = 0; b < kBuckets && rc == NBODY_OK; ++b) {
+    // the systems of this size class, gathered into a scratch ensemble
+    std::vector<int32_t> ids;
+    for (int32_t s = 0; s < nsys; ++s)
+      if (size_class_host(offs[s + 1] - offs[s]) == b) ids.push_back(s);
+    if (ids.empty()) continue;
+    c->h_toffs.assign(ids.size() + 1, 0);
+    for (size_t k = 0; k < ids.size(); ++k) c->h_toffs[k + 1] = c->h_toffs[k] + offs[ids[k] + 1] - offs[ids[k]];
+    const int64_t tot = c->h_toffs.back();
+    double4 *txm = (double4 *)ensure(c, B_T_XM, (size_t)tot * sizeof(double4));
+    double4 *tv = (double4 *)ensure(c, B_T_V, (size_t)tot * sizeof(double4));
+    if (!txm || !tv) { rc = fail(c, NBODY_E_NOMEM, "workspace allocation failed (autotune)"); break; }
+    const int64_t nmax = int64_t(64) << b;
+    double best = 1e300;
+    int best_code = c->tiles[b];
+    for (int code = 0; code < 4 && rc == NBODY_OK; ++code) {
+      if ((code & 1) && nmax > batched_max_wave_n()) continue;
+      for (int rep = 0; rep < 2 && rc == NBODY_OK; ++rep) {   // rep 0 warms up
+        for (size_t k = 0; k < ids.size(); ++k) {
+          const size_t nb = (size_t)(offs[ids[k] + 1] - offs[ids[k]]) * sizeof(double4);
+          hipError_t e = hipMemcpyAsync(txm + c->h_toffs[k], (const double4 *)xm + offs[ids[k]], nb,
+                                        hipMemcpyDeviceToDevice, st);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(tv + c->h_toffs[k], (const double4 *)v + offs[ids[k]], nb,
+                               hipMemcpyDeviceToDevice, st);
+          if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
+        }
+        if (rc != NBODY_OK) break;
+        hipError_t e = hipEventRecord(e0, st);
+        if (e != hipSuccess) { rc = hip_fail(c, e, "event"); break; }
+        rc = run_batched(c, (int32_t)ids.size(), c->h_toffs, c->h_torder, B_T_OFFS, B_T_ORDER, txm, tv, nsteps,
+                         code, nullptr, st);
+        if (rc != NBODY_OK) break;
+        float ms = 0.f;
+        e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { rc = hip_fail(c, e, "autotune timing"); break; }
+        if (rep == 1 && ms < best) { best = ms; best_code = code; }
+      }
+    }
+    c->tiles[b] = best_code;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == NBODY_OK) c->tuned = true;
+  return rc;
+}
+
+int nbody_get_batched_tiles(const nbody_ctx *c, int32_t *tiles, int32_t n) {
+  if (!c || !tiles || n < kBuckets) return NBODY_E_INVAL;
+  for (int b = 0; b < kBuckets; ++b) tiles[b] = c->tiles[b];
+  return kBuckets;
+}
+
+int nbody_set_batched_tiles(nbody_ctx *c, const int32_t *tiles, int32_t n) {
+  if (!c || !tiles || n != kBuckets) return NBODY_E_INVAL;
+  for (int b = 0; b < kBuckets; ++b)
+    if (tiles[b] < 0 || tiles[b] > 3) return fail(c, NBODY_E_INVAL, "tile code %d out of range", tiles[b]);
+  for (int b = 0; b < kBuckets; ++b) c->tiles[b] = tiles[b];
   return NBODY_OK;
 }
 

@@ -54,6 +54,23 @@ hipError_t launch_jump_vjp(const double4 *xm, const double4 *v, double h, double
 hipError_t launch_drift_vjp(const double4 *xm, const double4 *v, int n, double dt, double mu,
                             double4 *lam_x, double4 *lam_v, hipStream_t st);
 
+// batched.hip
+constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048
+struct BatchLaunch {
+  const int64_t *offs;
+  const int32_t *order;
+  const int32_t *cfg;
+  int nsys, nsteps, forced, grid;
+  double4 *xm, *v, *thr;
+  unsigned long long *npairs;
+  unsigned *queue;
+  double G, m0, dt, f_in, cH, cV, n1, n2dt;
+};
+hipError_t launch_batched(const BatchLaunch &b, hipStream_t st);
+hipError_t batched_occupancy(int *blocks_per_cu);
+int batched_max_group_n();
+int batched_max_wave_n();
+
 inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace nbk
@@ -72,6 +89,23 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     v = v > w ? v : w;
   }
   return v;
+}
+
+// Critical radius and thresholds of one body (the library's definition, see nbody.h):
+// {rc, H, V, T}, T bounding every r^2 that H or V can flag.
+__device__ __forceinline__ double4 body_thresholds(double4 p, double4 q, double m0, double cH,
+                                                   double cV, double n1, double n2dt) {
+  const double r2 = fma(p.z, p.z, fma(p.y, p.y, p.x * p.x));
+  const double mu = p.w / m0;
+  const double vv = fma(q.z, q.z, fma(q.y, q.y, q.x * q.x));
+  const double H = (cH * ((r2 * r2) * r2)) * (mu * mu);
+  const double V = cV * vv;
+  const double rhill = sqrt(r2) * cbrt(mu / 3.0);
+  const double a = n1 * rhill, b = n2dt * sqrt(vv);
+  const double rc = a > b ? a : b;
+  const double c = cbrt(H);
+  const double T = (V > c ? V : c) * (1.0 + 0x1p-30);
+  return make_double4(rc, H, V, T);
 }
 
 // Exact binary64 close-encounter predicate (the library's definition, see nbody.h).

@@ -18,20 +18,7 @@ __global__ __launch_bounds__(kBlock) void k_rcrit(const double4 *__restrict__ xm
                                                   double cH, double cV, double n1, double n2dt) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const double4 p = xm[i];
-  const double4 q = v[i];
-  const double r2 = fma(p.z, p.z, fma(p.y, p.y, p.x * p.x));
-  const double mu = p.w / m0;
-  const double vv = fma(q.z, q.z, fma(q.y, q.y, q.x * q.x));
-  const double H = (cH * ((r2 * r2) * r2)) * (mu * mu);
-  const double V = cV * vv;
-  const double rhill = sqrt(r2) * cbrt(mu / 3.0);
-  const double a = n1 * rhill, b = n2dt * sqrt(vv);
-  const double rc = a > b ? a : b;
-  // Every r^2 that these thresholds flag lies below max(V, cbrt(H)) up to a few roundings.
-  const double c = cbrt(H);
-  const double T = (V > c ? V : c) * (1.0 + 0x1p-30);
-  thr[i] = make_double4(rc, H, V, T);
+  thr[i] = body_thresholds(xm[i], v[i], m0, cH, cV, n1, n2dt);
 }
 
 hipError_t launch_rcrit(const double4 *xm, const double4 *v, double4 *thr, int n, double m0,

@@ -1,0 +1,112 @@
+"""GPU parity of the batched-ensemble launch: every system of an uneven ensemble must match its
+own single-system run (1e-12 relative on the state after the steps; identical j-order, only the
+momentum reductions differ) and the CPU oracle, for every tile; close-pair counts must equal the
+oracle's list length at the oracle's final state."""
+import numpy as np
+import pytest
+
+import diskgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+SIZES = [1, 2, 3, 40, 63, 64, 65, 127, 200, 300, 511, 512, 513, 700, 1024, 1500, 2048, 2]
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2604_09184_amd as nb
+    nb.lib()
+    return nb
+
+
+def ensemble(sizes, seed=77):
+    ss = np.random.SeedSequence(seed).spawn(len(sizes))
+    parts = [diskgen.make_disk(diskgen.Disk(n, 0.5, 4.0, 0.01, 0.005, 2.0, seed=ss[k])) for k, n in enumerate(sizes)]
+    offs = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    x = np.concatenate([p["x"] for p in parts]); v = np.concatenate([p["v"] for p in parts])
+    m = np.concatenate([p["m"] for p in parts])
+    return offs, x, v, m
+
+
+def to_dev(x, v, m):
+    xm, v4 = diskgen.pack4(x, v, m)
+    return torch.tensor(xm, device=DEV), torch.tensor(v4, device=DEV)
+
+
+def rel_state_err(a, b):
+    return (np.abs(a - b).max(1) / np.linalg.norm(b, axis=1)).max()
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_batched_matches_single_system_runs(nb, tile):
+    say(f"batched tile={tile} sizes={SIZES}")
+    p = diskgen.PARAMS
+    ctx = nb.Context(nb.Params(**p))
+    ctx.set_batched_tiles([tile] * 6)
+    offs, x, v, m = ensemble(SIZES)
+    X, V = to_dev(x, v, m)
+    k = 6
+    npairs = ctx.step_batched(offs, X, V, k, count_pairs=True).cpu().numpy()
+    Xb, Vb = X.cpu().numpy(), V.cpu().numpy()
+    for s in range(len(SIZES)):
+        a, b = offs[s], offs[s + 1]
+        Xs, Vs = to_dev(x[a:b], v[a:b], m[a:b])
+        ctx.step(Xs, Vs, k)
+        assert rel_state_err(Xb[a:b, :3], Xs.cpu().numpy()[:, :3]) < 1e-12, s
+        assert rel_state_err(Vb[a:b, :3], Vs.cpu().numpy()[:, :3]) < 1e-12, s
+        np.testing.assert_array_equal(Xb[a:b, 3], m[a:b])
+    # oracle on a few systems (small, medium, the largest)
+    for s in (2, 9, 16):
+        a, b = offs[s], offs[s + 1]
+        othr = oracle.thresholds(x[a:b], v[a:b], m[a:b], p)
+        ox, ov, _ = oracle.step(x[a:b], v[a:b], m[a:b], p, k, thr=othr)
+        assert rel_state_err(Xb[a:b, :3], ox) < 1e-11
+        assert rel_state_err(Vb[a:b, :3], ov) < 1e-11
+        assert npairs[s] == len(oracle.encounters(ox, othr))
+
+
+def test_batched_independent_of_system_order(nb):
+    say("batched order invariance")
+    ctx = nb.Context(nb.Params(**diskgen.PARAMS))
+    offs, x, v, m = ensemble(SIZES, seed=5)
+    X, V = to_dev(x, v, m)
+    ctx.step_batched(offs, X, V, 4)
+    perm = np.random.default_rng(1).permutation(len(SIZES))
+    sizes_p = [SIZES[s] for s in perm]
+    offs_p = np.zeros(len(perm) + 1, dtype=np.int64); offs_p[1:] = np.cumsum(sizes_p)
+    idx = np.concatenate([np.arange(offs[s], offs[s + 1]) for s in perm])
+    Xp, Vp = to_dev(x[idx], v[idx], m[idx])
+    ctx.step_batched(offs_p, Xp, Vp, 4)
+    assert torch.equal(Xp, X[torch.tensor(idx, device=DEV)])
+    assert torch.equal(Vp, V[torch.tensor(idx, device=DEV)])
+
+
+def test_autotune_and_rejections(nb):
+    say("batched autotune")
+    ctx = nb.Context(nb.Params(**diskgen.PARAMS))
+    offs, x, v, m = ensemble([64] * 30 + [300] * 20 + [1500] * 6, seed=9)
+    X, V = to_dev(x, v, m)
+    X0, V0 = X.clone(), V.clone()
+    tiles = ctx.autotune_batched(offs, X, V, nsteps=2)
+    assert len(tiles) == 6 and all(0 <= t <= 3 for t in tiles)
+    assert torch.equal(X, X0) and torch.equal(V, V0)          # tuning works on copies
+    ctx.step_batched(offs, X, V, 3)
+    ref = nb.Context(nb.Params(**diskgen.PARAMS))
+    Xr, Vr = X0.clone(), V0.clone()
+    ref.set_batched_tiles([2] * 6)
+    ref.step_batched(offs, Xr, Vr, 3)
+    assert (X - Xr).abs().max().item() < 1e-12 * 4
+    with pytest.raises(nb.NBodyError):
+        ctx.step_batched(np.array([0, 3000]), torch.zeros((3000, 4), dtype=torch.float64, device=DEV),
+                         torch.zeros((3000, 4), dtype=torch.float64, device=DEV), 1)
+    with pytest.raises(nb.NBodyError):
+        ctx.step_batched(np.array([1, 5]), X, V, 1)
