@@ -24,9 +24,129 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# HBM bytes per launch of the binary64 pair kernel from the FETCH_SIZE / WRITE_SIZE passes
+# (calibrated with a plain copy; see profiles/k_pairs_disk32768.md), valid for the kernel source
+# whose hash is stored beside it.
+PAIR_KERNEL_TRAFFIC = {"bytes": 48435196, "source_sha256": "c98142df27b5929c399ebc58ab245ed0b7bc43d292007f0bb1eab204ab61e724"}
+PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/kick.hip", "paper_2604_09184_amd/csrc/internal.hpp"]
+
 FLOP_PER_PAIR = 20                 # N-body convention: 3 sub, 5 for r^2, rsqrt, 3 for m r^-3, 6 accumulate, 2 slack
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 128 flop/clk x 2.4 GHz
 METRIC = "pair interactions/s & % FP64 peak: plain vs split-prec/batched/adjoint"
+
+
+def pair_kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PAIR_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    t = PAIR_KERNEL_TRAFFIC
+    return t["bytes"] if t["source_sha256"] == pair_kernel_sha() else None
+
+
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    s = torch.cuda.current_stream()
+    e0.record(s)
+    r = fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, r
+
+
+def variant_split(nb, p):
+    """Split-precision kick on the 131072-body narrow ring, 100 steps, against binary64."""
+    import numpy as np
+    import torch
+
+    import diskgen
+    d = diskgen.workload("ring131072")
+    n = len(d["m"])
+    xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+    out = {"workload": "ring131072", "n": n, "steps": 100}
+    res = {}
+    for name, prec in (("f64", nb.PREC_F64), ("split", nb.PREC_SPLIT)):
+        ctx = nb.Context(nb.Params(**p, precision=prec))
+        X = torch.tensor(xm, device="cuda:0")
+        V = torch.tensor(v4, device="cuda:0")
+        thr = ctx.rcrit(X, V)
+        acc = ctx.accelerations(X, thr)
+        ctx.step(X, V, 2, thr=thr)                      # warm-up on a copy of the path
+        X = torch.tensor(xm, device="cuda:0")
+        V = torch.tensor(v4, device="cuda:0")
+        sec, _ = timed(lambda: ctx.step(X, V, 100, thr=thr))
+        kms = ctx.bench_pairs(X, thr, reps=3)
+        res[name] = (sec, acc, X, V, kms)
+        out[f"{name}_pairs_per_s"] = 101 * n * (n - 1) / sec
+        out[f"{name}_kernel_ms"] = round(kms, 3)
+    a64, a32 = res["f64"][1][:, :3], res["split"][1][:, :3]
+    rel = ((a32 - a64).norm(dim=1) / a64.norm(dim=1)).cpu().numpy()
+    out["speedup_vs_f64"] = round(res["f64"][0] / res["split"][0], 3)
+    out["acc_rel_err_vs_f64"] = {"max": float(rel.max()), "median": float(np.median(rel)),
+                                 "p99": float(np.quantile(rel, 0.99))}
+    dx = (res["split"][2][:, :3] - res["f64"][2][:, :3]).norm(dim=1) / res["f64"][2][:, :3].norm(dim=1)
+    out["state_rel_err_after_100_steps"] = {"max": float(dx.max()), "median": float(dx.median())}
+    return out
+
+
+def variant_batched(nb, p):
+    """4096 independent disks, N log-uniform in 64..2048, 100 steps in one persistent launch."""
+    import torch
+
+    import diskgen
+    offs, x, v, m = diskgen.ensemble()
+    xm, v4 = diskgen.pack4(x, v, m)
+    X = torch.tensor(xm, device="cuda:0")
+    V = torch.tensor(v4, device="cuda:0")
+    ctx = nb.Context(nb.Params(**p))
+    t_tune, tiles = timed(lambda: ctx.autotune_batched(offs, X, V, nsteps=2))
+    sec, _ = timed(lambda: ctx.step_batched(offs, X, V, 100))
+    sizes = offs[1:] - offs[:-1]
+    pairs = 101 * float((sizes * (sizes - 1)).sum())
+    return {"workload": "ensemble4096", "systems": len(sizes), "bodies": int(offs[-1]), "steps": 100,
+            "pairs_per_s": pairs / sec, "seconds": round(sec, 4), "tiles": tiles,
+            "autotune_seconds": round(t_tune, 3)}
+
+
+def variant_adjoint(nb, p):
+    """Gradient of |x(T) - target|^2 after 100 steps of the 8192-body disk, checkpoint every 10."""
+    import torch
+
+    import diskgen
+    from paper_2604_09184_amd.autograd import trajectory
+    d = diskgen.workload("adjoint8192")
+    n = len(d["m"])
+    xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+    ctx = nb.Context(nb.Params(**p))
+    X0 = torch.tensor(xm, device="cuda:0")
+    V0 = torch.tensor(v4, device="cuda:0")
+    thr = ctx.rcrit(X0, V0)
+    target = None
+    res = {}
+    for rep in range(2):
+        X = X0.clone().requires_grad_(True)
+        V = V0.clone().requires_grad_(True)
+        fsec, (xT, vT) = timed(lambda: trajectory(ctx, X, V, 100, every=10, thr=thr))
+        if target is None:
+            target = (xT[:, :3] + 1e-4).detach()
+        loss = ((xT[:, :3] - target) ** 2).sum()
+        bsec, _ = timed(lambda: loss.backward())
+        res = {"forward_s": fsec, "backward_s": bsec}
+    # pair evaluations in the backward: per step one recomputed step (2 kicks) plus two kick
+    # VJPs, plus the in-segment replay of the checkpointed states (9 of every 10 steps, 2 kicks)
+    evals = 100 * 2 + 100 * 2 + 90 * 2
+    return {"workload": "adjoint8192", "n": n, "steps": 100, "checkpoint_every": 10,
+            "forward_s": round(res["forward_s"], 4), "backward_s": round(res["backward_s"], 4),
+            "backward_over_forward": round(res["backward_s"] / res["forward_s"], 2),
+            "forward_pairs_per_s": 101 * n * (n - 1) / res["forward_s"],
+            "backward_pair_evals_per_s": evals * n * (n - 1) / res["backward_s"]}
 
 
 def cpu_baseline(budget_s=25.0):
@@ -118,18 +238,18 @@ def main():
     achieved = FLOP_PER_PAIR * n * (n - 1) / (kernel_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": "k_pairs (binary64)",
+                "traffic": traffic_bytes(), "kernel": "k_pairs (binary64)",
                 "kernel_ms": round(kernel_ms, 4),
                 "pairs_per_s_kernel": n * (n - 1) / (kernel_ms / 1e3)}
 
     variants = {}
     if not args.no_variants:
-        print("[bench] variants", file=sys.stderr, flush=True)
-        ctx_s = nb.Context(nb.Params(**p, precision=nb.PREC_SPLIT))
-        ms_s = ctx_s.bench_pairs(X, thr, reps=20)
-        variants["split_precision_kick"] = {"pairs_per_s": n * (n - 1) / (ms_s / 1e3),
-                                            "kernel_ms": round(ms_s, 4),
-                                            "speedup_vs_f64": round(kernel_ms / ms_s, 3)}
+        print("[bench] variant: split precision (ring131072)", file=sys.stderr, flush=True)
+        variants["split_precision"] = variant_split(nb, p)
+        print("[bench] variant: batched (ensemble4096)", file=sys.stderr, flush=True)
+        variants["batched"] = variant_batched(nb, p)
+        print("[bench] variant: adjoint (adjoint8192)", file=sys.stderr, flush=True)
+        variants["adjoint"] = variant_adjoint(nb, p)
 
     out = {
         "metric": METRIC,
