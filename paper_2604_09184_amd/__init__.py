@@ -71,7 +71,7 @@ EXPORTS = {
     "nbody_set_batched_tiles": [_P, _I32],
 }
 OTHER_EXPORTS = ["nbody_create", "nbody_destroy", "nbody_set_params", "nbody_last_error",
-                 "nbody_version"]
+                 "nbody_version", "nbody_tune"]
 
 _lib = None
 
@@ -91,6 +91,8 @@ def lib():
     L.nbody_last_error.restype = ctypes.c_char_p
     L.nbody_last_error.argtypes = [_P]
     L.nbody_version.restype = ctypes.c_char_p
+    L.nbody_tune.restype = ctypes.c_int
+    L.nbody_tune.argtypes = [_P, ctypes.c_char_p, _I64]
     for name, args in EXPORTS.items():
         f = getattr(L, name)
         f.restype = ctypes.c_int
@@ -140,6 +142,10 @@ class Context:
     def set_params(self, params: Params):
         self.params = params
         self._check(lib().nbody_set_params(self._h, ctypes.byref(params.c())), "nbody_set_params")
+
+    def tune(self, name, value):
+        """Launch-shape knobs: locality_min_n, locality_every, emit_slots, target_waves."""
+        self._check(lib().nbody_tune(self._h, name.encode(), int(value)), "nbody_tune")
 
     def _check(self, rc, name):
         if rc != 0:

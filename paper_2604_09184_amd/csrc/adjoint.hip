@@ -19,14 +19,18 @@ using namespace nbd;
 
 // ------------------------------------------------------------------ kick VJP pair kernel
 // One body k per lane, wave-uniform j-bodies (x, m) and their lam_a through scalar loads.
+// perm (may be null) maps lanes to bodies; as in the forward pair kernel it changes no result.
 __global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__ xm,
                                                      const double4 *__restrict__ thr,
+                                                     const int *__restrict__ perm,
                                                      const double4 *__restrict__ lam_a, int n,
                                                      int chunk, double f_in,
                                                      double4 *__restrict__ part) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
+  const int lane_body = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = lane_body < n;
+  const int lb = valid ? lane_body : n - 1;
+  const int ii = perm ? perm[lb] : lb;
+  const int i = ii;
   const double4 pk = xm[ii];
   const double4 lk = lam_a[ii];
   const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
@@ -115,12 +119,12 @@ __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restri
   lam_x[i] = l;
 }
 
-hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const double4 *lam_v, double h,
-                           double G, double f_in, int n, int S, int chunk, double4 *lam_a,
+hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double4 *lam_v,
+                           double h, double G, double f_in, int n, int S, int chunk, double4 *lam_a,
                            double4 *part, double4 *lam_x, hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(nblocks(n)), dim3(kBlock), 0, st, lam_v, h, n, lam_a);
-  hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, lam_a, n, chunk,
-                     f_in, part);
+  hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, perm, lam_a, n,
+                     chunk, f_in, part);
   hipLaunchKernelGGL(k_vjp_finalize, dim3(nblocks(n)), dim3(kBlock), 0, st, part, S, n, G, lam_x);
   return hipGetLastError();
 }

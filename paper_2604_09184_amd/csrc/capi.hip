@@ -25,7 +25,8 @@ struct Buf {
 
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_B_OFFS, B_B_ORDER,
-             B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_T_OFFS, B_T_ORDER, B_NUM };
+             B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_T_OFFS, B_T_ORDER, B_PERM, B_CELL,
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_NUM };
 
 }  // namespace
 
@@ -34,6 +35,8 @@ struct nbody_ctx {
   std::string err;
   Buf buf[B_NUM];
   int R = 128;              // partner slots per (row, j-chunk) in the emission buffer
+  int locality_min_n = 4096;  // lane permutation by position for n at least this
+  int locality_every = 10;    // steps between refreshes of the lane permutation in nbody_step
   int target_waves = 8192;  // pair-kernel waves to aim for (8 per SIMD on 256 CUs)
   // batched tiles per size class (bit 0: wave tile, bit 1: two bodies per lane); -1 = untuned
   int32_t tiles[nbk::kBuckets] = {1, 1, 1, 3, 2, 2};
@@ -128,9 +131,29 @@ void plan(const nbody_ctx *c, int n, int &S, int &chunk) {
   S = (n + chunk - 1) / chunk;
 }
 
+// Lane permutation grouping spatially close bodies into waves (no effect on any result bit);
+// null below the size where it pays.
+int locality(nbody_ctx *c, int n, const double4 *xm, hipStream_t st, const int **perm) {
+  *perm = nullptr;
+  if (n < c->locality_min_n) return NBODY_OK;
+  const int nb = nblocks(n);
+  int *p = (int *)ensure(c, B_PERM, (size_t)n * sizeof(int));
+  unsigned short *cell = (unsigned short *)ensure(c, B_CELL, (size_t)n * sizeof(unsigned short));
+  float2 *range = (float2 *)ensure(c, B_RANGE, (size_t)nb * sizeof(float2));
+  const bool fresh = c->buf[B_CCOUNT].p == nullptr;
+  unsigned *count = (unsigned *)ensure(c, B_CCOUNT, (size_t)locality_cells() * sizeof(unsigned));
+  unsigned *cursor = (unsigned *)ensure(c, B_CCURSOR, (size_t)locality_cells() * sizeof(unsigned));
+  if (!p || !cell || !range || !count || !cursor) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (locality)");
+  if (fresh) HIPCHK(c, hipMemsetAsync(count, 0, (size_t)locality_cells() * sizeof(unsigned), st), "memset");
+  HIPCHK(c, launch_locality(xm, n, range, cell, count, cursor, p, st), "locality");
+  *perm = p;
+  return NBODY_OK;
+}
+
 int make_kick_args(nbody_ctx *c, int n, const double *xm, const double *thr, bool need_force,
                    bool need_ce, bool need_emit, KickArgs &a) {
   plan(c, n, a.nchunk, a.chunk);
+  a.perm = nullptr;
   a.xm = reinterpret_cast<const double4 *>(xm);
   a.thr = reinterpret_cast<const double4 *>(thr);
   a.n = n;
@@ -163,8 +186,9 @@ int kick_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *thr, const d
   TRY(make_kick_args(c, n, (const double *)xm, (const double *)thr, true, false, false, a));
   double4 *la = (double4 *)ensure(c, B_LAMA, (size_t)n * sizeof(double4));
   if (!la) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint)");
-  HIPCHK(c, launch_kick_vjp(xm, thr, lam_v, h, c->p.G, c->p.f_in, n, a.nchunk, a.chunk, la, a.part, lam_x, st),
-         "kick vjp");
+  TRY(locality(c, n, xm, st, &a.perm));
+  HIPCHK(c, launch_kick_vjp(xm, thr, a.perm, lam_v, h, c->p.G, c->p.f_in, n, a.nchunk, a.chunk, la, a.part,
+                            lam_x, st), "kick vjp");
   return NBODY_OK;
 }
 
@@ -173,34 +197,6 @@ int jump_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *v, double h,
   double4 *parts = (double4 *)ensure(c, B_LSUM, (size_t)nblocks(n) * sizeof(double4));
   if (!parts) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint)");
   HIPCHK(c, launch_jump_vjp(xm, v, h, c->p.m0, n, parts, lam_x, lam_v, st), "jump vjp");
-  return NBODY_OK;
-}
-
-// One step B C A C B of (X, V) in place with unmerged kicks; optionally keeps the velocity after
-// the first kick (V1), the position before the drift (X1) and the velocity after the drift (V2).
-int one_step(nbody_ctx *c, int n, double4 *X, double4 *V, const double4 *thr, double4 *X1, double4 *V1,
-             double4 *V2, hipStream_t st) {
-  const nbody_params &p = c->p;
-  const double h = 0.5 * p.dt;
-  const int nb = nblocks(n);
-  const size_t bytes = (size_t)n * sizeof(double4);
-  double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
-  if (!mom) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
-  KickArgs a;
-  TRY(make_kick_args(c, n, (const double *)X, (const double *)thr, true, false, false, a));
-  HIPCHK(c, launch_pairs(a, true, false, false, p.precision == NBODY_PREC_SPLIT, st), "pairs");
-  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, n, p.G, h, 1, X, V, nullptr, nullptr, mom, st),
-         "finalize");
-  if (V1) HIPCHK(c, hipMemcpyAsync(V1, V, bytes, hipMemcpyDeviceToDevice, st), "copy");
-  HIPCHK(c, launch_jump(X, mom, nb, n, h, p.m0, st), "jump");
-  if (X1) HIPCHK(c, hipMemcpyAsync(X1, X, bytes, hipMemcpyDeviceToDevice, st), "copy");
-  HIPCHK(c, launch_drift(X, V, n, p.dt, p.G * p.m0, nullptr, st), "drift");
-  if (V2) HIPCHK(c, hipMemcpyAsync(V2, V, bytes, hipMemcpyDeviceToDevice, st), "copy");
-  HIPCHK(c, launch_momentum(X, V, n, mom, st), "momentum");
-  HIPCHK(c, launch_jump(X, mom, nb, n, h, p.m0, st), "jump");
-  HIPCHK(c, launch_pairs(a, true, false, false, p.precision == NBODY_PREC_SPLIT, st), "pairs");
-  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, n, p.G, h, 1, X, V, nullptr, nullptr, nullptr, st),
-         "finalize");
   return NBODY_OK;
 }
 
@@ -331,6 +327,7 @@ int nbody_kick(nbody_ctx *c, int64_t n, const double *xm, const double *thr, dou
   KickArgs a;
   TRY(make_kick_args(c, (int)n, xm, thr, true, acc_ce != nullptr, false, a));
   hipStream_t st = (hipStream_t)stream;
+  TRY(locality(c, (int)n, a.xm, st, &a.perm));
   HIPCHK(c, launch_pairs(a, true, false, acc_ce != nullptr, c->p.precision == NBODY_PREC_SPLIT, st),
          "kick pairs");
   HIPCHK(c, launch_finalize(a.part, a.part_ce, a.nchunk, (int)n, c->p.G, h, 1, a.xm, (double4 *)v,
@@ -349,6 +346,7 @@ int nbody_encounters(nbody_ctx *c, int64_t n, const double *xm, const double *th
   KickArgs a;
   TRY(make_kick_args(c, (int)n, xm, thr, false, false, true, a));
   hipStream_t st = (hipStream_t)stream;
+  TRY(locality(c, (int)n, a.xm, st, &a.perm));
   HIPCHK(c, launch_pairs(a, false, true, false, false, st), "encounter pairs");
   return emit_list(c, a, pairs, cap, count, st);
 }
@@ -410,6 +408,7 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
   const double mu = p.G * p.m0;
   double4 *X = (double4 *)xm;
   double4 *Vv = (double4 *)v;
+  TRY(locality(c, N, X, st, &a.perm));
   if (nsteps == 0) {
     if (emit) {
       HIPCHK(c, launch_pairs(a, false, true, false, false, st), "step pairs");
@@ -423,6 +422,7 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
   for (int s = 1; s <= nsteps; ++s) {
     HIPCHK(c, launch_jump_drift(X, Vv, momA, nb, N, h, p.dt, p.m0, mu, nullptr, momB, st), "jump+drift");
     HIPCHK(c, launch_jump(X, momB, nb, N, h, p.m0, st), "jump");
+    if (a.perm && s % c->locality_every == 0) TRY(locality(c, N, X, st, &a.perm));
     const bool last = s == nsteps;
     HIPCHK(c, launch_pairs(a, true, last && emit, false, split, st), "step pairs");
     HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, last ? 1 : 2, X, Vv, nullptr,
@@ -492,36 +492,57 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
   if (nsteps == 0) return NBODY_OK;
   hipStream_t st = (hipStream_t)stream;
+  const nbody_params &p = c->p;
   const int N = (int)n;
+  const int nb = nblocks(n);
   const size_t bytes = (size_t)n * sizeof(double4);
-  double4 *S = (double4 *)ensure(c, B_ADJ_STATES, 2 * bytes * (size_t)nsteps);
+  // per step s: X_s (positions at its start), X1_s (before the drift), V1_s (after the first
+  // half kick), V2_s (after the drift); plus the final positions
+  double4 *S = (double4 *)ensure(c, B_ADJ_STATES, bytes * (4 * (size_t)nsteps + 1));
   double4 *XA = (double4 *)ensure(c, B_XA, bytes);
   double4 *VA = (double4 *)ensure(c, B_VA, bytes);
-  double4 *X1 = (double4 *)ensure(c, B_X1, bytes);
-  double4 *V1 = (double4 *)ensure(c, B_V1, bytes);
-  double4 *V2 = (double4 *)ensure(c, B_V2, bytes);
-  if (!S || !XA || !VA || !X1 || !V1 || !V2) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint states)");
+  double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
+  if (!S || !XA || !VA || !mom) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint states)");
+  auto Xs = [&](int s) { return S + (size_t)4 * s * N; };
+  auto X1 = [&](int s) { return S + ((size_t)4 * s + 1) * N; };
+  auto V1 = [&](int s) { return S + ((size_t)4 * s + 2) * N; };
+  auto V2 = [&](int s) { return S + ((size_t)4 * s + 3) * N; };
+  double4 *Xend = S + (size_t)4 * nsteps * N;
   const double4 *T = (const double4 *)thr;
-  const double h = 0.5 * c->p.dt;
-  // states at the start of every step of the segment
-  HIPCHK(c, hipMemcpyAsync(S, xm0, bytes, hipMemcpyDeviceToDevice, st), "copy");
-  HIPCHK(c, hipMemcpyAsync(S + N, v0, bytes, hipMemcpyDeviceToDevice, st), "copy");
-  for (int s = 0; s + 1 < nsteps; ++s) {
-    double4 *Xs = S + (size_t)2 * s * N, *Xn = S + (size_t)2 * (s + 1) * N;
-    HIPCHK(c, hipMemcpyAsync(Xn, Xs, 2 * bytes, hipMemcpyDeviceToDevice, st), "copy");
-    TRY(one_step(c, N, Xn, Xn + N, T, nullptr, nullptr, nullptr, st));
+  const double h = 0.5 * p.dt;
+  const bool split = p.precision == NBODY_PREC_SPLIT;
+  // replay of the segment with the forward's kernel sequence (merged half kicks), recording
+  HIPCHK(c, hipMemcpyAsync(XA, xm0, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  HIPCHK(c, hipMemcpyAsync(VA, v0, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  KickArgs a;
+  TRY(make_kick_args(c, N, (const double *)XA, thr, true, false, false, a));
+  TRY(locality(c, N, XA, st, &a.perm));
+  HIPCHK(c, launch_pairs(a, true, false, false, split, st), "pairs");
+  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, XA, VA, nullptr, nullptr, mom, st), "finalize");
+  for (int s = 0; s < nsteps; ++s) {
+    if (s == 0) HIPCHK(c, hipMemcpyAsync(Xs(0), XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    HIPCHK(c, hipMemcpyAsync(V1(s), VA, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    HIPCHK(c, launch_jump(XA, mom, nb, N, h, p.m0, st), "jump");
+    HIPCHK(c, hipMemcpyAsync(X1(s), XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    HIPCHK(c, launch_drift(XA, VA, N, p.dt, p.G * p.m0, nullptr, st), "drift");
+    HIPCHK(c, hipMemcpyAsync(V2(s), VA, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    HIPCHK(c, launch_momentum(XA, VA, N, mom, st), "momentum");
+    HIPCHK(c, launch_jump(XA, mom, nb, N, h, p.m0, st), "jump");
+    HIPCHK(c, hipMemcpyAsync(s + 1 < nsteps ? Xs(s + 1) : Xend, XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    if (s + 1 < nsteps) {
+      HIPCHK(c, launch_pairs(a, true, false, false, split, st), "pairs");
+      HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 2, XA, VA, nullptr, nullptr, mom, st),
+             "finalize");
+    }
   }
+  // reverse sweep: B2^T C2^T A^T C1^T B1^T per step
   double4 *LX = (double4 *)lam_x, *LV = (double4 *)lam_v;
   for (int s = nsteps - 1; s >= 0; --s) {
-    const double4 *Xs = S + (size_t)2 * s * N;
-    HIPCHK(c, hipMemcpyAsync(XA, Xs, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    HIPCHK(c, hipMemcpyAsync(VA, Xs + N, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    TRY(one_step(c, N, XA, VA, T, X1, V1, V2, st));
-    TRY(kick_vjp(c, N, XA, T, LV, h, LX, st));          // second half kick at x_{s+1}
-    TRY(jump_vjp(c, N, XA, V2, h, LX, LV, st));          // jump after the drift
-    HIPCHK(c, launch_drift_vjp(X1, V1, N, c->p.dt, c->p.G * c->p.m0, LX, LV, st), "drift vjp");
-    TRY(jump_vjp(c, N, X1, V1, h, LX, LV, st));          // jump before the drift
-    TRY(kick_vjp(c, N, Xs, T, LV, h, LX, st));           // first half kick at x_s
+    TRY(kick_vjp(c, N, s + 1 < nsteps ? Xs(s + 1) : Xend, T, LV, h, LX, st));
+    TRY(jump_vjp(c, N, X1(s), V2(s), h, LX, LV, st));
+    HIPCHK(c, launch_drift_vjp(X1(s), V1(s), N, p.dt, p.G * p.m0, LX, LV, st), "drift vjp");
+    TRY(jump_vjp(c, N, X1(s), V1(s), h, LX, LV, st));
+    TRY(kick_vjp(c, N, Xs(s), T, LV, h, LX, st));
   }
   return NBODY_OK;
 }
@@ -601,6 +622,17 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
   return rc;
 }
 
+int nbody_tune(nbody_ctx *c, const char *name, int64_t value) {
+  if (!c || !name) return NBODY_E_INVAL;
+  const std::string k(name);
+  if (k == "locality_min_n" && value >= 1) c->locality_min_n = (int)std::min<int64_t>(value, INT32_MAX);
+  else if (k == "locality_every" && value >= 1) c->locality_every = (int)std::min<int64_t>(value, INT32_MAX);
+  else if (k == "emit_slots" && value >= 1 && value <= 4096) c->R = (int)value;
+  else if (k == "target_waves" && value >= 64 && value <= (1 << 20)) c->target_waves = (int)value;
+  else return fail(c, NBODY_E_INVAL, "unknown tuning key or value out of range: %s = %lld", name, (long long)value);
+  return NBODY_OK;
+}
+
 int nbody_get_batched_tiles(const nbody_ctx *c, int32_t *tiles, int32_t n) {
   if (!c || !tiles || n < kBuckets) return NBODY_E_INVAL;
   for (int b = 0; b < kBuckets; ++b) tiles[b] = c->tiles[b];
@@ -624,6 +656,7 @@ int nbody_bench_pairs(nbody_ctx *c, int64_t n, const double *xm, const double *t
   KickArgs a;
   TRY(make_kick_args(c, (int)n, xm, thr, true, false, false, a));
   hipStream_t st = (hipStream_t)stream;
+  TRY(locality(c, (int)n, a.xm, st, &a.perm));
   const bool split = c->p.precision == NBODY_PREC_SPLIT;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0), "event");

@@ -11,6 +11,7 @@ constexpr int kBlock = 256;   // threads per workgroup of the body-parallel kern
 struct KickArgs {
   const double4 *xm;
   const double4 *thr;
+  const int *perm;   // lane -> body (null: identity)
   int n;
   int nchunk;     // number of j-chunks (S)
   int chunk;      // bodies per j-chunk
@@ -30,6 +31,9 @@ hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool 
 hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, int n, double G,
                            double h, int napply, const double4 *xm, double4 *v, double4 *acc,
                            double4 *acc_ce, double4 *mom, hipStream_t st);
+hipError_t launch_locality(const double4 *xm, int n, float2 *range_part, unsigned short *cell,
+                           unsigned *count, unsigned *cursor, int *perm, hipStream_t st);
+int locality_cells();
 hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
                        int64_t *rowtot, int64_t *bsum, hipStream_t st);
 hipError_t launch_energy(const double4 *xm, const double4 *v, const double4 *thr, int n, double G,
@@ -46,8 +50,8 @@ hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, ui
                         hipStream_t st);
 
 // adjoint.hip
-hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const double4 *lam_v, double h,
-                           double G, double f_in, int n, int S, int chunk, double4 *lam_a,
+hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double4 *lam_v,
+                           double h, double G, double f_in, int n, int S, int chunk, double4 *lam_a,
                            double4 *part, double4 *lam_x, hipStream_t st);
 hipError_t launch_jump_vjp(const double4 *xm, const double4 *v, double h, double m0, int n,
                            double4 *parts, double4 *lam_x, double4 *lam_v, hipStream_t st);

@@ -31,16 +31,23 @@ hipError_t launch_rcrit(const double4 *xm, const double4 *v, double4 *thr, int n
 // ------------------------------------------------------------------ pair kernel
 // FORCE: accumulate accelerations; EMIT: record close partners j > i; CE: accumulate the
 // complementary close-encounter acceleration; SPLIT: binary32 r^-3 core.
+// perm (may be null) maps lanes to bodies. Every body's sum over j is formed in the same order
+// whatever lane computes it, so the permutation changes no result bit; it only groups spatially
+// close bodies into a wave, which keeps the wave-level prefilter of close pairs from firing for
+// j far from all of them.
 template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm,
-                                                  const double4 *__restrict__ thr, int n, int chunk,
+                                                  const double4 *__restrict__ thr,
+                                                  const int *__restrict__ perm, int n, int chunk,
                                                   double f_in, double4 *__restrict__ part,
                                                   double4 *__restrict__ part_ce,
                                                   int *__restrict__ cnt, int *__restrict__ rowbuf,
                                                   int R, double c15, double c1875) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
+  const int lane_body = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = lane_body < n;
+  const int lb = valid ? lane_body : n - 1;
+  const int ii = perm ? perm[lb] : lb;
+  const int i = ii;
   const double4 pi = xm[ii];
   // wave-uniform prefilter bound: a pair (i, j) can be close only if r^2 <= max(T_i, T_j)
   const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
@@ -77,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm
             }
             s = sn;
           }
-          if (EMIT && j > ii) {
+          if (EMIT && valid && j > ii) {
             if (nc < R) rowbuf[((size_t)blockIdx.y * R + nc) * n + ii] = j;
             ++nc;
           }
@@ -100,8 +107,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm
 template <bool F, bool E, bool C, bool S>
 static void go(const KickArgs &a, hipStream_t st) {
   dim3 grid(nblocks(a.n), a.nchunk);
-  hipLaunchKernelGGL((k_pairs<F, E, C, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.n, a.chunk,
-                     a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5, 1.875);
+  hipLaunchKernelGGL((k_pairs<F, E, C, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.n,
+                     a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5, 1.875);
 }
 
 hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool split,
@@ -117,6 +124,115 @@ hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool 
   }
   return hipGetLastError();
 }
+
+
+// ------------------------------------------------------------------ locality permutation
+// Bodies are binned into 64 x 64 cells of (log r, azimuth), r and azimuth taken in the x-y
+// plane, log r scaled to the call's range; cells are visited in Morton order and bodies within
+// a cell in arbitrary order (atomic placement: the order of bodies cannot change any result).
+constexpr int kCells = 4096;
+
+__device__ __forceinline__ float body_logr(double4 p) {
+  return logf(fmaxf((float)sqrt(p.x * p.x + p.y * p.y), 1e-30f));
+}
+
+__global__ __launch_bounds__(kBlock) void k_lr_range(const double4 *__restrict__ xm, int n,
+                                                     float2 *__restrict__ part) {
+  __shared__ float lo[kBlock], hi[kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  float v = i < n ? body_logr(xm[i]) : 0.f;
+  lo[threadIdx.x] = i < n ? v : INFINITY;
+  hi[threadIdx.x] = i < n ? v : -INFINITY;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      lo[threadIdx.x] = fminf(lo[threadIdx.x], lo[threadIdx.x + s]);
+      hi[threadIdx.x] = fmaxf(hi[threadIdx.x], hi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = make_float2(lo[0], hi[0]);
+}
+
+__device__ __forceinline__ unsigned spread6(unsigned v) {
+  unsigned r = 0;
+  for (int b = 0; b < 6; ++b) r |= ((v >> b) & 1u) << (2 * b);
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cells(const double4 *__restrict__ xm, int n,
+                                                  const float2 *__restrict__ part, int nb,
+                                                  unsigned short *__restrict__ cell,
+                                                  unsigned *__restrict__ count) {
+  __shared__ float lo[kBlock], hi[kBlock];
+  float a = INFINITY, b = -INFINITY;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    a = fminf(a, part[k].x);
+    b = fmaxf(b, part[k].y);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      lo[threadIdx.x] = fminf(lo[threadIdx.x], lo[threadIdx.x + s]);
+      hi[threadIdx.x] = fmaxf(hi[threadIdx.x], hi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = xm[i];
+  const float span = fmaxf(hi[0] - lo[0], 1e-6f);
+  int ir = (int)((body_logr(p) - lo[0]) / span * 64.f);
+  int ia = (int)((atan2f((float)p.y, (float)p.x) + 3.14159265f) * (64.f / 6.2831853f));
+  ir = min(max(ir, 0), 63);
+  ia = min(max(ia, 0), 63);
+  const unsigned c = spread6((unsigned)ir) | (spread6((unsigned)ia) << 1);
+  cell[i] = (unsigned short)c;
+  atomicAdd(count + c, 1u);
+}
+
+// Exclusive scan of the cell counts (one workgroup of 1024 threads, 4 cells each).
+__global__ __launch_bounds__(1024) void k_scan_cells(unsigned *__restrict__ count,
+                                                     unsigned *__restrict__ cursor) {
+  __shared__ unsigned lds[1024];
+  const int t = threadIdx.x;
+  unsigned v[4], s = 0;
+  for (int k = 0; k < 4; ++k) { v[k] = count[4 * t + k]; s += v[k]; }
+  lds[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    unsigned add = t >= o ? lds[t - o] : 0u;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  unsigned run = lds[t] - s;
+  for (int k = 0; k < 4; ++k) { cursor[4 * t + k] = run; run += v[k]; count[4 * t + k] = 0u; }
+}
+
+__global__ __launch_bounds__(kBlock) void k_place(const unsigned short *__restrict__ cell, int n,
+                                                  unsigned *__restrict__ cursor,
+                                                  int *__restrict__ perm) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const unsigned pos = atomicAdd(cursor + cell[i], 1u);
+  perm[pos] = i;
+}
+
+// count must hold kCells zeros on entry and holds zeros again on return.
+hipError_t launch_locality(const double4 *xm, int n, float2 *range_part, unsigned short *cell,
+                           unsigned *count, unsigned *cursor, int *perm, hipStream_t st) {
+  const int nb = nblocks(n);
+  hipLaunchKernelGGL(k_lr_range, dim3(nb), dim3(kBlock), 0, st, xm, n, range_part);
+  hipLaunchKernelGGL(k_cells, dim3(nb), dim3(kBlock), 0, st, xm, n, range_part, nb, cell, count);
+  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, st, count, cursor);
+  hipLaunchKernelGGL(k_place, dim3(nb), dim3(kBlock), 0, st, cell, n, cursor, perm);
+  return hipGetLastError();
+}
+
+int locality_cells() { return kCells; }
 
 // ------------------------------------------------------------------ finalize: sum partials
 __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__ part,

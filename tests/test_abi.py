@@ -90,3 +90,14 @@ def test_library_does_not_link_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "liboracle" not in text, f
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    """No CPU fallback: with the shared library absent the binding raises."""
+    import paper_2604_09184_amd as nb
+    monkeypatch.setattr(nb, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(nb, "_lib", None)
+    with pytest.raises(nb.NBodyError):
+        nb.lib()
+    with pytest.raises(nb.NBodyError):
+        nb.Context(nb.Params())

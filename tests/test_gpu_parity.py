@@ -343,3 +343,32 @@ def test_full_size_long_run_invariants(ctx, big):
     say(f"  dL/L {dL:.2e}  dE'/E' {dE:.2e}")
     assert dL < 1e-11
     assert dE < 1e-7
+
+
+def test_locality_permutation_changes_no_bit(nb):
+    """Grouping bodies into waves by position (n >= locality_min_n) must not change a bit of the
+    accelerations, the encounter list or a multi-step state."""
+    say("locality permutation on/off n=9000")
+    p = diskgen.PARAMS
+    d = cluster_disk(9000, 300)
+    res = []
+    for min_n in (1, 1 << 30):
+        ctx = nb.Context(nb.Params(**p))
+        ctx.tune("locality_min_n", min_n)
+        ctx.tune("locality_every", 3)
+        X, V = to_dev(d)
+        thr = ctx.rcrit(X, V)
+        acc, ce = ctx.accelerations(X, thr, with_ce=True)
+        pairs, count = ctx.encounters(X, thr)
+        spairs, scount = ctx.step(X, V, 7, thr=thr, pairs_cap=1 << 20)
+        res.append((acc, ce, pairs, X, V, spairs))
+    for a, b in zip(res[0], res[1]):
+        assert torch.equal(a, b)
+
+
+def test_tuning_knobs_validate(nb):
+    ctx = nb.Context(nb.Params(**diskgen.PARAMS))
+    with pytest.raises(nb.NBodyError):
+        ctx.tune("no_such_knob", 3)
+    with pytest.raises(nb.NBodyError):
+        ctx.tune("emit_slots", 0)
