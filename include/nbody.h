@@ -131,9 +131,9 @@ int nbody_energy(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, c
  * Launch-shape tuning of a context (host values; results never depend on them except where
  * stated): "locality_min_n" (bodies from which the pair kernels group spatially close bodies
  * into waves, default 4096; this changes no result bit), "locality_every" (steps between
- * regroupings inside nbody_step, default 10), "emit_slots" (partner slots per row and j-chunk
- * before a row is rescanned, default 128), "target_waves" (waves per pair-kernel launch, default
- * 8192; changes the summation order of the j-chunks). Returns NBODY_E_INVAL for an unknown key
+ * regroupings inside nbody_step, default 10), "emit_slots" (upper bound of the partner slots per
+ * row and j-chunk before a row is rescanned, default 64), "target_waves" (waves per pair-kernel
+ * launch, default 32768; changes the summation order of the j-chunks). Returns NBODY_E_INVAL for an unknown key
  * or a value out of range.
  */
 int nbody_tune(nbody_ctx *ctx, const char *name, int64_t value);

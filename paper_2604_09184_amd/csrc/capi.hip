@@ -26,7 +26,7 @@ struct Buf {
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_T_OFFS, B_T_ORDER, B_PERM, B_CELL,
-             B_RANGE, B_CCOUNT, B_CCURSOR, B_NUM };
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_NUM };
 
 }  // namespace
 
@@ -34,10 +34,10 @@ struct nbody_ctx {
   nbody_params p{};
   std::string err;
   Buf buf[B_NUM];
-  int R = 128;              // partner slots per (row, j-chunk) in the emission buffer
+  int R = 64;               // partner slots per (row, j-chunk) in the emission buffer (at most)
   int locality_min_n = 4096;  // lane permutation by position for n at least this
   int locality_every = 10;    // steps between refreshes of the lane permutation in nbody_step
-  int target_waves = 8192;  // pair-kernel waves to aim for (8 per SIMD on 256 CUs)
+  int target_waves = 32768; // pair-kernel waves per launch: 32 per SIMD, for load balance
   // batched tiles per size class (bit 0: wave tile, bit 1: two bodies per lane); -1 = untuned
   int32_t tiles[nbk::kBuckets] = {1, 1, 1, 3, 2, 2};
   bool tuned = false;
@@ -150,15 +150,27 @@ int locality(nbody_ctx *c, int n, const double4 *xm, hipStream_t st, const int *
   return NBODY_OK;
 }
 
+// Device flag {1, m} when all masses equal m (computed once per call; masses never change).
+int mass_check(nbody_ctx *c, int n, const double4 *xm, hipStream_t st, const double2 **uni) {
+  double2 *part = (double2 *)ensure(c, B_MPART, (size_t)nblocks(n) * sizeof(double2));
+  double2 *u = (double2 *)ensure(c, B_UNI, sizeof(double2));
+  if (!part || !u) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (mass check)");
+  HIPCHK(c, launch_mass_check(xm, n, part, u, st), "mass check");
+  *uni = u;
+  return NBODY_OK;
+}
+
 int make_kick_args(nbody_ctx *c, int n, const double *xm, const double *thr, bool need_force,
                    bool need_ce, bool need_emit, KickArgs &a) {
   plan(c, n, a.nchunk, a.chunk);
   a.perm = nullptr;
+  a.uni = nullptr;
   a.xm = reinterpret_cast<const double4 *>(xm);
   a.thr = reinterpret_cast<const double4 *>(thr);
   a.n = n;
   a.f_in = c->p.f_in;
-  a.R = c->R;
+  // partner slots per (row, chunk): a row-chunk that overflows is rescanned at O(chunk) cost
+  a.R = std::min(c->R, std::max(16, a.chunk / 32));
   const size_t sn = (size_t)a.nchunk * n;
   a.part = need_force ? (double4 *)ensure(c, B_PART, sn * sizeof(double4)) : nullptr;
   a.part_ce = need_ce ? (double4 *)ensure(c, B_PART_CE, sn * sizeof(double4)) : nullptr;
@@ -328,6 +340,7 @@ int nbody_kick(nbody_ctx *c, int64_t n, const double *xm, const double *thr, dou
   TRY(make_kick_args(c, (int)n, xm, thr, true, acc_ce != nullptr, false, a));
   hipStream_t st = (hipStream_t)stream;
   TRY(locality(c, (int)n, a.xm, st, &a.perm));
+  TRY(mass_check(c, (int)n, a.xm, st, &a.uni));
   HIPCHK(c, launch_pairs(a, true, false, acc_ce != nullptr, c->p.precision == NBODY_PREC_SPLIT, st),
          "kick pairs");
   HIPCHK(c, launch_finalize(a.part, a.part_ce, a.nchunk, (int)n, c->p.G, h, 1, a.xm, (double4 *)v,
@@ -409,6 +422,7 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
   double4 *X = (double4 *)xm;
   double4 *Vv = (double4 *)v;
   TRY(locality(c, N, X, st, &a.perm));
+  TRY(mass_check(c, N, X, st, &a.uni));
   if (nsteps == 0) {
     if (emit) {
       HIPCHK(c, launch_pairs(a, false, true, false, false, st), "step pairs");
@@ -517,6 +531,7 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   KickArgs a;
   TRY(make_kick_args(c, N, (const double *)XA, thr, true, false, false, a));
   TRY(locality(c, N, XA, st, &a.perm));
+  TRY(mass_check(c, N, XA, st, &a.uni));
   HIPCHK(c, launch_pairs(a, true, false, false, split, st), "pairs");
   HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, XA, VA, nullptr, nullptr, mom, st), "finalize");
   for (int s = 0; s < nsteps; ++s) {
@@ -657,6 +672,7 @@ int nbody_bench_pairs(nbody_ctx *c, int64_t n, const double *xm, const double *t
   TRY(make_kick_args(c, (int)n, xm, thr, true, false, false, a));
   hipStream_t st = (hipStream_t)stream;
   TRY(locality(c, (int)n, a.xm, st, &a.perm));
+  TRY(mass_check(c, (int)n, a.xm, st, &a.uni));
   const bool split = c->p.precision == NBODY_PREC_SPLIT;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0), "event");

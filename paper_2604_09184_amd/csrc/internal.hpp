@@ -12,6 +12,7 @@ struct KickArgs {
   const double4 *xm;
   const double4 *thr;
   const int *perm;   // lane -> body (null: identity)
+  const double2 *uni;  // {1, m} if all masses equal m, else {0, 0} (null: not known)
   int n;
   int nchunk;     // number of j-chunks (S)
   int chunk;      // bodies per j-chunk
@@ -34,6 +35,7 @@ hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, i
 hipError_t launch_locality(const double4 *xm, int n, float2 *range_part, unsigned short *cell,
                            unsigned *count, unsigned *cursor, int *perm, hipStream_t st);
 int locality_cells();
+hipError_t launch_mass_check(const double4 *xm, int n, double2 *part, double2 *uni, hipStream_t st);
 hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
                        int64_t *rowtot, int64_t *bsum, hipStream_t st);
 hipError_t launch_energy(const double4 *xm, const double4 *v, const double4 *thr, int n, double G,
@@ -145,6 +147,16 @@ __device__ __forceinline__ double m_rinv3(double r2, double m, double c15, doubl
   const double p = fma(e, c1875, c15);
   const double my3 = (m * y) * t;
   return fma(my3 * e, p, my3);
+}
+
+// r^-3 alone (equal-mass systems multiply by m once after the sum).
+__device__ __forceinline__ double rinv3(double r2, double c15, double c1875) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double t = y * y;
+  const double e = fma(-r2, t, 1.0);
+  const double p = fma(e, c1875, c15);
+  const double y3 = y * t;
+  return fma(y3 * e, p, y3);
 }
 
 // Split precision: r^-3 in binary32 (offsets and r^2 stay binary64), scaled by m in binary64.

@@ -35,27 +35,15 @@ hipError_t launch_rcrit(const double4 *xm, const double4 *v, double4 *thr, int n
 // whatever lane computes it, so the permutation changes no result bit; it only groups spatially
 // close bodies into a wave, which keeps the wave-level prefilter of close pairs from firing for
 // j far from all of them.
-template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm,
-                                                  const double4 *__restrict__ thr,
-                                                  const int *__restrict__ perm, int n, int chunk,
-                                                  double f_in, double4 *__restrict__ part,
-                                                  double4 *__restrict__ part_ce,
-                                                  int *__restrict__ cnt, int *__restrict__ rowbuf,
-                                                  int R, double c15, double c1875) {
-  const int lane_body = blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = lane_body < n;
-  const int lb = valid ? lane_body : n - 1;
-  const int ii = perm ? perm[lb] : lb;
-  const int i = ii;
-  const double4 pi = xm[ii];
-  // wave-uniform prefilter bound: a pair (i, j) can be close only if r^2 <= max(T_i, T_j)
-  const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
-  const int j0 = blockIdx.y * chunk;
-  const int j1 = min(n, j0 + chunk);
-  double ax = 0.0, ay = 0.0, az = 0.0;
-  double cx = 0.0, cy = 0.0, cz = 0.0;
-  int nc = 0;
+// uni (may be null) = {1, m} when every body has the same mass m: the loop then sums r^-3 d and
+// multiplies by m once (one multiply less per pair), otherwise {0, 0}.
+template <bool FORCE, bool EMIT, bool CE, bool SPLIT, bool UNI>
+__device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
+                                           const double4 *__restrict__ thr, double4 pi, int ii,
+                                           bool valid, uint32_t tw, int j0, int j1, int n,
+                                           double f_in, int *__restrict__ rowbuf, int R,
+                                           double c15, double c1875, double (&a)[3],
+                                           double (&ce)[3], int &nc) {
 #pragma unroll 2
   for (int j = j0; j < j1; ++j) {
     const double4 pj = xm[j];
@@ -65,8 +53,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm
     const double dy = pj.y - pi.y;
     const double dz = pj.z - pi.z;
     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double mj = UNI ? 1.0 : pj.w;
     double s = 0.0;
-    if (FORCE) s = SPLIT ? m_rinv3_split(r2, pj.w) : m_rinv3(r2, pj.w, c15, c1875);
+    if (FORCE) s = SPLIT ? m_rinv3_split(r2, mj) : (UNI ? rinv3(r2, c15, c1875) : m_rinv3(r2, mj, c15, c1875));
     if (hiword(r2) <= U) {
       if (j == ii) {
         s = 0.0;
@@ -75,12 +64,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm
         const double4 tq = thr[j];
         if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
           if (FORCE) {
-            const double sn = pj.w * close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
+            const double w = close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
+            const double sn = UNI ? w : mj * w;
             if (CE) {
               const double ds = s - sn;
-              cx = fma(ds, dx, cx);
-              cy = fma(ds, dy, cy);
-              cz = fma(ds, dz, cz);
+              ce[0] = fma(ds, dx, ce[0]);
+              ce[1] = fma(ds, dy, ce[1]);
+              ce[2] = fma(ds, dz, ce[2]);
             }
             s = sn;
           }
@@ -92,23 +82,112 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm
       }
     }
     if (FORCE) {
-      ax = fma(s, dx, ax);
-      ay = fma(s, dy, ay);
-      az = fma(s, dz, az);
+      a[0] = fma(s, dx, a[0]);
+      a[1] = fma(s, dy, a[1]);
+      a[2] = fma(s, dz, a[2]);
     }
   }
+}
+
+template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm,
+                                                  const double4 *__restrict__ thr,
+                                                  const int *__restrict__ perm,
+                                                  const double2 *__restrict__ uni, int n, int chunk,
+                                                  double f_in, double4 *__restrict__ part,
+                                                  double4 *__restrict__ part_ce,
+                                                  int *__restrict__ cnt, int *__restrict__ rowbuf,
+                                                  int R, double c15, double c1875) {
+  const int lane_body = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = lane_body < n;
+  const int lb = valid ? lane_body : n - 1;
+  const int ii = perm ? perm[lb] : lb;
+  const double4 pi = xm[ii];
+  // wave-uniform prefilter bound: a pair (i, j) can be close only if r^2 <= max(T_i, T_j)
+  const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  double a[3] = {0.0, 0.0, 0.0};
+  double ce[3] = {0.0, 0.0, 0.0};
+  int nc = 0;
+  double mu = 1.0;
+  bool uniform = false;
+  if (FORCE && uni) {
+    const double2 u = uni[0];
+    uniform = u.x != 0.0;
+    mu = u.y;
+  }
+  if (uniform)
+    pairs_loop<FORCE, EMIT, CE, SPLIT, true>(xm, thr, pi, ii, valid, tw, j0, j1, n, f_in, rowbuf, R,
+                                             c15, c1875, a, ce, nc);
+  else
+    pairs_loop<FORCE, EMIT, CE, SPLIT, false>(xm, thr, pi, ii, valid, tw, j0, j1, n, f_in, rowbuf,
+                                              R, c15, c1875, a, ce, nc);
   if (!valid) return;
-  const size_t o = (size_t)blockIdx.y * n + i;
-  if (FORCE) part[o] = make_double4(ax, ay, az, 0.0);
-  if (CE) part_ce[o] = make_double4(cx, cy, cz, 0.0);
+  const size_t o = (size_t)blockIdx.y * n + ii;
+  if (FORCE) {
+    if (uniform) { a[0] *= mu; a[1] *= mu; a[2] *= mu; }
+    part[o] = make_double4(a[0], a[1], a[2], 0.0);
+  }
+  if (CE) {
+    if (uniform) { ce[0] *= mu; ce[1] *= mu; ce[2] *= mu; }
+    part_ce[o] = make_double4(ce[0], ce[1], ce[2], 0.0);
+  }
   if (EMIT) cnt[o] = nc;
+}
+
+// ------------------------------------------------------------------ equal-mass detection
+__global__ __launch_bounds__(kBlock) void k_mass_range(const double4 *__restrict__ xm, int n,
+                                                       double2 *__restrict__ part) {
+  __shared__ double lo[kBlock], hi[kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const double m = i < n ? xm[i].w : xm[0].w;
+  lo[threadIdx.x] = m;
+  hi[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + s]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = make_double2(lo[0], hi[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mass_flag(const double2 *__restrict__ part, int nb,
+                                                      double2 *__restrict__ uni) {
+  __shared__ double lo[kBlock], hi[kBlock];
+  double a = part[0].x, b = part[0].y;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    a = fmin(a, part[k].x);
+    b = fmax(b, part[k].y);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + s]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) uni[0] = lo[0] == hi[0] ? make_double2(1.0, lo[0]) : make_double2(0.0, 0.0);
+}
+
+hipError_t launch_mass_check(const double4 *xm, int n, double2 *part, double2 *uni, hipStream_t st) {
+  const int nb = nblocks(n);
+  hipLaunchKernelGGL(k_mass_range, dim3(nb), dim3(kBlock), 0, st, xm, n, part);
+  hipLaunchKernelGGL(k_mass_flag, dim3(1), dim3(kBlock), 0, st, part, nb, uni);
+  return hipGetLastError();
 }
 
 template <bool F, bool E, bool C, bool S>
 static void go(const KickArgs &a, hipStream_t st) {
   dim3 grid(nblocks(a.n), a.nchunk);
-  hipLaunchKernelGGL((k_pairs<F, E, C, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.n,
-                     a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5, 1.875);
+  hipLaunchKernelGGL((k_pairs<F, E, C, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.uni,
+                     a.n, a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5, 1.875);
 }
 
 hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool split,
