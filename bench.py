@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch of the binary64 pair kernel from the FETCH_SIZE / WRITE_SIZE passes
 # (calibrated with a plain copy; see profiles/k_pairs_disk32768.md), valid for the kernel source
 # whose hash is stored beside it.
-PAIR_KERNEL_TRAFFIC = {"bytes": 48435196, "source_sha256": "c98142df27b5929c399ebc58ab245ed0b7bc43d292007f0bb1eab204ab61e724"}
+PAIR_KERNEL_TRAFFIC = {"bytes": 95130149, "source_sha256": "82145a65a91ef1d26bd0e63037f527a35effbf3a797cf5aaab2889448064cbd6"}
 PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/kick.hip", "paper_2604_09184_amd/csrc/internal.hpp"]
 
 FLOP_PER_PAIR = 20                 # N-body convention: 3 sub, 5 for r^2, rsqrt, 3 for m r^-3, 6 accumulate, 2 slack
