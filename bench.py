@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--only", choices=["split", "batched", "adjoint"],
+                    help="run only this variant and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -206,6 +208,11 @@ def main():
     import paper_2604_09184_amd as nb
 
     dev = torch.device("cuda:0")
+    if args.only:
+        p = diskgen.PARAMS
+        fn = {"split": variant_split, "batched": variant_batched, "adjoint": variant_adjoint}[args.only]
+        print(json.dumps({args.only: fn(nb, p)}), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         dst = torch.empty_like(src)

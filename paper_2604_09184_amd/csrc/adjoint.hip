@@ -110,7 +110,15 @@ __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restri
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   double gx = 0.0, gy = 0.0, gz = 0.0, gm = 0.0;
-  for (int s = 0; s < S; ++s) {
+  int s = 0;
+  for (; s + 8 <= S; s += 8) {
+    double4 q[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = part[(size_t)(s + k) * n + i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { gx += q[k].x; gy += q[k].y; gz += q[k].z; gm += q[k].w; }
+  }
+  for (; s < S; ++s) {
     const double4 p = part[(size_t)s * n + i];
     gx += p.x; gy += p.y; gz += p.z; gm += p.w;
   }

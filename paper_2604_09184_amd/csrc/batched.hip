@@ -256,6 +256,29 @@ hipError_t launch_batched(const BatchLaunch &b, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Copies the bodies of m chosen systems (source offsets src, destination offsets dst[0..m]) into
+// a packed scratch ensemble: one workgroup per system.
+__global__ __launch_bounds__(kBlock) void k_gather(const double4 *__restrict__ xm,
+                                                   const double4 *__restrict__ v,
+                                                   const int64_t *__restrict__ src,
+                                                   const int64_t *__restrict__ dst, int m,
+                                                   double4 *__restrict__ txm,
+                                                   double4 *__restrict__ tv) {
+  const int k = blockIdx.x;
+  if (k >= m) return;
+  const int64_t s0 = src[k], d0 = dst[k], len = dst[k + 1] - dst[k];
+  for (int64_t t = threadIdx.x; t < len; t += kBlock) {
+    txm[d0 + t] = xm[s0 + t];
+    tv[d0 + t] = v[s0 + t];
+  }
+}
+
+hipError_t launch_gather(const double4 *xm, const double4 *v, const int64_t *src, const int64_t *dst,
+                         int m, double4 *txm, double4 *tv, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(m), dim3(kBlock), 0, st, xm, v, src, dst, m, txm, tv);
+  return hipGetLastError();
+}
+
 int batched_max_group_n() { return kMaxGroupN; }
 int batched_max_wave_n() { return kMaxWaveN; }
 

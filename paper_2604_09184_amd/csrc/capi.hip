@@ -26,7 +26,7 @@ struct Buf {
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_T_OFFS, B_T_ORDER, B_PERM, B_CELL,
-             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_NUM };
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_T_SRC, B_T_DST, B_NUM };
 
 }  // namespace
 
@@ -45,6 +45,7 @@ struct nbody_ctx {
   std::vector<int32_t> h_order;
   std::vector<int64_t> h_toffs;
   std::vector<int32_t> h_torder;
+  std::vector<int64_t> h_tsrc;
 };
 
 namespace {
@@ -120,11 +121,11 @@ int check_n(nbody_ctx *c, int64_t n) {
     if (r_ != NBODY_OK) return r_; \
   } while (0)
 
-// j-chunking: enough waves to fill the chip, chunks of at least 128 bodies.
+// j-chunking: enough waves to fill the chip, chunks of at least 64 bodies.
 void plan(const nbody_ctx *c, int n, int &S, int &chunk) {
   const int iwaves = (n + 63) / 64;
   int s = (c->target_waves + iwaves - 1) / iwaves;
-  const int smax = (n + 127) / 128;
+  const int smax = (n + 63) / 64;
   if (s > smax) s = smax;
   if (s < 1) s = 1;
   chunk = (n + s - 1) / s;
@@ -599,23 +600,28 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
     const int64_t tot = c->h_toffs.back();
     double4 *txm = (double4 *)ensure(c, B_T_XM, (size_t)tot * sizeof(double4));
     double4 *tv = (double4 *)ensure(c, B_T_V, (size_t)tot * sizeof(double4));
-    if (!txm || !tv) { rc = fail(c, NBODY_E_NOMEM, "workspace allocation failed (autotune)"); break; }
+    int64_t *d_src = (int64_t *)ensure(c, B_T_SRC, ids.size() * sizeof(int64_t));
+    int64_t *d_dst = (int64_t *)ensure(c, B_T_DST, (ids.size() + 1) * sizeof(int64_t));
+    if (!txm || !tv || !d_src || !d_dst) { rc = fail(c, NBODY_E_NOMEM, "workspace allocation failed (autotune)"); break; }
+    c->h_tsrc.resize(ids.size());
+    for (size_t k = 0; k < ids.size(); ++k) c->h_tsrc[k] = offs[ids[k]];
+    {
+      hipError_t e = hipMemcpyAsync(d_src, c->h_tsrc.data(), ids.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d_dst, c->h_toffs.data(), (ids.size() + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
+    }
     const int64_t nmax = int64_t(64) << b;
     double best = 1e300;
     int best_code = c->tiles[b];
     for (int code = 0; code < 4 && rc == NBODY_OK; ++code) {
       if ((code & 1) && nmax > batched_max_wave_n()) continue;
       for (int rep = 0; rep < 2 && rc == NBODY_OK; ++rep) {   // rep 0 warms up
-        for (size_t k = 0; k < ids.size(); ++k) {
-          const size_t nb = (size_t)(offs[ids[k] + 1] - offs[ids[k]]) * sizeof(double4);
-          hipError_t e = hipMemcpyAsync(txm + c->h_toffs[k], (const double4 *)xm + offs[ids[k]], nb,
-                                        hipMemcpyDeviceToDevice, st);
-          if (e == hipSuccess)
-            e = hipMemcpyAsync(tv + c->h_toffs[k], (const double4 *)v + offs[ids[k]], nb,
-                               hipMemcpyDeviceToDevice, st);
-          if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
+        {
+          hipError_t e = launch_gather((const double4 *)xm, (const double4 *)v, d_src, d_dst, (int)ids.size(), txm,
+                                       tv, st);
+          if (e != hipSuccess) { rc = hip_fail(c, e, "autotune gather"); break; }
         }
-        if (rc != NBODY_OK) break;
         hipError_t e = hipEventRecord(e0, st);
         if (e != hipSuccess) { rc = hip_fail(c, e, "event"); break; }
         rc = run_batched(c, (int32_t)ids.size(), c->h_toffs, c->h_torder, B_T_OFFS, B_T_ORDER, txm, tv, nsteps,

@@ -75,6 +75,8 @@ struct BatchLaunch {
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t st);
 hipError_t batched_occupancy(int *blocks_per_cu);
 int batched_max_group_n();
+hipError_t launch_gather(const double4 *xm, const double4 *v, const int64_t *src, const int64_t *dst,
+                         int m, double4 *txm, double4 *tv, hipStream_t st);
 int batched_max_wave_n();
 
 inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
