@@ -148,9 +148,9 @@ def variant_adjoint(nb, p):
         loss = ((xT[:, :3] - target) ** 2).sum()
         bsec, _ = timed(lambda: loss.backward())
         res = {"forward_s": fsec, "backward_s": bsec}
-    # pair evaluations in the backward: per step one recomputed step (2 kicks) plus two kick
-    # VJPs, plus the in-segment replay of the checkpointed states (9 of every 10 steps, 2 kicks)
-    evals = 100 * 2 + 100 * 2 + 90 * 2
+    # pair evaluations in the backward, per segment of 10 steps: the replay (11 kick evaluations)
+    # and the kick derivatives (11 evaluations, two half kicks at the same positions sharing one)
+    evals = 10 * (11 + 11)
     return {"workload": "adjoint8192", "n": n, "steps": 100, "checkpoint_every": 10,
             "forward_s": round(res["forward_s"], 4), "backward_s": round(res["backward_s"], 4),
             "backward_over_forward": round(res["backward_s"] / res["forward_s"], 2),

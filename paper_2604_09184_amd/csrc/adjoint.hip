@@ -104,9 +104,12 @@ __global__ __launch_bounds__(kBlock) void k_scale(const double4 *__restrict__ lv
   la[i] = make_double4(h * q.x, h * q.y, h * q.z, 0.0);
 }
 
-// lam_x += G * sum of partials (component 3 accumulates dL/dm)
+// lam_x += G * sum of partials (component 3 accumulates dL/dm), napply times: two consecutive
+// kick derivatives at the same positions with the same lam_v give the same increment, so adding
+// one evaluation twice equals evaluating twice, bit for bit.
 __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restrict__ part, int S, int n,
-                                                         double G, double4 *__restrict__ lam_x) {
+                                                         double G, int napply,
+                                                         double4 *__restrict__ lam_x) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   double gx = 0.0, gy = 0.0, gz = 0.0, gm = 0.0;
@@ -123,17 +126,19 @@ __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restri
     gx += p.x; gy += p.y; gz += p.z; gm += p.w;
   }
   double4 l = lam_x[i];
-  l.x += G * gx; l.y += G * gy; l.z += G * gz; l.w += G * gm;
+  for (int k = 0; k < napply; ++k) {
+    l.x += G * gx; l.y += G * gy; l.z += G * gz; l.w += G * gm;
+  }
   lam_x[i] = l;
 }
 
 hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double4 *lam_v,
-                           double h, double G, double f_in, int n, int S, int chunk, double4 *lam_a,
-                           double4 *part, double4 *lam_x, hipStream_t st) {
+                           double h, double G, double f_in, int n, int S, int chunk, int napply,
+                           double4 *lam_a, double4 *part, double4 *lam_x, hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(nblocks(n)), dim3(kBlock), 0, st, lam_v, h, n, lam_a);
   hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, perm, lam_a, n,
                      chunk, f_in, part);
-  hipLaunchKernelGGL(k_vjp_finalize, dim3(nblocks(n)), dim3(kBlock), 0, st, part, S, n, G, lam_x);
+  hipLaunchKernelGGL(k_vjp_finalize, dim3(nblocks(n)), dim3(kBlock), 0, st, part, S, n, G, napply, lam_x);
   return hipGetLastError();
 }
 
