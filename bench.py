@@ -27,8 +27,8 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch of the binary64 pair kernel from the FETCH_SIZE / WRITE_SIZE passes
 # (calibrated with a plain copy; see profiles/k_pairs_disk32768.md), valid for the kernel source
 # whose hash is stored beside it.
-PAIR_KERNEL_TRAFFIC = {"bytes": 95130149, "source_sha256": "82145a65a91ef1d26bd0e63037f527a35effbf3a797cf5aaab2889448064cbd6"}
-PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/kick.hip", "paper_2604_09184_amd/csrc/internal.hpp"]
+PAIR_KERNEL_TRAFFIC = {"bytes": 95129580, "source_sha256": "7b24f9cbd78a7be6afe0be3ca8d0f3d57e7198d5985095e45b437ab255f65966"}
+PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/pairs.hip", "paper_2604_09184_amd/csrc/device.hpp"]
 
 FLOP_PER_PAIR = 20                 # N-body convention: 3 sub, 5 for r^2, rsqrt, 3 for m r^-3, 6 accumulate, 2 slack
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 128 flop/clk x 2.4 GHz
@@ -115,7 +115,7 @@ def variant_batched(nb, p):
     X = torch.tensor(xm, device="cuda:0")
     V = torch.tensor(v4, device="cuda:0")
     ctx = nb.Context(nb.Params(**p))
-    t_tune, tiles = timed(lambda: ctx.autotune_batched(offs, X, V, nsteps=2))
+    t_tune, tiles = timed(lambda: ctx.autotune_batched(offs, X, V, nsteps=10))
     sec, _ = timed(lambda: ctx.step_batched(offs, X, V, 100))
     sizes = offs[1:] - offs[:-1]
     pairs = 101 * float((sizes * (sizes - 1)).sum())

@@ -276,7 +276,7 @@ class Context:
                                              _stream()), "nbody_step_batched")
         return npairs
 
-    def autotune_batched(self, offs, xm, v, nsteps=3):
+    def autotune_batched(self, offs, xm, v, nsteps=10):
         _body(xm, "xm"); _body(v, "v")
         o, op = self._offs(offs)
         self._check(lib().nbody_autotune_batched(self._h, len(o) - 1, op, _ptr(xm), _ptr(v), int(nsteps),

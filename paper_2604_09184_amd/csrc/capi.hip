@@ -25,8 +25,8 @@ struct Buf {
 
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_B_OFFS, B_B_ORDER,
-             B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_T_OFFS, B_T_ORDER, B_PERM, B_CELL,
-             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_T_SRC, B_T_DST, B_NUM };
+             B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_NUM };
 
 }  // namespace
 
@@ -38,14 +38,12 @@ struct nbody_ctx {
   int locality_min_n = 4096;  // lane permutation by position for n at least this
   int locality_every = 10;    // steps between refreshes of the lane permutation in nbody_step
   int target_waves = 32768; // pair-kernel waves per launch: 32 per SIMD, for load balance
-  // batched tiles per size class (bit 0: wave tile, bit 1: two bodies per lane); -1 = untuned
-  int32_t tiles[nbk::kBuckets] = {1, 1, 1, 3, 2, 2};
+  // batched tile per size class: 1 = one wave per system (systems of at most 256 bodies),
+  // 0 = one workgroup per system
+  int32_t tiles[nbk::kBuckets] = {0, 0, 0, 0, 0, 0};
   bool tuned = false;
   std::vector<int64_t> h_offs;   // host staging kept alive across asynchronous copies
   std::vector<int32_t> h_order;
-  std::vector<int64_t> h_toffs;
-  std::vector<int32_t> h_torder;
-  std::vector<int64_t> h_tsrc;
 };
 
 namespace {
@@ -243,17 +241,22 @@ int grid_size(nbody_ctx *c, int *grid) {
   return NBODY_OK;
 }
 
-// Launches the persistent kernel over systems `ids` (host) laid out by host offsets `offs`.
-int run_batched(nbody_ctx *c, int32_t nsys, std::vector<int64_t> &h_offs, std::vector<int32_t> &h_order,
-                BufId b_offs, BufId b_order, double4 *xm, double4 *v, int32_t nsteps, int forced,
+// Launches the persistent kernel over the systems laid out by host offsets h_offs with the tile
+// table `tiles` (host, kBuckets codes).
+int run_batched(nbody_ctx *c, int32_t nsys, const int32_t *tiles, double4 *xm, double4 *v, int32_t nsteps,
                 unsigned long long *npairs, hipStream_t st) {
+  std::vector<int64_t> &h_offs = c->h_offs;
+  std::vector<int32_t> &h_order = c->h_order;
   const int64_t total = h_offs[nsys];
-  int64_t *d_offs = (int64_t *)ensure(c, b_offs, (size_t)(nsys + 1) * sizeof(int64_t));
-  int32_t *d_order = (int32_t *)ensure(c, b_order, (size_t)nsys * sizeof(int32_t));
+  BatchLaunch b;
+  TRY(grid_size(c, &b.grid));
+  int64_t *d_offs = (int64_t *)ensure(c, B_B_OFFS, (size_t)(nsys + 1) * sizeof(int64_t));
+  int32_t *d_order = (int32_t *)ensure(c, B_B_ORDER, (size_t)nsys * sizeof(int32_t));
   int32_t *d_cfg = (int32_t *)ensure(c, B_B_CFG, kBuckets * sizeof(int32_t));
   double4 *d_thr = (double4 *)ensure(c, B_B_THR, (size_t)total * sizeof(double4));
+  double4 *d_part = (double4 *)ensure(c, B_B_PART, (size_t)b.grid * 2 * kBatchedWaves * 64 * sizeof(double4));
   unsigned *d_q = (unsigned *)ensure(c, B_B_QUEUE, 256);
-  if (!d_offs || !d_order || !d_cfg || !d_thr || !d_q)
+  if (!d_offs || !d_order || !d_cfg || !d_thr || !d_part || !d_q)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (batched)");
   h_order.resize(nsys);
   std::iota(h_order.begin(), h_order.end(), 0);
@@ -262,11 +265,9 @@ int run_batched(nbody_ctx *c, int32_t nsys, std::vector<int64_t> &h_offs, std::v
   });
   HIPCHK(c, hipMemcpyAsync(d_offs, h_offs.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
   HIPCHK(c, hipMemcpyAsync(d_order, h_order.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
-  HIPCHK(c, hipMemcpyAsync(d_cfg, c->tiles, kBuckets * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
-  BatchLaunch b;
-  b.offs = d_offs; b.order = d_order; b.cfg = d_cfg; b.nsys = nsys; b.nsteps = nsteps; b.forced = forced;
-  TRY(grid_size(c, &b.grid));
-  b.xm = xm; b.v = v; b.thr = d_thr; b.npairs = npairs; b.queue = d_q;
+  HIPCHK(c, hipMemcpyAsync(d_cfg, tiles, kBuckets * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+  b.offs = d_offs; b.order = d_order; b.cfg = d_cfg; b.nsys = nsys; b.nsteps = nsteps;
+  b.xm = xm; b.v = v; b.thr = d_thr; b.part = d_part; b.npairs = npairs; b.queue = d_q;
   const nbody_params &p = c->p;
   b.G = p.G; b.m0 = p.m0; b.dt = p.dt; b.f_in = p.f_in;
   b.cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
@@ -274,7 +275,7 @@ int run_batched(nbody_ctx *c, int32_t nsys, std::vector<int64_t> &h_offs, std::v
   b.cV = b.n2dt * b.n2dt;
   b.n1 = p.n1;
   HIPCHK(c, launch_batched(b, st), "batched launch");
-  // the host staging vectors must outlive the copies above
+  // the host staging vectors (and the tile table) must outlive the copies above
   HIPCHK(c, hipStreamSynchronize(st), "batched sync");
   return NBODY_OK;
 }
@@ -575,8 +576,8 @@ int nbody_step_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, double *
   if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
   if (c->p.precision != NBODY_PREC_F64) return fail(c, NBODY_E_INVAL, "batched ensembles run in binary64");
   c->h_offs.assign(offs, offs + nsys + 1);
-  return run_batched(c, nsys, c->h_offs, c->h_order, B_B_OFFS, B_B_ORDER, (double4 *)xm, (double4 *)v,
-                     nsteps, -1, (unsigned long long *)npairs, (hipStream_t)stream);
+  return run_batched(c, nsys, c->tiles, (double4 *)xm, (double4 *)v, nsteps, (unsigned long long *)npairs,
+                     (hipStream_t)stream);
 }
 
 int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, const double *xm,
@@ -587,61 +588,58 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
   TRY(check_dev(c, v, "v", true));
   if (nsteps < 1) return fail(c, NBODY_E_INVAL, "nsteps < 1");
   hipStream_t st = (hipStream_t)stream;
+  c->h_offs.assign(offs, offs + nsys + 1);
+  const int64_t tot = offs[nsys];
+  double4 *txm = (double4 *)ensure(c, B_T_XM, (size_t)tot * sizeof(double4));
+  double4 *tv = (double4 *)ensure(c, B_T_V, (size_t)tot * sizeof(double4));
+  if (!txm || !tv) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (autotune)");
+  // classes present, and the largest system of each
+  int64_t nmax[kBuckets] = {0};
+  for (int32_t s = 0; s < nsys; ++s) {
+    const int64_t n = offs[s + 1] - offs[s];
+    const int b = size_class_host(n);
+    nmax[b] = std::max(nmax[b], n);
+  }
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0), "event");
   HIPCHK(c, hipEventCreate(&e1), "event");
   int rc = NBODY_OK;
-  for (int b = 0; b < kBuckets && rc == NBODY_OK; ++b) {
-    // the systems of this size class, gathered into a scratch ensemble
-    std::vector<int32_t> ids;
-    for (int32_t s = 0; s < nsys; ++s)
-      if (size_class_host(offs[s + 1] - offs[s]) == b) ids.push_back(s);
-    if (ids.empty()) continue;
-    c->h_toffs.assign(ids.size() + 1, 0);
-    for (size_t k = 0; k < ids.size(); ++k) c->h_toffs[k + 1] = c->h_toffs[k] + offs[ids[k] + 1] - offs[ids[k]];
-    const int64_t tot = c->h_toffs.back();
-    double4 *txm = (double4 *)ensure(c, B_T_XM, (size_t)tot * sizeof(double4));
-    double4 *tv = (double4 *)ensure(c, B_T_V, (size_t)tot * sizeof(double4));
-    int64_t *d_src = (int64_t *)ensure(c, B_T_SRC, ids.size() * sizeof(int64_t));
-    int64_t *d_dst = (int64_t *)ensure(c, B_T_DST, (ids.size() + 1) * sizeof(int64_t));
-    if (!txm || !tv || !d_src || !d_dst) { rc = fail(c, NBODY_E_NOMEM, "workspace allocation failed (autotune)"); break; }
-    c->h_tsrc.resize(ids.size());
-    for (size_t k = 0; k < ids.size(); ++k) c->h_tsrc[k] = offs[ids[k]];
-    {
-      hipError_t e = hipMemcpyAsync(d_src, c->h_tsrc.data(), ids.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(d_dst, c->h_toffs.data(), (ids.size() + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
-      if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
-    }
-    const int64_t nmax = int64_t(64) << b;
-    double best = 1e300;
-    int best_code = c->tiles[b];
-    for (int code = 0; code < 4 && rc == NBODY_OK; ++code) {
-      if ((code & 1) && nmax > batched_max_wave_n()) continue;
+  int32_t trial[kBuckets];
+  std::copy(c->tiles, c->tiles + kBuckets, trial);
+  // one sweep of coordinate descent, largest class first: the whole ensemble (on scratch copies)
+  // is timed with each admissible tile of one class while the other classes keep theirs, so the
+  // measure includes how the classes fill each other's gaps in the queue
+  for (int b = kBuckets - 1; b >= 0 && rc == NBODY_OK; --b) {
+    if (nmax[b] == 0 || nmax[b] > batched_max_wave_n()) continue;
+    const int incumbent = trial[b];
+    double t_code[2] = {1e300, 1e300};
+    for (int code = 0; code < 2 && rc == NBODY_OK; ++code) {
+      trial[b] = code;
       for (int rep = 0; rep < 2 && rc == NBODY_OK; ++rep) {   // rep 0 warms up
-        {
-          hipError_t e = launch_gather((const double4 *)xm, (const double4 *)v, d_src, d_dst, (int)ids.size(), txm,
-                                       tv, st);
-          if (e != hipSuccess) { rc = hip_fail(c, e, "autotune gather"); break; }
-        }
-        hipError_t e = hipEventRecord(e0, st);
-        if (e != hipSuccess) { rc = hip_fail(c, e, "event"); break; }
-        rc = run_batched(c, (int32_t)ids.size(), c->h_toffs, c->h_torder, B_T_OFFS, B_T_ORDER, txm, tv, nsteps,
-                         code, nullptr, st);
+        hipError_t e = hipMemcpyAsync(txm, xm, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(tv, v, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
+        rc = run_batched(c, nsys, trial, txm, tv, nsteps, nullptr, st);
         if (rc != NBODY_OK) break;
         float ms = 0.f;
         e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (e != hipSuccess) { rc = hip_fail(c, e, "autotune timing"); break; }
-        if (rep == 1 && ms < best) { best = ms; best_code = code; }
+        if (rep == 1) t_code[code] = ms;
       }
     }
-    c->tiles[b] = best_code;
+    // the other tile must win by more than the run-to-run spread to replace the incumbent
+    const int other = 1 - incumbent;
+    trial[b] = t_code[other] < 0.97 * t_code[incumbent] ? other : incumbent;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (rc == NBODY_OK) c->tuned = true;
+  if (rc == NBODY_OK) {
+    std::copy(trial, trial + kBuckets, c->tiles);
+    c->tuned = true;
+  }
   return rc;
 }
 
@@ -665,7 +663,7 @@ int nbody_get_batched_tiles(const nbody_ctx *c, int32_t *tiles, int32_t n) {
 int nbody_set_batched_tiles(nbody_ctx *c, const int32_t *tiles, int32_t n) {
   if (!c || !tiles || n != kBuckets) return NBODY_E_INVAL;
   for (int b = 0; b < kBuckets; ++b)
-    if (tiles[b] < 0 || tiles[b] > 3) return fail(c, NBODY_E_INVAL, "tile code %d out of range", tiles[b]);
+    if (tiles[b] < 0 || tiles[b] > 1) return fail(c, NBODY_E_INVAL, "tile code %d out of range (0 or 1)", tiles[b]);
   for (int b = 0; b < kBuckets; ++b) c->tiles[b] = tiles[b];
   return NBODY_OK;
 }

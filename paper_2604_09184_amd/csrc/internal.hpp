@@ -4,9 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
-namespace nbk {
+#include "device.hpp"
 
-constexpr int kBlock = 256;   // threads per workgroup of the body-parallel kernels (4 wave64)
+namespace nbk {
 
 struct KickArgs {
   const double4 *xm;
@@ -62,12 +62,14 @@ hipError_t launch_drift_vjp(const double4 *xm, const double4 *v, int n, double d
 
 // batched.hip
 constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048
+constexpr int kBatchedWaves = 8;   // waves per workgroup of the batched kernel
 struct BatchLaunch {
   const int64_t *offs;
   const int32_t *order;
-  const int32_t *cfg;
-  int nsys, nsteps, forced, grid;
+  const int32_t *cfg;   // [kBuckets] 1 = one wave per system, 0 = one workgroup per system
+  int nsys, nsteps, grid;
   double4 *xm, *v, *thr;
+  double4 *part;        // [grid][2 * kBatchedWaves][64]
   unsigned long long *npairs;
   unsigned *queue;
   double G, m0, dt, f_in, cH, cV, n1, n2dt;
@@ -75,131 +77,8 @@ struct BatchLaunch {
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t st);
 hipError_t batched_occupancy(int *blocks_per_cu);
 int batched_max_group_n();
-hipError_t launch_gather(const double4 *xm, const double4 *v, const int64_t *src, const int64_t *dst,
-                         int m, double4 *txm, double4 *tv, hipStream_t st);
 int batched_max_wave_n();
 
 inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace nbk
-
-// ------------------------------------------------------------------ device helpers
-namespace nbd {
-
-__device__ __forceinline__ uint32_t hiword(double x) {
-  return (uint32_t)((unsigned long long)__double_as_longlong(x) >> 32);
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    uint32_t w = (uint32_t)__shfl_xor((int)v, o, 64);
-    v = v > w ? v : w;
-  }
-  return v;
-}
-
-// Critical radius and thresholds of one body (the library's definition, see nbody.h):
-// {rc, H, V, T}, T bounding every r^2 that H or V can flag.
-__device__ __forceinline__ double4 body_thresholds(double4 p, double4 q, double m0, double cH,
-                                                   double cV, double n1, double n2dt) {
-  const double r2 = fma(p.z, p.z, fma(p.y, p.y, p.x * p.x));
-  const double mu = p.w / m0;
-  const double vv = fma(q.z, q.z, fma(q.y, q.y, q.x * q.x));
-  const double H = (cH * ((r2 * r2) * r2)) * (mu * mu);
-  const double V = cV * vv;
-  const double rhill = sqrt(r2) * cbrt(mu / 3.0);
-  const double a = n1 * rhill, b = n2dt * sqrt(vv);
-  const double rc = a > b ? a : b;
-  const double c = cbrt(H);
-  const double T = (V > c ? V : c) * (1.0 + 0x1p-30);
-  return make_double4(rc, H, V, T);
-}
-
-// Exact binary64 close-encounter predicate (the library's definition, see nbody.h).
-__device__ __forceinline__ bool close_exact(double r2, double Hi, double Hj, double Vi, double Vj) {
-  const double H = Hi > Hj ? Hi : Hj;
-  const double V = Vi > Vj ? Vi : Vj;
-  return ((r2 * r2) * r2 < H) || (r2 < V);
-}
-
-// Pair weight for a close pair: w = K/r^3 - K'(r)/r^2 with the changeover
-// K(y) = y^2/(2y^2-2y+1), y = clamp((r - f_in rc)/((1-f_in) rc), 0, 1).
-__device__ __forceinline__ double close_weight(double r2, double rcij, double f_in) {
-  const double r = sqrt(r2);
-  const double r3 = r2 * r;
-  const double span = (1.0 - f_in) * rcij;
-  double y = (r - f_in * rcij) / span;
-  if (y <= 0.0) return 0.0;
-  if (y >= 1.0) return 1.0 / r3;
-  const double D = 2.0 * y * y - 2.0 * y + 1.0;
-  const double K = y * y / D;
-  const double dKdy = 2.0 * y * (1.0 - y) / (D * D);
-  return K / r3 - (dKdy / span) / r2;
-}
-
-// m * r^-3 from the hardware reciprocal-square-root seed (relative error about 2^-24) and the
-// second-order expansion of (1 - e)^(-3/2), e = 1 - r2 y^2: result within a few ulp.
-// c15 = 1.5 and c1875 = 1.875 arrive as kernel arguments: kept in loop-invariant registers
-// instead of being re-materialised per pair (no literal operands in 64-bit VOP3 on gfx9).
-__device__ __forceinline__ double m_rinv3(double r2, double m, double c15, double c1875) {
-  const double y = __builtin_amdgcn_rsq(r2);
-  const double t = y * y;
-  const double e = fma(-r2, t, 1.0);
-  const double p = fma(e, c1875, c15);
-  const double my3 = (m * y) * t;
-  return fma(my3 * e, p, my3);
-}
-
-// r^-3 alone (equal-mass systems multiply by m once after the sum).
-__device__ __forceinline__ double rinv3(double r2, double c15, double c1875) {
-  const double y = __builtin_amdgcn_rsq(r2);
-  const double t = y * y;
-  const double e = fma(-r2, t, 1.0);
-  const double p = fma(e, c1875, c15);
-  const double y3 = y * t;
-  return fma(y3 * e, p, y3);
-}
-
-// Split precision: r^-3 in binary32 (offsets and r^2 stay binary64), scaled by m in binary64.
-__device__ __forceinline__ double m_rinv3_split(double r2, double m) {
-  const float f = (float)r2;
-  const float y = __builtin_amdgcn_rsqf(f);
-  const float y3 = (y * y) * y;
-  return m * (double)y3;
-}
-
-
-// Deterministic workgroup sum of NV doubles per thread (fixed tree order); every thread gets the
-// totals. lds must hold NV * kBlock doubles.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&x)[NV], double *lds) {
-  constexpr int B = nbk::kBlock;
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) lds[k * B + t] = x[k];
-  __syncthreads();
-  for (int s = B / 2; s > 0; s >>= 1) {
-    if (t < s) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) lds[k * B + t] += lds[k * B + t + s];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 0; k < NV; ++k) x[k] = lds[k * B];
-  __syncthreads();
-}
-
-// Total momentum from per-block partials, summed in the same order by every workgroup.
-__device__ __forceinline__ void momentum_total(const double4 *__restrict__ mom, int nb, double (&P)[3],
-                                               double *lds) {
-  P[0] = P[1] = P[2] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += nbk::kBlock) {
-    const double4 q = mom[b];
-    P[0] += q.x; P[1] += q.y; P[2] += q.z;
-  }
-  block_sum<3>(P, lds);
-}
-
-}  // namespace nbd
