@@ -106,28 +106,42 @@ __global__ __launch_bounds__(kBlock) void k_scale(const double4 *__restrict__ lv
 
 // lam_x += G * sum of partials (component 3 accumulates dL/dm), napply times: two consecutive
 // kick derivatives at the same positions with the same lam_v give the same increment, so adding
-// one evaluation twice equals evaluating twice, bit for bit.
+// one evaluation twice equals evaluating twice, bit for bit. Same partial-sum layout as
+// k_finalize: 64 bodies per workgroup, four waves over the chunks, added in wave order.
 __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restrict__ part, int S, int n,
                                                          double G, int napply,
                                                          double4 *__restrict__ lam_x) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  double gx = 0.0, gy = 0.0, gz = 0.0, gm = 0.0;
-  int s = 0;
-  for (; s + 8 <= S; s += 8) {
-    double4 q[8];
+  constexpr int W = kBlock / 64;
+  __shared__ double red[W - 1][4][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = blockIdx.x * 64 + lane;
+  const int cs = (S + W - 1) / W;
+  const int s0 = w * cs, s1 = min(S, s0 + cs);
+  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < n) {
+    int s = s0;
+    for (; s + 8 <= s1; s += 8) {
+      double4 q[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) q[k] = part[(size_t)(s + k) * n + i];
+      for (int k = 0; k < 8; ++k) q[k] = part[(size_t)(s + k) * n + i];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { gx += q[k].x; gy += q[k].y; gz += q[k].z; gm += q[k].w; }
+      for (int k = 0; k < 8; ++k) { g[0] += q[k].x; g[1] += q[k].y; g[2] += q[k].z; g[3] += q[k].w; }
+    }
+    for (; s < s1; ++s) {
+      const double4 q = part[(size_t)s * n + i];
+      g[0] += q.x; g[1] += q.y; g[2] += q.z; g[3] += q.w;
+    }
   }
-  for (; s < S; ++s) {
-    const double4 p = part[(size_t)s * n + i];
-    gx += p.x; gy += p.y; gz += p.z; gm += p.w;
-  }
+  if (w > 0)
+    for (int k = 0; k < 4; ++k) red[w - 1][k][lane] = g[k];
+  __syncthreads();
+  if (w > 0 || i >= n) return;
+  for (int q = 0; q < W - 1; ++q)
+    for (int k = 0; k < 4; ++k) g[k] += red[q][k][lane];
   double4 l = lam_x[i];
   for (int k = 0; k < napply; ++k) {
-    l.x += G * gx; l.y += G * gy; l.z += G * gz; l.w += G * gm;
+    l.x += G * g[0]; l.y += G * g[1]; l.z += G * g[2]; l.w += G * g[3];
   }
   lam_x[i] = l;
 }
@@ -138,7 +152,8 @@ hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *per
   hipLaunchKernelGGL(k_scale, dim3(nblocks(n)), dim3(kBlock), 0, st, lam_v, h, n, lam_a);
   hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, perm, lam_a, n,
                      chunk, f_in, part);
-  hipLaunchKernelGGL(k_vjp_finalize, dim3(nblocks(n)), dim3(kBlock), 0, st, part, S, n, G, napply, lam_x);
+  hipLaunchKernelGGL(k_vjp_finalize, dim3(fin_blocks(n)), dim3(kBlock), 0, st, part, S, n, G, napply,
+                     lam_x);
   return hipGetLastError();
 }
 

@@ -413,7 +413,8 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
     TRY(nbody_rcrit(c, n, xm, v, t, stream));
     thr = t;
   }
-  double4 *momA = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
+  const int nbf = fin_blocks(n);   // momentum partials written by the finalize kernel
+  double4 *momA = (double4 *)ensure(c, B_MOM_A, (size_t)nbf * sizeof(double4));
   double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nb * sizeof(double4));
   if (!momA || !momB) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
   KickArgs a;
@@ -436,7 +437,7 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
   HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, X, Vv, nullptr, nullptr, momA, st),
          "step finalize");
   for (int s = 1; s <= nsteps; ++s) {
-    HIPCHK(c, launch_jump_drift(X, Vv, momA, nb, N, h, p.dt, p.m0, mu, nullptr, momB, st), "jump+drift");
+    HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st), "jump+drift");
     HIPCHK(c, launch_jump(X, momB, nb, N, h, p.m0, st), "jump");
     if (a.perm && s % c->locality_every == 0) TRY(locality(c, N, X, st, &a.perm));
     const bool last = s == nsteps;
@@ -517,7 +518,8 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   double4 *S = (double4 *)ensure(c, B_ADJ_STATES, bytes * (4 * (size_t)nsteps + 1));
   double4 *XA = (double4 *)ensure(c, B_XA, bytes);
   double4 *VA = (double4 *)ensure(c, B_VA, bytes);
-  double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
+  const int nbf = fin_blocks(n);   // momentum partials written by the finalize kernel
+  double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)std::max(nb, nbf) * sizeof(double4));
   if (!S || !XA || !VA || !mom) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint states)");
   auto Xs = [&](int s) { return S + (size_t)4 * s * N; };
   auto X1 = [&](int s) { return S + ((size_t)4 * s + 1) * N; };
@@ -539,7 +541,7 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   for (int s = 0; s < nsteps; ++s) {
     if (s == 0) HIPCHK(c, hipMemcpyAsync(Xs(0), XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
     HIPCHK(c, hipMemcpyAsync(V1(s), VA, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    HIPCHK(c, launch_jump(XA, mom, nb, N, h, p.m0, st), "jump");
+    HIPCHK(c, launch_jump(XA, mom, nbf, N, h, p.m0, st), "jump");
     HIPCHK(c, hipMemcpyAsync(X1(s), XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
     HIPCHK(c, launch_drift(XA, VA, N, p.dt, p.G * p.m0, nullptr, st), "drift");
     HIPCHK(c, hipMemcpyAsync(V2(s), VA, bytes, hipMemcpyDeviceToDevice, st), "copy");

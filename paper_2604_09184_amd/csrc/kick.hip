@@ -179,6 +179,9 @@ hipError_t launch_locality(const double4 *xm, int n, float2 *range_part, unsigne
 int locality_cells() { return kCells; }
 
 // ------------------------------------------------------------------ finalize: sum partials
+// One workgroup per 64 bodies: wave w sums chunks [w cs, (w+1) cs) of each body's S partials in
+// chunk order (cs = ceil(S/4)), and wave 0 adds the four sums in wave order. Four waves per body
+// keep enough loads in flight when n is small. Momentum partials: one per 64 bodies.
 __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__ part,
                                                      const double4 *__restrict__ part_ce, int S,
                                                      int n, double G, double h, int napply,
@@ -187,34 +190,45 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
                                                      double4 *__restrict__ acc,
                                                      double4 *__restrict__ acc_ce,
                                                      double4 *__restrict__ mom) {
-  __shared__ double lds[3 * kBlock];
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  double P[3] = {0.0, 0.0, 0.0};
+  constexpr int W = kBlock / 64;
+  __shared__ double red[2][W - 1][3][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = blockIdx.x * 64 + lane;
+  const int cs = (S + W - 1) / W;
+  const int s0 = w * cs, s1 = min(S, s0 + cs);
+  double a[3] = {0.0, 0.0, 0.0};
+  double c[3] = {0.0, 0.0, 0.0};
   if (i < n) {
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    // loads issued eight at a time, summed in chunk order
-    int s = 0;
-    for (; s + 8 <= S; s += 8) {
+    int s = s0;
+    for (; s + 8 <= s1; s += 8) {
       double4 q[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) q[k] = part[(size_t)(s + k) * n + i];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) { ax += q[k].x; ay += q[k].y; az += q[k].z; }
+      for (int k = 0; k < 8; ++k) { a[0] += q[k].x; a[1] += q[k].y; a[2] += q[k].z; }
     }
-    for (; s < S; ++s) {
-      const double4 p = part[(size_t)s * n + i];
-      ax += p.x; ay += p.y; az += p.z;
+    for (; s < s1; ++s) {
+      const double4 q = part[(size_t)s * n + i];
+      a[0] += q.x; a[1] += q.y; a[2] += q.z;
     }
-    ax *= G; ay *= G; az *= G;
-    if (acc) acc[i] = make_double4(ax, ay, az, 0.0);
-    if (acc_ce) {
-      double cx = 0.0, cy = 0.0, cz = 0.0;
-      for (int s = 0; s < S; ++s) {
-        const double4 p = part_ce[(size_t)s * n + i];
-        cx += p.x; cy += p.y; cz += p.z;
+    if (part_ce)
+      for (s = s0; s < s1; ++s) {
+        const double4 q = part_ce[(size_t)s * n + i];
+        c[0] += q.x; c[1] += q.y; c[2] += q.z;
       }
-      acc_ce[i] = make_double4(G * cx, G * cy, G * cz, 0.0);
-    }
+  }
+  if (w > 0)
+    for (int k = 0; k < 3; ++k) { red[0][w - 1][k][lane] = a[k]; red[1][w - 1][k][lane] = c[k]; }
+  __syncthreads();
+  if (w > 0) return;
+  for (int q = 0; q < W - 1; ++q)
+    for (int k = 0; k < 3; ++k) { a[k] += red[0][q][k][lane]; c[k] += red[1][q][k][lane]; }
+  double P[3] = {0.0, 0.0, 0.0};
+  if (i < n) {
+    const double ax = G * a[0], ay = G * a[1], az = G * a[2];
+    if (acc) acc[i] = make_double4(ax, ay, az, 0.0);
+    if (acc_ce) acc_ce[i] = make_double4(G * c[0], G * c[1], G * c[2], 0.0);
     if (v) {
       double4 q = v[i];
       for (int k = 0; k < napply; ++k) {
@@ -228,16 +242,20 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
     }
   }
   if (mom) {
-    block_sum<3>(P, lds);
-    if (threadIdx.x == 0) mom[blockIdx.x] = make_double4(P[0], P[1], P[2], 0.0);
+    // butterfly: every lane ends with the same bits
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) P[k] += __shfl_xor(P[k], o, 64);
+    if (lane == 0) mom[blockIdx.x] = make_double4(P[0], P[1], P[2], 0.0);
   }
 }
 
 hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, int n, double G,
                            double h, int napply, const double4 *xm, double4 *v, double4 *acc,
                            double4 *acc_ce, double4 *mom, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(nblocks(n)), dim3(kBlock), 0, st, part, part_ce, S, n, G, h,
-                     napply, xm, v, acc, acc_ce, mom);
+  hipLaunchKernelGGL(k_finalize, dim3(fin_blocks(n)), dim3(kBlock), 0, st, part, part_ce, S, n, G,
+                     h, napply, xm, v, acc, acc_ce, mom);
   return hipGetLastError();
 }
 
