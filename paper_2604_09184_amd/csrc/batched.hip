@@ -143,7 +143,7 @@ __device__ __forceinline__ void pair_lds(const double4 &xi, const double4 &pj, u
 
 // Adds to acc the accelerations (without G; without m when UNI) on body ii from bodies j0..j1-1
 // in LDS, in ascending j. tw = wave maximum of the prefilter words of the wave's bodies. The
-// j-bodies are read two at a time, so one LDS address serves both.
+// j-bodies are read four at a time, so one LDS address serves all four.
 template <bool UNI>
 __device__ __forceinline__ void kick_rows(const double4 *X, const uint32_t *T,
                                           const double4 *__restrict__ thr, int ii, bool valid,
@@ -151,16 +151,25 @@ __device__ __forceinline__ void kick_rows(const double4 *X, const uint32_t *T,
                                           double c1875, double (&acc)[3], unsigned &npairs,
                                           bool count) {
   const double4 xi = X[ii];
+  // 1.5 held in a VGPR for the whole loop: the expansion's fma already reads 1.875 from an SGPR,
+  // and one VOP3 instruction reads at most one scalar operand
+  double c15v;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(c15v) : "s"(c15));
   int j = j0;
-  for (; j + 2 <= j1; j += 2) {
-    const double4 p0 = X[j], p1 = X[j + 1];
-    const uint32_t t0 = __builtin_amdgcn_readfirstlane(T[j]);
-    const uint32_t t1 = __builtin_amdgcn_readfirstlane(T[j + 1]);
-    pair_lds<UNI>(xi, p0, t0, j, thr, ii, valid, tw, f_in, c15, c1875, acc, npairs, count);
-    pair_lds<UNI>(xi, p1, t1, j + 1, thr, ii, valid, tw, f_in, c15, c1875, acc, npairs, count);
+  for (; j + 4 <= j1; j += 4) {
+    double4 p[4];
+    uint32_t t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      p[q] = X[j + q];
+      t[q] = __builtin_amdgcn_readfirstlane(T[j + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      pair_lds<UNI>(xi, p[q], t[q], j + q, thr, ii, valid, tw, f_in, c15v, c1875, acc, npairs, count);
   }
-  if (j < j1)
-    pair_lds<UNI>(xi, X[j], __builtin_amdgcn_readfirstlane(T[j]), j, thr, ii, valid, tw, f_in, c15,
+  for (; j < j1; ++j)
+    pair_lds<UNI>(xi, X[j], __builtin_amdgcn_readfirstlane(T[j]), j, thr, ii, valid, tw, f_in, c15v,
                   c1875, acc, npairs, count);
 }
 
