@@ -114,11 +114,26 @@ int nbody_drift(nbody_ctx *ctx, int64_t n, double *xm, double *v, double h, uint
  * nsteps steps B(dt/2) C(dt/2) A(dt) C(dt/2) B(dt/2). thr: NULL = computed from the state at
  * call start into the context; otherwise used as given. thr is held fixed for the call, so a
  * call is exactly the composition of its steps and consecutive kicks at the same positions are
- * evaluated once (v += h a applied twice). If pairs is not NULL the encounter list at the final
- * positions is written as in nbody_encounters.
+ * evaluated once (v += h a applied twice). If count is not NULL the encounter list at the final
+ * positions is written to pairs/cap/count as in nbody_encounters. step_counts (device int64
+ * [nsteps + 1], may be NULL) receives the number of close pairs (same predicate) at each of the
+ * nsteps + 1 force evaluations: the initial positions, then the positions of each step's second
+ * kick; the counts come from the kick's own pair loop.
  */
 int nbody_step(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr, int32_t nsteps,
-               int32_t *pairs, int64_t cap, int64_t *count, void *stream);
+               int32_t *pairs, int64_t cap, int64_t *count, int64_t *step_counts, void *stream);
+
+/*
+ * Input check before integrating a state. The method has no softening, so a body at the central
+ * mass (r_i = 0 in eq. Ha) or two bodies at one position (r_ij = 0 in eq. Hb) are invalid input.
+ * result (device int64 [2]) receives {i, reason} for the smallest body index i with a problem
+ * (and the smallest reason code for that index), or {-1, 0}:
+ *   1 = a non-finite position, mass or velocity component;   2 = negative mass;
+ *   3 = position exactly at the central mass;                4 = same position as a body j > i.
+ * The coincidence test is an all-pairs scan (about the cost of one kick). Deterministic.
+ */
+int nbody_validate(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, int64_t *result,
+                   void *stream);
 
 /*
  * Diagnostics (device out[8]): E (full Newtonian energy in democratic heliocentric form),

@@ -58,7 +58,8 @@ EXPORTS = {
     "nbody_encounters": [_I64, _P, _P, _P, _I64, _P, _P],
     "nbody_jump": [_I64, _P, _P, _D, _P],
     "nbody_drift": [_I64, _P, _P, _D, _P, _P],
-    "nbody_step": [_I64, _P, _P, _P, _I32, _P, _I64, _P, _P],
+    "nbody_step": [_I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P],
+    "nbody_validate": [_I64, _P, _P, _P, _P],
     "nbody_energy": [_I64, _P, _P, _P, _P, _P],
     "nbody_bench_pairs": [_I64, _P, _P, _I32, _P, _P],
     "nbody_kick_vjp": [_I64, _P, _P, _D, _P, _P, _P],
@@ -201,20 +202,34 @@ class Context:
                                       _stream()), "nbody_drift")
         return status
 
-    def step(self, xm, v, nsteps, thr=None, pairs_cap=None):
-        """nsteps steps in place. With pairs_cap, also returns the final encounter list."""
+    def step(self, xm, v, nsteps, thr=None, pairs_cap=None, step_counts=False):
+        """nsteps steps in place. With pairs_cap, also returns the final encounter list (pairs, count).
+        With step_counts, also returns the int64 tensor of close-pair counts at the nsteps + 1 force
+        evaluations. Returns None, (pairs, count), counts or ((pairs, count), counts)."""
         _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
         n = xm.shape[0]
+        sc = torch.zeros(int(nsteps) + 1, dtype=torch.int64, device=xm.device) if step_counts else None
         if pairs_cap is None:
             self._check(lib().nbody_step(self._h, n, _ptr(xm), _ptr(v), _ptr(thr), int(nsteps), None, 0,
-                                         None, _stream()), "nbody_step")
-            return None
+                                         None, _ptr(sc), _stream()), "nbody_step")
+            return sc
         count = torch.zeros(1, dtype=torch.int64, device=xm.device)
         pairs = torch.empty((max(pairs_cap, 1), 2), dtype=torch.int32, device=xm.device)
         self._check(lib().nbody_step(self._h, n, _ptr(xm), _ptr(v), _ptr(thr), int(nsteps), _ptr(pairs),
-                                     pairs_cap, _ptr(count), _stream()), "nbody_step")
+                                     pairs_cap, _ptr(count), _ptr(sc), _stream()), "nbody_step")
         c = int(count.item())
-        return pairs[:min(c, pairs_cap)], c
+        res = (pairs[:min(c, pairs_cap)], c)
+        return (res, sc) if step_counts else res
+
+    def validate(self, xm, v):
+        """(index, reason) of the first invalid body, or (-1, 0); reasons: 1 non-finite value,
+        2 negative mass, 3 at the central mass, 4 same position as a later body."""
+        _body(xm, "xm"); _body(v, "v")
+        out = torch.empty(2, dtype=torch.int64, device=xm.device)
+        self._check(lib().nbody_validate(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(out), _stream()),
+                    "nbody_validate")
+        o = out.cpu().tolist()
+        return int(o[0]), int(o[1])
 
     def energy(self, xm, v, thr):
         out = torch.empty(8, dtype=torch.float64, device=xm.device)

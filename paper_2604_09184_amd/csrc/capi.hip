@@ -26,7 +26,7 @@ struct Buf {
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
-             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_NUM };
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_NUM };
 
 }  // namespace
 
@@ -391,7 +391,7 @@ int nbody_drift(nbody_ctx *c, int64_t n, double *xm, double *v, double h, uint32
 }
 
 int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr, int32_t nsteps,
-               int32_t *pairs, int64_t cap, int64_t *count, void *stream) {
+               int32_t *pairs, int64_t cap, int64_t *count, int64_t *step_counts, void *stream) {
   TRY(check_n(c, n));
   TRY(check_dev(c, xm, "xm", true));
   TRY(check_dev(c, v, "v", true));
@@ -403,7 +403,12 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
     if (cap < 0) return fail(c, NBODY_E_INVAL, "cap < 0");
     if (cap > 0) TRY(check_dev(c, pairs, "pairs", true));
   }
+  TRY(check_dev(c, step_counts, "step_counts", false));
+  const bool counting = step_counts != nullptr;
+  unsigned long long *sc = (unsigned long long *)step_counts;
   hipStream_t st = (hipStream_t)stream;
+  if (counting)
+    HIPCHK(c, hipMemsetAsync(step_counts, 0, ((size_t)nsteps + 1) * sizeof(int64_t), st), "memset");
   const nbody_params &p = c->p;
   const int N = (int)n;
   const int nb = nblocks(n);
@@ -418,7 +423,11 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
   double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nb * sizeof(double4));
   if (!momA || !momB) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
   KickArgs a;
-  TRY(make_kick_args(c, N, xm, thr, true, false, emit, a));
+  TRY(make_kick_args(c, N, xm, thr, true, false, emit || counting, a));
+  // counting-only evaluations: the emission path with no partner slots (partners counted, not kept)
+  KickArgs ac = a;
+  ac.R = 0;
+  ac.rowbuf = nullptr;
   const bool split = p.precision == NBODY_PREC_SPLIT;
   const double h = 0.5 * p.dt;
   const double mu = p.G * p.m0;
@@ -426,26 +435,47 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
   double4 *Vv = (double4 *)v;
   TRY(locality(c, N, X, st, &a.perm));
   TRY(mass_check(c, N, X, st, &a.uni));
+  ac.perm = a.perm;
+  ac.uni = a.uni;
   if (nsteps == 0) {
-    if (emit) {
-      HIPCHK(c, launch_pairs(a, false, true, false, false, st), "step pairs");
-      return emit_list(c, a, pairs, cap, count, st);
-    }
+    if (emit || counting) HIPCHK(c, launch_pairs(emit ? a : ac, false, true, false, false, st), "step pairs");
+    if (counting)
+      HIPCHK(c, launch_finalize(nullptr, nullptr, a.nchunk, N, p.G, h, 1, X, nullptr, nullptr, nullptr,
+                                nullptr, st, a.cnt, sc), "step count");
+    if (emit) return emit_list(c, a, pairs, cap, count, st);
     return NBODY_OK;
   }
-  HIPCHK(c, launch_pairs(a, true, false, false, split, st), "step pairs");
-  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, X, Vv, nullptr, nullptr, momA, st),
-         "step finalize");
+  HIPCHK(c, launch_pairs(counting ? ac : a, true, counting, false, split, st), "step pairs");
+  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, X, Vv, nullptr, nullptr, momA, st,
+                            counting ? a.cnt : nullptr, sc), "step finalize");
   for (int s = 1; s <= nsteps; ++s) {
     HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st), "jump+drift");
     HIPCHK(c, launch_jump(X, momB, nb, N, h, p.m0, st), "jump");
-    if (a.perm && s % c->locality_every == 0) TRY(locality(c, N, X, st, &a.perm));
+    if (a.perm && s % c->locality_every == 0) {
+      TRY(locality(c, N, X, st, &a.perm));
+      ac.perm = a.perm;
+    }
     const bool last = s == nsteps;
-    HIPCHK(c, launch_pairs(a, true, last && emit, false, split, st), "step pairs");
+    const bool em = last && emit;
+    HIPCHK(c, launch_pairs(em ? a : ac, true, em || counting, false, split, st), "step pairs");
     HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, last ? 1 : 2, X, Vv, nullptr,
-                              nullptr, momA, st), "step finalize");
+                              nullptr, momA, st, counting ? a.cnt : nullptr, counting ? sc + s : nullptr),
+           "step finalize");
   }
   if (emit) return emit_list(c, a, pairs, cap, count, st);
+  return NBODY_OK;
+}
+
+int nbody_validate(nbody_ctx *c, int64_t n, const double *xm, const double *v, int64_t *result,
+                   void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, result, "result", true));
+  unsigned long long *key = (unsigned long long *)ensure(c, B_VKEY, sizeof(unsigned long long));
+  if (!key) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (validate)");
+  HIPCHK(c, launch_validate((const double4 *)xm, (const double4 *)v, (int)n, key, result, (hipStream_t)stream),
+         "validate");
   return NBODY_OK;
 }
 

@@ -31,13 +31,16 @@ hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool 
                         hipStream_t st);
 hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, int n, double G,
                            double h, int napply, const double4 *xm, double4 *v, double4 *acc,
-                           double4 *acc_ce, double4 *mom, hipStream_t st);
+                           double4 *acc_ce, double4 *mom, hipStream_t st, const int *cnt = nullptr,
+                           unsigned long long *count_out = nullptr);
 hipError_t launch_locality(const double4 *xm, int n, float2 *range_part, unsigned short *cell,
                            unsigned *count, unsigned *cursor, int *perm, hipStream_t st);
 int locality_cells();
 hipError_t launch_mass_check(const double4 *xm, int n, double2 *part, double2 *uni, hipStream_t st);
 hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
                        int64_t *rowtot, int64_t *bsum, hipStream_t st);
+hipError_t launch_validate(const double4 *xm, const double4 *v, int n, unsigned long long *key,
+                           int64_t *out, hipStream_t st);
 hipError_t launch_energy(const double4 *xm, const double4 *v, const double4 *thr, int n, double G,
                          double m0, double f_in, double4 *eparts, double *out, hipStream_t st);
 

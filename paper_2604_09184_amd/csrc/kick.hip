@@ -182,6 +182,9 @@ int locality_cells() { return kCells; }
 // One workgroup per 64 bodies: wave w sums chunks [w cs, (w+1) cs) of each body's S partials in
 // chunk order (cs = ceil(S/4)), and wave 0 adds the four sums in wave order. Four waves per body
 // keep enough loads in flight when n is small. Momentum partials: one per 64 bodies.
+// cnt (may be null): per-(chunk, body) numbers of close partners j > i; their total is added to
+// *count_out (integer atomics: the total does not depend on the order). part may be null
+// (counting only).
 __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__ part,
                                                      const double4 *__restrict__ part_ce, int S,
                                                      int n, double G, double h, int napply,
@@ -189,7 +192,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
                                                      double4 *__restrict__ v,
                                                      double4 *__restrict__ acc,
                                                      double4 *__restrict__ acc_ce,
-                                                     double4 *__restrict__ mom) {
+                                                     double4 *__restrict__ mom,
+                                                     const int *__restrict__ cnt,
+                                                     unsigned long long *__restrict__ count_out) {
   constexpr int W = kBlock / 64;
   __shared__ double red[2][W - 1][3][64];
   const int lane = threadIdx.x & 63;
@@ -197,6 +202,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
   const int i = blockIdx.x * 64 + lane;
   const int cs = (S + W - 1) / W;
   const int s0 = w * cs, s1 = min(S, s0 + cs);
+  if (cnt) {
+    unsigned long long t = 0;
+    if (i < n)
+      for (int s = s0; s < s1; ++s) t += (unsigned)cnt[(size_t)s * n + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0 && t) atomicAdd(count_out, t);
+  }
+  if (!part) return;
   double a[3] = {0.0, 0.0, 0.0};
   double c[3] = {0.0, 0.0, 0.0};
   if (i < n) {
@@ -253,9 +267,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
 
 hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, int n, double G,
                            double h, int napply, const double4 *xm, double4 *v, double4 *acc,
-                           double4 *acc_ce, double4 *mom, hipStream_t st) {
+                           double4 *acc_ce, double4 *mom, hipStream_t st, const int *cnt,
+                           unsigned long long *count_out) {
   hipLaunchKernelGGL(k_finalize, dim3(fin_blocks(n)), dim3(kBlock), 0, st, part, part_ce, S, n, G,
-                     h, napply, xm, v, acc, acc_ce, mom);
+                     h, napply, xm, v, acc, acc_ce, mom, cnt, count_out);
   return hipGetLastError();
 }
 
@@ -365,6 +380,63 @@ hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *
   if (pairs && cap > 0)
     hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kBlock), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
                        a.cnt, a.rowbuf, a.R, rowtot, bsum, pairs, cap);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ input validation
+// Problems are reported as key = (index << 3) | reason, folded with atomicMin: the smallest
+// index wins, then the smallest reason, whatever the order in which threads find them.
+__device__ __forceinline__ void report(unsigned long long *key, long long i, unsigned reason) {
+  atomicMin(key, ((unsigned long long)i << 3) | reason);
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate_bodies(const double4 *__restrict__ xm,
+                                                            const double4 *__restrict__ v, int n,
+                                                            unsigned long long *__restrict__ key) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = xm[i];
+  const double4 q = v[i];
+  const bool finite = isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w) &&
+                      isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
+  if (!finite) report(key, i, 1);
+  else if (p.w < 0.0) report(key, i, 2);
+  else if (p.x == 0.0 && p.y == 0.0 && p.z == 0.0) report(key, i, 3);
+}
+
+// Coincident bodies: lane i against the wave-uniform j of its chunk, j > i.
+__global__ __launch_bounds__(kBlock) void k_validate_pairs(const double4 *__restrict__ xm, int n,
+                                                           int chunk,
+                                                           unsigned long long *__restrict__ key) {
+  const int i0 = blockIdx.x * kBlock + threadIdx.x;
+  const int i = i0 < n ? i0 : n - 1;
+  const double4 p = xm[i];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  bool hit = false;
+  for (int j = j0; j < j1; ++j) {
+    const double4 q = xm[j];
+    hit |= (j > i) & (q.x == p.x) & (q.y == p.y) & (q.z == p.z);
+  }
+  if (hit && i0 < n) report(key, i, 4);
+}
+
+__global__ void k_validate_out(const unsigned long long *__restrict__ key, int64_t *__restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long k = *key;
+  out[0] = k == ~0ull ? -1 : (int64_t)(k >> 3);
+  out[1] = k == ~0ull ? 0 : (int64_t)(k & 7);
+}
+
+hipError_t launch_validate(const double4 *xm, const double4 *v, int n, unsigned long long *key,
+                           int64_t *out, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(key, 0xff, sizeof(unsigned long long), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_validate_bodies, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, n, key);
+  const int chunk = 1024;
+  hipLaunchKernelGGL(k_validate_pairs, dim3(nblocks(n), (n + chunk - 1) / chunk), dim3(kBlock), 0, st,
+                     xm, n, chunk, key);
+  hipLaunchKernelGGL(k_validate_out, dim3(1), dim3(64), 0, st, key, out);
   return hipGetLastError();
 }
 

@@ -28,9 +28,16 @@ def nb():
     return nb
 
 
-def ensemble(sizes, seed=77):
+def ensemble(sizes, seed=77, powerlaw_every=0):
+    """Equal-mass disks; with powerlaw_every = k, every k-th system has dN/dm ~ m^-2.5 masses."""
     ss = np.random.SeedSequence(seed).spawn(len(sizes))
-    parts = [diskgen.make_disk(diskgen.Disk(n, 0.5, 4.0, 0.01, 0.005, 2.0, seed=ss[k])) for k, n in enumerate(sizes)]
+    parts = []
+    for k, n in enumerate(sizes):
+        if powerlaw_every and k % powerlaw_every == 0:
+            d = diskgen.Disk(n, 0.5, 4.0, 0.01, 0.005, None, powerlaw=(2.5, 1e-3, 1e-1), seed=ss[k])
+        else:
+            d = diskgen.Disk(n, 0.5, 4.0, 0.01, 0.005, 2.0, seed=ss[k])
+        parts.append(diskgen.make_disk(d))
     offs = np.zeros(len(sizes) + 1, dtype=np.int64)
     offs[1:] = np.cumsum(sizes)
     x = np.concatenate([p["x"] for p in parts]); v = np.concatenate([p["v"] for p in parts])
@@ -47,13 +54,16 @@ def rel_state_err(a, b):
     return (np.abs(a - b).max(1) / np.linalg.norm(b, axis=1)).max()
 
 
+@pytest.mark.parametrize("masses", ["equal", "mixed"])
 @pytest.mark.parametrize("tile", [0, 1])
-def test_batched_matches_single_system_runs(nb, tile):
-    say(f"batched tile={tile} sizes={SIZES}")
+def test_batched_matches_single_system_runs(nb, tile, masses):
+    say(f"batched tile={tile} masses={masses} sizes={SIZES}")
     p = diskgen.PARAMS
     ctx = nb.Context(nb.Params(**p))
     ctx.set_batched_tiles([tile] * 6)
-    offs, x, v, m = ensemble(SIZES)
+    offs, x, v, m = ensemble(SIZES, powerlaw_every=2 if masses == "mixed" else 0)
+    if masses == "mixed":
+        assert np.ptp(m[offs[2]:offs[3]]) > 0 and np.ptp(m[offs[1]:offs[2]]) == 0
     X, V = to_dev(x, v, m)
     k = 6
     npairs = ctx.step_batched(offs, X, V, k, count_pairs=True).cpu().numpy()

@@ -277,6 +277,72 @@ def test_step_zero_steps_lists_pairs(ctx):
     np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("case", ["disk2048", "cluster4096"])
+def test_step_counts_match_oracle(ctx, case):
+    """Close-pair counts at each of the nsteps + 1 force evaluations equal the oracle's list
+    lengths at the oracle's states; counting changes no bit of the state."""
+    say(f"step counts {case}")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048") if case == "disk2048" else cluster_disk(4096, 300)
+    k = 5 if case == "disk2048" else 2
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    Xa, Va = X.clone(), V.clone()
+    (pairs, count), sc = ctx.step(Xa, Va, k, thr=thr, pairs_cap=200000, step_counts=True)
+    Xb, Vb = X.clone(), V.clone()
+    ctx.step(Xb, Vb, k, thr=thr)
+    Xc, Vc = X.clone(), V.clone()
+    sc_only = ctx.step(Xc, Vc, k, thr=thr, step_counts=True)
+    torch.cuda.synchronize()
+    assert torch.equal(Xa, Xb) and torch.equal(Va, Vb)
+    assert torch.equal(Xa, Xc) and torch.equal(Va, Vc)
+    sc = sc.cpu().numpy()
+    np.testing.assert_array_equal(sc, sc_only.cpu().numpy())
+    assert sc[-1] == count
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov = d["x"].copy(), d["v"].copy()
+    ref = [len(oracle.encounters(ox, othr))]
+    for s in range(k):
+        ox, ov, _ = oracle.step(ox, ov, d["m"], p, 1, thr=othr)
+        ref.append(len(oracle.encounters(ox, othr)))
+    say(f"  counts {sc.tolist()}")
+    np.testing.assert_array_equal(sc, np.array(ref))
+    # no steps: the count at the given positions
+    sc0 = ctx.step(X.clone(), V.clone(), 0, thr=thr, step_counts=True).cpu().numpy()
+    np.testing.assert_array_equal(sc0, ref[:1])
+
+
+def test_validate_reports_first_problem(ctx):
+    say("validate")
+    d = diskgen.workload("disk2048", n=1000)
+    xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+
+    def run(mod):
+        a, b = xm.copy(), v4.copy()
+        mod(a, b)
+        return ctx.validate(torch.tensor(a, device=DEV), torch.tensor(b, device=DEV))
+
+    assert run(lambda a, b: None) == (-1, 0)
+    assert run(lambda a, b: a.__setitem__((500, 1), np.nan)) == (500, 1)
+    assert run(lambda a, b: b.__setitem__((42, 2), np.inf)) == (42, 1)
+
+    def two(a, b):
+        a[300, 3] = -1e-9
+        a[700, 0] = np.nan
+    assert run(two) == (300, 2)
+    assert run(lambda a, b: a.__setitem__((600, slice(0, 3)), 0.0)) == (600, 3)
+
+    def dup(a, b):
+        a[789, :3] = a[123, :3]
+    assert run(dup) == (123, 4)
+
+    def both(a, b):          # index 5 has a duplicate later and a negative mass: smallest reason
+        a[900, :3] = a[5, :3]
+        a[5, 3] = -1.0
+    assert run(both) == (5, 2)
+    assert ctx.validate(torch.tensor(xm[:1], device=DEV), torch.tensor(v4[:1], device=DEV)) == (-1, 0)
+
+
 def test_energy_matches_oracle(ctx):
     say("energy n=2048")
     p = diskgen.PARAMS
