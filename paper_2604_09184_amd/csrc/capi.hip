@@ -644,26 +644,27 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
   for (int b = kBuckets - 1; b >= 0 && rc == NBODY_OK; --b) {
     if (nmax[b] == 0 || nmax[b] > batched_max_wave_n()) continue;
     const int incumbent = trial[b];
-    double t_code[2] = {1e300, 1e300};
-    for (int code = 0; code < 2 && rc == NBODY_OK; ++code) {
-      trial[b] = code;
-      for (int rep = 0; rep < 2 && rc == NBODY_OK; ++rep) {   // rep 0 warms up
-        hipError_t e = hipMemcpyAsync(txm, xm, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(tv, v, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipEventRecord(e0, st);
-        if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
-        rc = run_batched(c, nsys, trial, txm, tv, nsteps, nullptr, st);
-        if (rc != NBODY_OK) break;
-        float ms = 0.f;
-        e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) { rc = hip_fail(c, e, "autotune timing"); break; }
-        if (rep == 1) t_code[code] = ms;
-      }
+    const int other = 1 - incumbent;
+    // a warm-up run, then incumbent, other, other, incumbent: the clock drifts upward during the
+    // first runs, and this order cancels a linear drift
+    const int seq[5] = {incumbent, incumbent, other, other, incumbent};
+    double t_code[2] = {0.0, 0.0};
+    for (int r = 0; r < 5 && rc == NBODY_OK; ++r) {
+      trial[b] = seq[r];
+      hipError_t e = hipMemcpyAsync(txm, xm, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(tv, v, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
+      rc = run_batched(c, nsys, trial, txm, tv, nsteps, nullptr, st);
+      if (rc != NBODY_OK) break;
+      float ms = 0.f;
+      e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) { rc = hip_fail(c, e, "autotune timing"); break; }
+      if (r > 0) t_code[seq[r]] += ms;
     }
     // the other tile must win by more than the run-to-run spread to replace the incumbent
-    const int other = 1 - incumbent;
     trial[b] = t_code[other] < 0.97 * t_code[incumbent] ? other : incumbent;
   }
   (void)hipEventDestroy(e0);

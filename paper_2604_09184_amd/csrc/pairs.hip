@@ -4,22 +4,108 @@
 // (blockIdx.y). All lanes of a wave visit the same j, so the j-body (x, y, z, m) and its
 // threshold are wave-uniform and arrive through scalar loads into SGPRs: no LDS traffic and no
 // per-lane loads inside the loop. The per-pair fast path is binary64 FMA work plus one
-// quarter-rate reciprocal-square-root seed; close-encounter handling runs only for lanes whose r^2
-// passes a conservative wave-level bound (one integer compare per pair).
+// quarter-rate reciprocal-square-root seed. Close-encounter handling is reached in two
+// conservative stages: a screen of 64 j at a time against the bounding box of the wave's bodies
+// (a few vector instructions per 64 j), then, for the j it keeps, a per-pair integer compare.
 #include "internal.hpp"
 
 namespace nbk {
 using namespace nbd;
 
 // ------------------------------------------------------------------ pair kernel
+// Wave minimum / maximum of a double, returned as a wave-uniform (scalar register) value.
+__device__ __forceinline__ double uniform_f64(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return uniform_f64(v);
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return uniform_f64(v);
+}
+
+// The close-pair part of one pair (i, j) whose j passed the block screen: the per-pair prefilter
+// hi(r2) <= max(T_i, T_j), then the exact predicate, the changeover weight and the emission.
+template <bool FORCE, bool EMIT, bool CE, bool UNI>
+__device__ __forceinline__ void close_part(const double4 *__restrict__ thr, int ii, bool valid,
+                                           uint32_t tw, int j, int n, double f_in,
+                                           int *__restrict__ rowbuf, int R, double r2, double dx,
+                                           double dy, double dz, double mj, double &s,
+                                           double (&ce)[3], int &nc) {
+  const uint32_t tj = hiword(thr[j].w);
+  const uint32_t U = tw > tj ? tw : tj;
+  if (hiword(r2) <= U) {
+    if (j == ii) {
+      s = 0.0;
+    } else {
+      const double4 ti = thr[ii];
+      const double4 tq = thr[j];
+      if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
+        if (FORCE) {
+          const double w = close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
+          const double sn = UNI ? w : mj * w;
+          if (CE) {
+            const double ds = s - sn;
+            ce[0] = fma(ds, dx, ce[0]);
+            ce[1] = fma(ds, dy, ce[1]);
+            ce[2] = fma(ds, dz, ce[2]);
+          }
+          s = sn;
+        }
+        if (EMIT && valid && j > ii) {
+          if (nc < R) rowbuf[((size_t)blockIdx.y * R + nc) * n + ii] = j;
+          ++nc;
+        }
+      }
+    }
+  }
+}
+
+// One pair of the force loop: r^-3 on the fast path; close_part only for a screened-in j.
+template <bool EMIT, bool CE, bool SPLIT, bool UNI>
+__device__ __forceinline__ void pair_force(const double4 *__restrict__ thr, const double4 &pi,
+                                           const double4 &pj, int ii, bool valid, uint32_t tw, int j,
+                                           int n, double f_in, int *__restrict__ rowbuf, int R,
+                                           double c15, double c1875, bool screened, double (&a)[3],
+                                           double (&ce)[3], int &nc) {
+  const double dx = pj.x - pi.x;
+  const double dy = pj.y - pi.y;
+  const double dz = pj.z - pi.z;
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  const double mj = UNI ? 1.0 : pj.w;
+  double s = SPLIT ? m_rinv3_split(r2, mj) : (UNI ? rinv3(r2, c15, c1875) : m_rinv3(r2, mj, c15, c1875));
+  if (screened)
+    close_part<true, EMIT, CE, UNI>(thr, ii, valid, tw, j, n, f_in, rowbuf, R, r2, dx, dy, dz, mj, s,
+                                    ce, nc);
+  a[0] = fma(s, dx, a[0]);
+  a[1] = fma(s, dy, a[1]);
+  a[2] = fma(s, dz, a[2]);
+}
+
 // FORCE: accumulate accelerations; EMIT: record close partners j > i; CE: accumulate the
 // complementary close-encounter acceleration; SPLIT: binary32 r^-3 core.
 // perm (may be null) maps lanes to bodies. Every body's sum over j is formed in the same order
 // whatever lane computes it, so the permutation changes no result bit; it only groups spatially
-// close bodies into a wave, which keeps the wave-level prefilter of close pairs from firing for
-// j far from all of them.
+// close bodies into a wave, which keeps the bounding box of the wave small and the screen below
+// selective.
 // uni (may be null) = {1, m} when every body has the same mass m: the loop then sums r^-3 d and
 // multiplies by m once (one multiply less per pair), otherwise {0, 0}.
+//
+// Block screen: the j-range is taken 64 bodies at a time; lane l tests j = jb + l against the
+// bounding box of the wave's 64 i-bodies. If even the box distance d2 has hi(d2) >= U_j + 2, no
+// pair (i, j) of the wave can pass the per-pair prefilter: the computed r2 of any such pair is at
+// least d2 up to a few ulp, and one unit of the high word is a relative 2^-20. Those j run the
+// fast path only; the ballot of the others selects, per j, the uniform branch into close_part.
+// The arithmetic of every pair is the same on both paths, so the screen changes no result bit.
 template <bool FORCE, bool EMIT, bool CE, bool SPLIT, bool UNI>
 __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
                                            const double4 *__restrict__ thr, double4 pi, int ii,
@@ -27,53 +113,64 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
                                            double f_in, int *__restrict__ rowbuf, int R,
                                            double c15, double c1875, double (&a)[3],
                                            double (&ce)[3], int &nc) {
-#pragma unroll 2
-  for (int j = j0; j < j1; ++j) {
-    const double4 pj = xm[j];
-    const uint32_t tj = hiword(thr[j].w);
-    const uint32_t U = tw > tj ? tw : tj;
-    const double dx = pj.x - pi.x;
-    const double dy = pj.y - pi.y;
-    const double dz = pj.z - pi.z;
-    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    const double mj = UNI ? 1.0 : pj.w;
-    double s = 0.0;
-    if (FORCE) s = SPLIT ? m_rinv3_split(r2, mj) : (UNI ? rinv3(r2, c15, c1875) : m_rinv3(r2, mj, c15, c1875));
-    if (hiword(r2) <= U) {
-      if (j == ii) {
-        s = 0.0;
-      } else {
-        const double4 ti = thr[ii];
-        const double4 tq = thr[j];
-        if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
-          if (FORCE) {
-            const double w = close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
-            const double sn = UNI ? w : mj * w;
-            if (CE) {
-              const double ds = s - sn;
-              ce[0] = fma(ds, dx, ce[0]);
-              ce[1] = fma(ds, dy, ce[1]);
-              ce[2] = fma(ds, dz, ce[2]);
-            }
-            s = sn;
-          }
-          if (EMIT && valid && j > ii) {
-            if (nc < R) rowbuf[((size_t)blockIdx.y * R + nc) * n + ii] = j;
-            ++nc;
-          }
-        }
+  const int lane = threadIdx.x & 63;
+  // lanes past n hold body n - 1, a real body: the box stays conservative
+  const double bx0 = wave_min_f64(pi.x), bx1 = wave_max_f64(pi.x);
+  const double by0 = wave_min_f64(pi.y), by1 = wave_max_f64(pi.y);
+  const double bz0 = wave_min_f64(pi.z), bz1 = wave_max_f64(pi.z);
+  // 1.5 held in a VGPR for the whole loop: the expansion's fma already reads 1.875 from an SGPR,
+  // and one VOP3 instruction reads at most one scalar operand
+  double c15v;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(c15v) : "s"(c15));
+  for (int jb = j0; jb < j1; jb += 64) {
+    const int jl = jb + lane;
+    bool near = false;
+    if (jl < j1) {
+      const double4 q = xm[jl];
+      const uint32_t tq = hiword(thr[jl].w);
+      const uint32_t U = tw > tq ? tw : tq;
+      const double ex = fmax(fmax(bx0 - q.x, q.x - bx1), 0.0);
+      const double ey = fmax(fmax(by0 - q.y, q.y - by1), 0.0);
+      const double ez = fmax(fmax(bz0 - q.z, q.z - bz1), 0.0);
+      const double d2 = fma(ez, ez, fma(ey, ey, ex * ex));
+      near = !(hiword(d2) >= U + 2u);
+    }
+    const unsigned long long mask = __ballot(near);
+    const int je = min(j1, jb + 64);
+    if (!FORCE) {
+      // without forces only the screened-in j need a visit
+      unsigned long long m = mask;
+      while (m) {
+        const int j = jb + __builtin_ctzll(m);
+        m &= m - 1;
+        const double4 pj = xm[j];
+        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        double s = 0.0;
+        close_part<FORCE, EMIT, CE, UNI>(thr, ii, valid, tw, j, n, f_in, rowbuf, R, r2, dx, dy, dz,
+                                         1.0, s, ce, nc);
       }
+      continue;
     }
-    if (FORCE) {
-      a[0] = fma(s, dx, a[0]);
-      a[1] = fma(s, dy, a[1]);
-      a[2] = fma(s, dz, a[2]);
+    // j-bodies fetched two at a time, so their scalar loads overlap
+    int j = jb;
+    for (; j + 2 <= je; j += 2) {
+      double4 pq[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) pq[q] = xm[j + q];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, pq[q], ii, valid, tw, j + q, n, f_in, rowbuf, R,
+                                         c15v, c1875, (mask >> (j + q - jb)) & 1ull, a, ce, nc);
     }
+    for (; j < je; ++j)
+      pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, xm[j], ii, valid, tw, j, n, f_in, rowbuf, R, c15v,
+                                       c1875, (mask >> (j - jb)) & 1ull, a, ce, nc);
   }
 }
 
 template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_pairs(const double4 *__restrict__ xm,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_pairs(const double4 *__restrict__ xm,
                                                   const double4 *__restrict__ thr,
                                                   const int *__restrict__ perm,
                                                   const double2 *__restrict__ uni, int n, int chunk,
