@@ -169,8 +169,10 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
   }
 }
 
+// Register budget for seven waves per SIMD (72 VGPRs): enough to keep two j-bodies in flight
+// without spilling, and enough waves to hide the scalar-load and reciprocal-square-root latency.
 template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_pairs(const double4 *__restrict__ xm,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_pairs(const double4 *__restrict__ xm,
                                                   const double4 *__restrict__ thr,
                                                   const int *__restrict__ perm,
                                                   const double2 *__restrict__ uni, int n, int chunk,
