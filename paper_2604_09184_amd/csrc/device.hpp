@@ -116,6 +116,26 @@ __device__ __forceinline__ void block_sum(double (&x)[NV], double *lds) {
   __syncthreads();
 }
 
+// Wave minimum / maximum of a double, returned as a wave-uniform (scalar register) value.
+__device__ __forceinline__ double uniform_f64(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return uniform_f64(v);
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return uniform_f64(v);
+}
+
 // Total momentum from per-block partials, summed in the same order by every workgroup.
 __device__ __forceinline__ void momentum_total(const double4 *__restrict__ mom, int nb, double (&P)[3],
                                                double *lds) {

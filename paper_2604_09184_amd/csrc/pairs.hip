@@ -13,26 +13,6 @@ namespace nbk {
 using namespace nbd;
 
 // ------------------------------------------------------------------ pair kernel
-// Wave minimum / maximum of a double, returned as a wave-uniform (scalar register) value.
-__device__ __forceinline__ double uniform_f64(double v) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-__device__ __forceinline__ double wave_min_f64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return uniform_f64(v);
-}
-
-__device__ __forceinline__ double wave_max_f64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return uniform_f64(v);
-}
-
 // The close-pair part of one pair (i, j) whose j passed the block screen: the per-pair prefilter
 // hi(r2) <= max(T_i, T_j), then the exact predicate, the changeover weight and the emission.
 template <bool FORCE, bool EMIT, bool CE, bool UNI>
