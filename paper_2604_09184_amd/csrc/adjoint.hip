@@ -18,43 +18,40 @@ namespace nbk {
 using namespace nbd;
 
 // ------------------------------------------------------------------ kick VJP pair kernel
-// One body k per lane, wave-uniform j-bodies (x, m) and their lam_a through scalar loads.
+// For the kick a_k = G sum_j m_j w(r_kj) d_kj (d_kj = x_j - x_k), the derivative contracted with
+// lam_a gives, per body k (before the factor G),
+//   g_k = sum_j [ w b + (w'/r) (d . b) d ],   b = m_k lam_j - m_j lam_k,
+//   dL/dm_k part = -sum_j w (lam_j . d).
+// The sum is split so that b is never formed per pair:
+//   sum_j w b      = m_k A - lam_k B,        A = sum_j w lam_j,   B = sum_j m_j w,
+//   sum_j q d      with q = (w'/r) (m_k (lam_j . d) - m_j (lam_k . d)).
+// Far from the changeover w = r^-3 and w'/r = -3 r^-5; the loop accumulates r^-5 (d . b) d and
+// the factor -3 is applied once at the end (close pairs store their w'/r divided by -3).
+// One body k per lane, wave-uniform j-bodies (x, m) and their lam_a through scalar loads, and the
+// block screen of the forward pair kernel in front of the per-pair prefilter.
 // perm (may be null) maps lanes to bodies; as in the forward pair kernel it changes no result.
-__global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__ xm,
-                                                     const double4 *__restrict__ thr,
-                                                     const int *__restrict__ perm,
-                                                     const double4 *__restrict__ lam_a, int n,
-                                                     int chunk, double f_in,
-                                                     double4 *__restrict__ part) {
-  const int lane_body = blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = lane_body < n;
-  const int lb = valid ? lane_body : n - 1;
-  const int ii = perm ? perm[lb] : lb;
-  const int i = ii;
-  const double4 pk = xm[ii];
-  const double4 lk = lam_a[ii];
-  const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
-  const int j0 = blockIdx.y * chunk;
-  const int j1 = min(n, j0 + chunk);
-  double gx = 0.0, gy = 0.0, gz = 0.0, gm = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    const double4 pj = xm[j];
-    const double4 lj = lam_a[j];
+// uni (may be null) = {1, m} when all masses are equal: m_j leaves the loop.
+template <bool UNI>
+__device__ __forceinline__ void vjp_pair(const double4 *__restrict__ thr, const double4 &pk,
+                                         const double4 &lk, const double4 &pj, const double4 &lj,
+                                         int ii, uint32_t tw, int j, bool screened, double f_in,
+                                         double (&A)[3], double &B, double (&C)[3], double &gm) {
+  const double dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  // 1/r to full precision from the hardware seed (second-order correction)
+  const double y0 = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2, y0 * y0, 1.0);
+  const double ri = fma(y0 * e, fma(e, 0.375, 0.5), y0);
+  const double ri2 = ri * ri;
+  double w = ri2 * ri;       // 1/r^3
+  double wq = w * ri2;       // (w'/r) / (-3) = 1/r^5
+  if (screened) {
     const uint32_t tj = hiword(thr[j].w);
     const uint32_t U = tw > tj ? tw : tj;
-    const double dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
-    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    // 1/r to full precision from the hardware seed (second-order correction)
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double e = fma(-r2, y0 * y0, 1.0);
-    const double ri = fma(y0 * e, fma(e, 0.375, 0.5), y0);
-    const double ri2 = ri * ri;
-    double w = ri2 * ri;            // 1/r^3
-    double wr = -3.0 * w * ri2;     // w'(r)/r = -3/r^5
     if (hiword(r2) <= U) {
       if (j == ii) {
         w = 0.0;
-        wr = 0.0;
+        wq = 0.0;
       } else {
         const double4 ti = thr[ii];
         const double4 tq = thr[j];
@@ -65,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__
           const double y = (r - f_in * rcij) / span;
           if (y <= 0.0) {
             w = 0.0;
-            wr = 0.0;
+            wq = 0.0;
           } else if (y < 1.0) {
             const double D = 2.0 * y * y - 2.0 * y + 1.0;
             const double K = y * y / D;
@@ -74,25 +71,98 @@ __global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__
                               (D * D * D) / (span * span);                                 // d2K/dr2
             const double r3 = r2 * r;
             w = K / r3 - K1 / r2;
-            wr = (3.0 * K1 / r3 - 3.0 * K / (r3 * r) - K2 / r2) / r;
+            wq = (3.0 * K1 / r3 - 3.0 * K / (r3 * r) - K2 / r2) / r / -3.0;
           }
         }
       }
     }
-    // b = m_k lam_a_j - m_j lam_a_k
-    const double bx = fma(pk.w, lj.x, -pj.w * lk.x);
-    const double by = fma(pk.w, lj.y, -pj.w * lk.y);
-    const double bz = fma(pk.w, lj.z, -pj.w * lk.z);
-    const double db = fma(dz, bz, fma(dy, by, dx * bx));
-    const double q = wr * db;
-    gx = fma(w, bx, fma(q, dx, gx));
-    gy = fma(w, by, fma(q, dy, gy));
-    gz = fma(w, bz, fma(q, dz, gz));
-    const double ld = fma(lj.z, dz, fma(lj.y, dy, lj.x * dx));
-    gm = fma(-w, ld, gm);
   }
+  const double ld = fma(lj.z, dz, fma(lj.y, dy, lj.x * dx));     // lam_j . d
+  const double lkd = fma(lk.z, dz, fma(lk.y, dy, lk.x * dx));    // lam_k . d
+  const double db = UNI ? ld - lkd : fma(pk.w, ld, -pj.w * lkd);
+  const double q = wq * db;
+  C[0] = fma(q, dx, C[0]);
+  C[1] = fma(q, dy, C[1]);
+  C[2] = fma(q, dz, C[2]);
+  A[0] = fma(w, lj.x, A[0]);
+  A[1] = fma(w, lj.y, A[1]);
+  A[2] = fma(w, lj.z, A[2]);
+  B = UNI ? B + w : fma(pj.w, w, B);
+  gm = fma(-w, ld, gm);
+}
+
+template <bool UNI>
+__device__ __forceinline__ void vjp_loop(const double4 *__restrict__ xm, const double4 *__restrict__ thr,
+                                         const double4 *__restrict__ lam_a, const double4 &pk,
+                                         const double4 &lk, int ii, uint32_t tw, int j0, int j1,
+                                         double f_in, double (&A)[3], double &B, double (&C)[3],
+                                         double &gm) {
+  const int lane = threadIdx.x & 63;
+  const double bx0 = wave_min_f64(pk.x), bx1 = wave_max_f64(pk.x);
+  const double by0 = wave_min_f64(pk.y), by1 = wave_max_f64(pk.y);
+  const double bz0 = wave_min_f64(pk.z), bz1 = wave_max_f64(pk.z);
+  for (int jb = j0; jb < j1; jb += 64) {
+    const int jl = jb + lane;
+    bool near = false;
+    if (jl < j1) {
+      const double4 q = xm[jl];
+      const uint32_t tq = hiword(thr[jl].w);
+      const uint32_t U = tw > tq ? tw : tq;
+      const double ex = fmax(fmax(bx0 - q.x, q.x - bx1), 0.0);
+      const double ey = fmax(fmax(by0 - q.y, q.y - by1), 0.0);
+      const double ez = fmax(fmax(bz0 - q.z, q.z - bz1), 0.0);
+      const double d2 = fma(ez, ez, fma(ey, ey, ex * ex));
+      near = !(hiword(d2) >= U + 2u);
+    }
+    const unsigned long long mask = __ballot(near);
+    const int je = min(j1, jb + 64);
+    // j-bodies fetched two at a time, so their scalar loads overlap
+    int j = jb;
+    for (; j + 2 <= je; j += 2) {
+      const double4 p0 = xm[j], p1 = xm[j + 1], l0 = lam_a[j], l1 = lam_a[j + 1];
+      vjp_pair<UNI>(thr, pk, lk, p0, l0, ii, tw, j, (mask >> (j - jb)) & 1ull, f_in, A, B, C, gm);
+      vjp_pair<UNI>(thr, pk, lk, p1, l1, ii, tw, j + 1, (mask >> (j + 1 - jb)) & 1ull, f_in, A, B, C,
+                    gm);
+    }
+    if (j < je)
+      vjp_pair<UNI>(thr, pk, lk, xm[j], lam_a[j], ii, tw, j, (mask >> (j - jb)) & 1ull, f_in, A, B,
+                    C, gm);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__ xm,
+                                                     const double4 *__restrict__ thr,
+                                                     const int *__restrict__ perm,
+                                                     const double2 *__restrict__ uni,
+                                                     const double4 *__restrict__ lam_a, int n,
+                                                     int chunk, double f_in,
+                                                     double4 *__restrict__ part) {
+  const int lane_body = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = lane_body < n;
+  const int lb = valid ? lane_body : n - 1;
+  const int ii = perm ? perm[lb] : lb;
+  const double4 pk = xm[ii];
+  const double4 lk = lam_a[ii];
+  const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  double A[3] = {0.0, 0.0, 0.0}, C[3] = {0.0, 0.0, 0.0};
+  double B = 0.0, gm = 0.0;
+  const bool uniform = uni && uni[0].x != 0.0;
+  if (uniform) vjp_loop<true>(xm, thr, lam_a, pk, lk, ii, tw, j0, j1, f_in, A, B, C, gm);
+  else vjp_loop<false>(xm, thr, lam_a, pk, lk, ii, tw, j0, j1, f_in, A, B, C, gm);
   if (!valid) return;
-  part[(size_t)blockIdx.y * n + i] = make_double4(gx, gy, gz, gm);
+  if (uniform) {
+    // equal masses: the loop summed sum_j w and (lam_j - lam_k) . d without the common mass
+    const double m = uni[0].y;
+    B *= m;
+    C[0] *= m; C[1] *= m; C[2] *= m;
+  }
+  // g = m_k A - lam_k B - 3 C
+  const double gx = fma(pk.w, A[0], fma(-lk.x, B, -3.0 * C[0]));
+  const double gy = fma(pk.w, A[1], fma(-lk.y, B, -3.0 * C[1]));
+  const double gz = fma(pk.w, A[2], fma(-lk.z, B, -3.0 * C[2]));
+  part[(size_t)blockIdx.y * n + ii] = make_double4(gx, gy, gz, gm);
 }
 
 // lam_a = h * lam_v
@@ -146,12 +216,13 @@ __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restri
   lam_x[i] = l;
 }
 
-hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double4 *lam_v,
-                           double h, double G, double f_in, int n, int S, int chunk, int napply,
-                           double4 *lam_a, double4 *part, double4 *lam_x, hipStream_t st) {
+hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double2 *uni,
+                           const double4 *lam_v, double h, double G, double f_in, int n, int S,
+                           int chunk, int napply, double4 *lam_a, double4 *part, double4 *lam_x,
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(nblocks(n)), dim3(kBlock), 0, st, lam_v, h, n, lam_a);
-  hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, perm, lam_a, n,
-                     chunk, f_in, part);
+  hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, perm, uni, lam_a,
+                     n, chunk, f_in, part);
   hipLaunchKernelGGL(k_vjp_finalize, dim3(fin_blocks(n)), dim3(kBlock), 0, st, part, S, n, G, napply,
                      lam_x);
   return hipGetLastError();

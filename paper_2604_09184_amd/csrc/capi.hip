@@ -191,15 +191,16 @@ int emit_list(nbody_ctx *c, const KickArgs &a, int32_t *pairs, int64_t cap, int6
 }
 
 // lam += VJP of the kick v' = v + h a(x) at positions xm (adds to lam_x, including dL/dm).
-int kick_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *thr, const double4 *lam_v, double h,
-             double4 *lam_x, hipStream_t st, int napply = 1) {
+// uni: the equal-mass flag of xm (from mass_check; masses never change along a trajectory).
+int kick_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *thr, const double2 *uni,
+             const double4 *lam_v, double h, double4 *lam_x, hipStream_t st, int napply = 1) {
   KickArgs a;
   TRY(make_kick_args(c, n, (const double *)xm, (const double *)thr, true, false, false, a));
   double4 *la = (double4 *)ensure(c, B_LAMA, (size_t)n * sizeof(double4));
   if (!la) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint)");
   TRY(locality(c, n, xm, st, &a.perm));
-  HIPCHK(c, launch_kick_vjp(xm, thr, a.perm, lam_v, h, c->p.G, c->p.f_in, n, a.nchunk, a.chunk, napply, la,
-                            a.part, lam_x, st), "kick vjp");
+  HIPCHK(c, launch_kick_vjp(xm, thr, a.perm, uni, lam_v, h, c->p.G, c->p.f_in, n, a.nchunk, a.chunk, napply,
+                            la, a.part, lam_x, st), "kick vjp");
   return NBODY_OK;
 }
 
@@ -501,7 +502,9 @@ int nbody_kick_vjp(nbody_ctx *c, int64_t n, const double *xm, const double *thr,
   TRY(check_dev(c, thr, "thr", true));
   TRY(check_dev(c, lam_v, "lam_v", true));
   TRY(check_dev(c, lam_x, "lam_x", true));
-  return kick_vjp(c, (int)n, (const double4 *)xm, (const double4 *)thr, (const double4 *)lam_v, h,
+  const double2 *uni = nullptr;
+  TRY(mass_check(c, (int)n, (const double4 *)xm, (hipStream_t)stream, &uni));
+  return kick_vjp(c, (int)n, (const double4 *)xm, (const double4 *)thr, uni, (const double4 *)lam_v, h,
                   (double4 *)lam_x, (hipStream_t)stream);
 }
 
@@ -588,12 +591,12 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   // half kick of step s-1 sit at the same positions and see the same lam_v: one evaluation is
   // applied twice (identical bits to two evaluations).
   double4 *LX = (double4 *)lam_x, *LV = (double4 *)lam_v;
-  TRY(kick_vjp(c, N, Xend, T, LV, h, LX, st, 1));
+  TRY(kick_vjp(c, N, Xend, T, a.uni, LV, h, LX, st, 1));
   for (int s = nsteps - 1; s >= 0; --s) {
     TRY(jump_vjp(c, N, X1(s), V2(s), h, LX, LV, st));
     HIPCHK(c, launch_drift_vjp(X1(s), V1(s), N, p.dt, p.G * p.m0, LX, LV, st), "drift vjp");
     TRY(jump_vjp(c, N, X1(s), V1(s), h, LX, LV, st));
-    TRY(kick_vjp(c, N, Xs(s), T, LV, h, LX, st, s > 0 ? 2 : 1));
+    TRY(kick_vjp(c, N, Xs(s), T, a.uni, LV, h, LX, st, s > 0 ? 2 : 1));
   }
   return NBODY_OK;
 }
