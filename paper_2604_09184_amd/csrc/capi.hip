@@ -192,13 +192,17 @@ int emit_list(nbody_ctx *c, const KickArgs &a, int32_t *pairs, int64_t cap, int6
 
 // lam += VJP of the kick v' = v + h a(x) at positions xm (adds to lam_x, including dL/dm).
 // uni: the equal-mass flag of xm (from mass_check; masses never change along a trajectory).
+// perm: a lane permutation to reuse (any permutation gives the same bits), or null to build one
+// for xm.
 int kick_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *thr, const double2 *uni,
-             const double4 *lam_v, double h, double4 *lam_x, hipStream_t st, int napply = 1) {
+             const double4 *lam_v, double h, double4 *lam_x, hipStream_t st, int napply = 1,
+             const int *perm = nullptr) {
   KickArgs a;
   TRY(make_kick_args(c, n, (const double *)xm, (const double *)thr, true, false, false, a));
   double4 *la = (double4 *)ensure(c, B_LAMA, (size_t)n * sizeof(double4));
   if (!la) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint)");
-  TRY(locality(c, n, xm, st, &a.perm));
+  if (perm) a.perm = perm;
+  else TRY(locality(c, n, xm, st, &a.perm));
   HIPCHK(c, launch_kick_vjp(xm, thr, a.perm, uni, lam_v, h, c->p.G, c->p.f_in, n, a.nchunk, a.chunk, napply,
                             la, a.part, lam_x, st), "kick vjp");
   return NBODY_OK;
@@ -591,12 +595,14 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   // half kick of step s-1 sit at the same positions and see the same lam_v: one evaluation is
   // applied twice (identical bits to two evaluations).
   double4 *LX = (double4 *)lam_x, *LV = (double4 *)lam_v;
-  TRY(kick_vjp(c, N, Xend, T, a.uni, LV, h, LX, st, 1));
+  // the segment's lane permutation (built at its start) serves every kick derivative: bodies
+  // move little within a segment, and the permutation changes no result bit
+  TRY(kick_vjp(c, N, Xend, T, a.uni, LV, h, LX, st, 1, a.perm));
   for (int s = nsteps - 1; s >= 0; --s) {
     TRY(jump_vjp(c, N, X1(s), V2(s), h, LX, LV, st));
     HIPCHK(c, launch_drift_vjp(X1(s), V1(s), N, p.dt, p.G * p.m0, LX, LV, st), "drift vjp");
     TRY(jump_vjp(c, N, X1(s), V1(s), h, LX, LV, st));
-    TRY(kick_vjp(c, N, Xs(s), T, a.uni, LV, h, LX, st, s > 0 ? 2 : 1));
+    TRY(kick_vjp(c, N, Xs(s), T, a.uni, LV, h, LX, st, s > 0 ? 2 : 1, a.perm));
   }
   return NBODY_OK;
 }
