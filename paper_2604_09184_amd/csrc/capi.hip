@@ -556,8 +556,10 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   double4 *XA = (double4 *)ensure(c, B_XA, bytes);
   double4 *VA = (double4 *)ensure(c, B_VA, bytes);
   const int nbf = fin_blocks(n);   // momentum partials written by the finalize kernel
-  double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)std::max(nb, nbf) * sizeof(double4));
-  if (!S || !XA || !VA || !mom) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint states)");
+  double4 *momA = (double4 *)ensure(c, B_MOM_A, (size_t)nbf * sizeof(double4));
+  double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nb * sizeof(double4));
+  if (!S || !XA || !VA || !momA || !momB)
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint states)");
   auto Xs = [&](int s) { return S + (size_t)4 * s * N; };
   auto X1 = [&](int s) { return S + ((size_t)4 * s + 1) * N; };
   auto V1 = [&](int s) { return S + ((size_t)4 * s + 2) * N; };
@@ -566,29 +568,27 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   const double4 *T = (const double4 *)thr;
   const double h = 0.5 * p.dt;
   const bool split = p.precision == NBODY_PREC_SPLIT;
-  // replay of the segment with the forward's kernel sequence (merged half kicks), recording
+  // replay of the segment with the forward's own kernels in the forward's order (merged half
+  // kicks, jump fused with the drift), so every recorded state equals the forward's bit for bit;
+  // the kernels write the records as side outputs
   HIPCHK(c, hipMemcpyAsync(XA, xm0, bytes, hipMemcpyDeviceToDevice, st), "copy");
   HIPCHK(c, hipMemcpyAsync(VA, v0, bytes, hipMemcpyDeviceToDevice, st), "copy");
+  HIPCHK(c, hipMemcpyAsync(Xs(0), xm0, bytes, hipMemcpyDeviceToDevice, st), "copy");
   KickArgs a;
   TRY(make_kick_args(c, N, (const double *)XA, thr, true, false, false, a));
   TRY(locality(c, N, XA, st, &a.perm));
   TRY(mass_check(c, N, XA, st, &a.uni));
   HIPCHK(c, launch_pairs(a, true, false, false, split, st), "pairs");
-  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, XA, VA, nullptr, nullptr, mom, st), "finalize");
+  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, XA, VA, nullptr, nullptr, momA, st,
+                            nullptr, nullptr, V1(0)), "finalize");
   for (int s = 0; s < nsteps; ++s) {
-    if (s == 0) HIPCHK(c, hipMemcpyAsync(Xs(0), XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    HIPCHK(c, hipMemcpyAsync(V1(s), VA, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    HIPCHK(c, launch_jump(XA, mom, nbf, N, h, p.m0, st), "jump");
-    HIPCHK(c, hipMemcpyAsync(X1(s), XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    HIPCHK(c, launch_drift(XA, VA, N, p.dt, p.G * p.m0, nullptr, st), "drift");
-    HIPCHK(c, hipMemcpyAsync(V2(s), VA, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    HIPCHK(c, launch_momentum(XA, VA, N, mom, st), "momentum");
-    HIPCHK(c, launch_jump(XA, mom, nb, N, h, p.m0, st), "jump");
-    HIPCHK(c, hipMemcpyAsync(s + 1 < nsteps ? Xs(s + 1) : Xend, XA, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    HIPCHK(c, launch_jump_drift(XA, VA, momA, nbf, N, h, p.dt, p.m0, p.G * p.m0, nullptr, momB, st, X1(s),
+                                V2(s)), "jump+drift");
+    HIPCHK(c, launch_jump(XA, momB, nb, N, h, p.m0, st, s + 1 < nsteps ? Xs(s + 1) : Xend), "jump");
     if (s + 1 < nsteps) {
       HIPCHK(c, launch_pairs(a, true, false, false, split, st), "pairs");
-      HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 2, XA, VA, nullptr, nullptr, mom, st),
-             "finalize");
+      HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 2, XA, VA, nullptr, nullptr, momA, st,
+                                nullptr, nullptr, V1(s + 1)), "finalize");
     }
   }
   // reverse sweep: B2^T C2^T A^T C1^T B1^T per step. The first half kick of step s and the second

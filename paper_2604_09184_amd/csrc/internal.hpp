@@ -32,7 +32,7 @@ hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool 
 hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, int n, double G,
                            double h, int napply, const double4 *xm, double4 *v, double4 *acc,
                            double4 *acc_ce, double4 *mom, hipStream_t st, const int *cnt = nullptr,
-                           unsigned long long *count_out = nullptr);
+                           unsigned long long *count_out = nullptr, double4 *v_rec = nullptr);
 hipError_t launch_locality(const double4 *xm, int n, float2 *range_part, unsigned short *cell,
                            unsigned *count, unsigned *cursor, int *perm, hipStream_t st);
 int locality_cells();
@@ -47,10 +47,11 @@ hipError_t launch_energy(const double4 *xm, const double4 *v, const double4 *thr
 // kepler.hip
 hipError_t launch_momentum(const double4 *xm, const double4 *v, int n, double4 *mom, hipStream_t st);
 hipError_t launch_jump(double4 *xm, const double4 *mom, int nb, int n, double h, double m0,
-                       hipStream_t st);
+                       hipStream_t st, double4 *x_rec = nullptr);
 hipError_t launch_jump_drift(double4 *xm, double4 *v, const double4 *mom_in, int nb, int n,
                              double hjump, double dt, double m0, double mu, uint32_t *status,
-                             double4 *mom_out, hipStream_t st);
+                             double4 *mom_out, hipStream_t st, double4 *x_rec = nullptr,
+                             double4 *v_rec = nullptr);
 hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, uint32_t *status,
                         hipStream_t st);
 

@@ -25,9 +25,10 @@ __global__ __launch_bounds__(kBlock) void k_momentum(const double4 *__restrict__
   if (threadIdx.x == 0) mom[blockIdx.x] = make_double4(P[0], P[1], P[2], 0.0);
 }
 
+// x_rec (may be null) receives a copy of the new positions.
 __global__ __launch_bounds__(kBlock) void k_jump(double4 *__restrict__ xm,
                                                  const double4 *__restrict__ mom, int nb, int n,
-                                                 double h, double m0) {
+                                                 double h, double m0, double4 *__restrict__ x_rec) {
   __shared__ double lds[3 * kBlock];
   double P[3];
   momentum_total(mom, nb, P, lds);
@@ -37,14 +38,19 @@ __global__ __launch_bounds__(kBlock) void k_jump(double4 *__restrict__ xm,
   double4 p = xm[i];
   p.x = p.x + sx; p.y = p.y + sy; p.z = p.z + sz;
   xm[i] = p;
+  if (x_rec) x_rec[i] = p;
 }
 
+// x_rec / v_rec (may be null) receive the positions after the jump (before the drift) and the
+// velocities after the drift.
 __global__ __launch_bounds__(kBlock) void k_jump_drift(double4 *__restrict__ xm,
                                                        double4 *__restrict__ v,
                                                        const double4 *__restrict__ mom_in, int nb,
                                                        int n, double hjump, double dt, double m0,
                                                        double mu, uint32_t *__restrict__ status,
-                                                       double4 *__restrict__ mom_out) {
+                                                       double4 *__restrict__ mom_out,
+                                                       double4 *__restrict__ x_rec,
+                                                       double4 *__restrict__ v_rec) {
   __shared__ double lds[3 * kBlock];
   double P[3];
   momentum_total(mom_in, nb, P, lds);
@@ -55,9 +61,11 @@ __global__ __launch_bounds__(kBlock) void k_jump_drift(double4 *__restrict__ xm,
     double4 p = xm[i];
     double4 q = v[i];
     p.x = p.x + sx; p.y = p.y + sy; p.z = p.z + sz;
+    if (x_rec) x_rec[i] = p;
     const int st = kepler_advance(p.x, p.y, p.z, q.x, q.y, q.z, mu, dt);
     xm[i] = p;
     v[i] = q;
+    if (v_rec) v_rec[i] = q;
     if (status) status[i] |= (uint32_t)st;
     Q[0] = p.w * q.x; Q[1] = p.w * q.y; Q[2] = p.w * q.z;
   }
@@ -84,16 +92,16 @@ hipError_t launch_momentum(const double4 *xm, const double4 *v, int n, double4 *
 }
 
 hipError_t launch_jump(double4 *xm, const double4 *mom, int nb, int n, double h, double m0,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_jump, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, mom, nb, n, h, m0);
+                       hipStream_t st, double4 *x_rec) {
+  hipLaunchKernelGGL(k_jump, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, mom, nb, n, h, m0, x_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_jump_drift(double4 *xm, double4 *v, const double4 *mom_in, int nb, int n,
                              double hjump, double dt, double m0, double mu, uint32_t *status,
-                             double4 *mom_out, hipStream_t st) {
+                             double4 *mom_out, hipStream_t st, double4 *x_rec, double4 *v_rec) {
   hipLaunchKernelGGL(k_jump_drift, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, mom_in, nb, n,
-                     hjump, dt, m0, mu, status, mom_out);
+                     hjump, dt, m0, mu, status, mom_out, x_rec, v_rec);
   return hipGetLastError();
 }
 

@@ -184,7 +184,7 @@ int locality_cells() { return kCells; }
 // keep enough loads in flight when n is small. Momentum partials: one per 64 bodies.
 // cnt (may be null): per-(chunk, body) numbers of close partners j > i; their total is added to
 // *count_out (integer atomics: the total does not depend on the order). part may be null
-// (counting only).
+// (counting only). v_rec (may be null) receives a copy of the updated velocities.
 __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__ part,
                                                      const double4 *__restrict__ part_ce, int S,
                                                      int n, double G, double h, int napply,
@@ -194,7 +194,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
                                                      double4 *__restrict__ acc_ce,
                                                      double4 *__restrict__ mom,
                                                      const int *__restrict__ cnt,
-                                                     unsigned long long *__restrict__ count_out) {
+                                                     unsigned long long *__restrict__ count_out,
+                                                     double4 *__restrict__ v_rec) {
   constexpr int W = kBlock / 64;
   __shared__ double red[2][W - 1][3][64];
   const int lane = threadIdx.x & 63;
@@ -251,6 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
         q.z = q.z + h * az;
       }
       v[i] = q;
+      if (v_rec) v_rec[i] = q;
       const double m = xm[i].w;
       P[0] = m * q.x; P[1] = m * q.y; P[2] = m * q.z;
     }
@@ -268,9 +270,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double4 *__restrict__
 hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, int n, double G,
                            double h, int napply, const double4 *xm, double4 *v, double4 *acc,
                            double4 *acc_ce, double4 *mom, hipStream_t st, const int *cnt,
-                           unsigned long long *count_out) {
+                           unsigned long long *count_out, double4 *v_rec) {
   hipLaunchKernelGGL(k_finalize, dim3(fin_blocks(n)), dim3(kBlock), 0, st, part, part_ce, S, n, G,
-                     h, napply, xm, v, acc, acc_ce, mom, cnt, count_out);
+                     h, napply, xm, v, acc, acc_ce, mom, cnt, count_out, v_rec);
   return hipGetLastError();
 }
 
