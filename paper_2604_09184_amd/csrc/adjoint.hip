@@ -19,7 +19,8 @@ using namespace nbd;
 
 // ------------------------------------------------------------------ kick VJP pair kernel
 // For the kick a_k = G sum_j m_j w(r_kj) d_kj (d_kj = x_j - x_k), the derivative contracted with
-// lam_a gives, per body k (before the factor G),
+// lam_a gives, per body k (before the factor G; the kernel contracts with lam_v, and h, the other
+// factor of lam_a = h lam_v, is applied with G in the finalize),
 //   g_k = sum_j [ w b + (w'/r) (d . b) d ],   b = m_k lam_j - m_j lam_k,
 //   dL/dm_k part = -sum_j w (lam_j . d).
 // The sum is split so that b is never formed per pair:
@@ -27,7 +28,7 @@ using namespace nbd;
 //   sum_j q d      with q = (w'/r) (m_k (lam_j . d) - m_j (lam_k . d)).
 // Far from the changeover w = r^-3 and w'/r = -3 r^-5; the loop accumulates r^-5 (d . b) d and
 // the factor -3 is applied once at the end (close pairs store their w'/r divided by -3).
-// One body k per lane, wave-uniform j-bodies (x, m) and their lam_a through scalar loads, and the
+// One body k per lane, wave-uniform j-bodies (x, m) and their lam_v through scalar loads, and the
 // block screen of the forward pair kernel in front of the per-pair prefilter.
 // perm (may be null) maps lanes to bodies; as in the forward pair kernel it changes no result.
 // uni (may be null) = {1, m} when all masses are equal: m_j leaves the loop.
@@ -93,7 +94,7 @@ __device__ __forceinline__ void vjp_pair(const double4 *__restrict__ thr, const 
 
 template <bool UNI>
 __device__ __forceinline__ void vjp_loop(const double4 *__restrict__ xm, const double4 *__restrict__ thr,
-                                         const double4 *__restrict__ lam_a, const double4 &pk,
+                                         const double4 *__restrict__ lam_v, const double4 &pk,
                                          const double4 &lk, int ii, uint32_t tw, int j0, int j1,
                                          double f_in, double (&A)[3], double &B, double (&C)[3],
                                          double &gm) {
@@ -119,13 +120,13 @@ __device__ __forceinline__ void vjp_loop(const double4 *__restrict__ xm, const d
     // j-bodies fetched two at a time, so their scalar loads overlap
     int j = jb;
     for (; j + 2 <= je; j += 2) {
-      const double4 p0 = xm[j], p1 = xm[j + 1], l0 = lam_a[j], l1 = lam_a[j + 1];
+      const double4 p0 = xm[j], p1 = xm[j + 1], l0 = lam_v[j], l1 = lam_v[j + 1];
       vjp_pair<UNI>(thr, pk, lk, p0, l0, ii, tw, j, (mask >> (j - jb)) & 1ull, f_in, A, B, C, gm);
       vjp_pair<UNI>(thr, pk, lk, p1, l1, ii, tw, j + 1, (mask >> (j + 1 - jb)) & 1ull, f_in, A, B, C,
                     gm);
     }
     if (j < je)
-      vjp_pair<UNI>(thr, pk, lk, xm[j], lam_a[j], ii, tw, j, (mask >> (j - jb)) & 1ull, f_in, A, B,
+      vjp_pair<UNI>(thr, pk, lk, xm[j], lam_v[j], ii, tw, j, (mask >> (j - jb)) & 1ull, f_in, A, B,
                     C, gm);
   }
 }
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__
                                                      const double4 *__restrict__ thr,
                                                      const int *__restrict__ perm,
                                                      const double2 *__restrict__ uni,
-                                                     const double4 *__restrict__ lam_a, int n,
+                                                     const double4 *__restrict__ lam_v, int n,
                                                      int chunk, double f_in,
                                                      double4 *__restrict__ part) {
   const int lane_body = blockIdx.x * kBlock + threadIdx.x;
@@ -142,15 +143,15 @@ __global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__
   const int lb = valid ? lane_body : n - 1;
   const int ii = perm ? perm[lb] : lb;
   const double4 pk = xm[ii];
-  const double4 lk = lam_a[ii];
+  const double4 lk = lam_v[ii];
   const uint32_t tw = __builtin_amdgcn_readfirstlane(wave_max_u32(hiword(thr[ii].w)));
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
   double A[3] = {0.0, 0.0, 0.0}, C[3] = {0.0, 0.0, 0.0};
   double B = 0.0, gm = 0.0;
   const bool uniform = uni && uni[0].x != 0.0;
-  if (uniform) vjp_loop<true>(xm, thr, lam_a, pk, lk, ii, tw, j0, j1, f_in, A, B, C, gm);
-  else vjp_loop<false>(xm, thr, lam_a, pk, lk, ii, tw, j0, j1, f_in, A, B, C, gm);
+  if (uniform) vjp_loop<true>(xm, thr, lam_v, pk, lk, ii, tw, j0, j1, f_in, A, B, C, gm);
+  else vjp_loop<false>(xm, thr, lam_v, pk, lk, ii, tw, j0, j1, f_in, A, B, C, gm);
   if (!valid) return;
   if (uniform) {
     // equal masses: the loop summed sum_j w and (lam_j - lam_k) . d without the common mass
@@ -165,21 +166,12 @@ __global__ __launch_bounds__(kBlock) void k_kick_vjp(const double4 *__restrict__
   part[(size_t)blockIdx.y * n + ii] = make_double4(gx, gy, gz, gm);
 }
 
-// lam_a = h * lam_v
-__global__ __launch_bounds__(kBlock) void k_scale(const double4 *__restrict__ lv, double h, int n,
-                                                  double4 *__restrict__ la) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double4 q = lv[i];
-  la[i] = make_double4(h * q.x, h * q.y, h * q.z, 0.0);
-}
-
-// lam_x += G * sum of partials (component 3 accumulates dL/dm), napply times: two consecutive
+// lam_x += Gh * sum of partials (component 3 accumulates dL/dm), napply times: two consecutive
 // kick derivatives at the same positions with the same lam_v give the same increment, so adding
 // one evaluation twice equals evaluating twice, bit for bit. Same partial-sum layout as
 // k_finalize: 64 bodies per workgroup, four waves over the chunks, added in wave order.
 __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restrict__ part, int S, int n,
-                                                         double G, int napply,
+                                                         double Gh, int napply,
                                                          double4 *__restrict__ lam_x) {
   constexpr int W = kBlock / 64;
   __shared__ double red[W - 1][4][64];
@@ -211,20 +203,20 @@ __global__ __launch_bounds__(kBlock) void k_vjp_finalize(const double4 *__restri
     for (int k = 0; k < 4; ++k) g[k] += red[q][k][lane];
   double4 l = lam_x[i];
   for (int k = 0; k < napply; ++k) {
-    l.x += G * g[0]; l.y += G * g[1]; l.z += G * g[2]; l.w += G * g[3];
+    l.x += Gh * g[0]; l.y += Gh * g[1]; l.z += Gh * g[2]; l.w += Gh * g[3];
   }
   lam_x[i] = l;
 }
 
+// The derivative is linear in lam_v = h lam_v: the pair kernel runs on lam_v and the factor h joins
+// G in the finalize.
 hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double2 *uni,
                            const double4 *lam_v, double h, double G, double f_in, int n, int S,
-                           int chunk, int napply, double4 *lam_a, double4 *part, double4 *lam_x,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_scale, dim3(nblocks(n)), dim3(kBlock), 0, st, lam_v, h, n, lam_a);
-  hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, perm, uni, lam_a,
+                           int chunk, int napply, double4 *part, double4 *lam_x, hipStream_t st) {
+  hipLaunchKernelGGL(k_kick_vjp, dim3(nblocks(n), S), dim3(kBlock), 0, st, xm, thr, perm, uni, lam_v,
                      n, chunk, f_in, part);
-  hipLaunchKernelGGL(k_vjp_finalize, dim3(fin_blocks(n)), dim3(kBlock), 0, st, part, S, n, G, napply,
-                     lam_x);
+  hipLaunchKernelGGL(k_vjp_finalize, dim3(fin_blocks(n)), dim3(kBlock), 0, st, part, S, n, G * h,
+                     napply, lam_x);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ struct Buf {
 };
 
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
-             B_ADJ_STATES, B_XA, B_VA, B_X1, B_V1, B_V2, B_LAMA, B_LSUM, B_B_OFFS, B_B_ORDER,
+             B_ADJ_STATES, B_XA, B_VA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_NUM };
 
@@ -199,12 +199,10 @@ int kick_vjp(nbody_ctx *c, int n, const double4 *xm, const double4 *thr, const d
              const int *perm = nullptr) {
   KickArgs a;
   TRY(make_kick_args(c, n, (const double *)xm, (const double *)thr, true, false, false, a));
-  double4 *la = (double4 *)ensure(c, B_LAMA, (size_t)n * sizeof(double4));
-  if (!la) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint)");
   if (perm) a.perm = perm;
   else TRY(locality(c, n, xm, st, &a.perm));
   HIPCHK(c, launch_kick_vjp(xm, thr, a.perm, uni, lam_v, h, c->p.G, c->p.f_in, n, a.nchunk, a.chunk, napply,
-                            la, a.part, lam_x, st), "kick vjp");
+                            a.part, lam_x, st), "kick vjp");
   return NBODY_OK;
 }
 

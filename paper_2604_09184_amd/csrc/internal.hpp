@@ -58,8 +58,7 @@ hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, ui
 // adjoint.hip
 hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double2 *uni,
                            const double4 *lam_v, double h, double G, double f_in, int n, int S,
-                           int chunk, int napply, double4 *lam_a, double4 *part, double4 *lam_x,
-                           hipStream_t st);
+                           int chunk, int napply, double4 *part, double4 *lam_x, hipStream_t st);
 hipError_t launch_jump_vjp(const double4 *xm, const double4 *v, double h, double m0, int n,
                            double4 *parts, double4 *lam_x, double4 *lam_v, hipStream_t st);
 hipError_t launch_drift_vjp(const double4 *xm, const double4 *v, int n, double dt, double mu,
