@@ -373,7 +373,7 @@ int nbody_jump(nbody_ctx *c, int64_t n, double *xm, const double *v, double h, v
   TRY(check_n(c, n));
   TRY(check_dev(c, xm, "xm", true));
   TRY(check_dev(c, v, "v", true));
-  const int nb = nblocks(n);
+  const int nb = fin_blocks(n);
   double4 *mom = (double4 *)ensure(c, B_MOM_A, (size_t)nb * sizeof(double4));
   if (!mom) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
   hipStream_t st = (hipStream_t)stream;
@@ -414,16 +414,15 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
     HIPCHK(c, hipMemsetAsync(step_counts, 0, ((size_t)nsteps + 1) * sizeof(int64_t), st), "memset");
   const nbody_params &p = c->p;
   const int N = (int)n;
-  const int nb = nblocks(n);
   if (!thr) {
     double *t = (double *)ensure(c, B_THR, (size_t)n * sizeof(double4));
     if (!t) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (thresholds)");
     TRY(nbody_rcrit(c, n, xm, v, t, stream));
     thr = t;
   }
-  const int nbf = fin_blocks(n);   // momentum partials written by the finalize kernel
+  const int nbf = fin_blocks(n);   // momentum partials (one per 64 bodies)
   double4 *momA = (double4 *)ensure(c, B_MOM_A, (size_t)nbf * sizeof(double4));
-  double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nb * sizeof(double4));
+  double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nbf * sizeof(double4));
   if (!momA || !momB) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (momentum)");
   KickArgs a;
   TRY(make_kick_args(c, N, xm, thr, true, false, emit || counting, a));
@@ -453,7 +452,7 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
                             counting ? a.cnt : nullptr, sc), "step finalize");
   for (int s = 1; s <= nsteps; ++s) {
     HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st), "jump+drift");
-    HIPCHK(c, launch_jump(X, momB, nb, N, h, p.m0, st), "jump");
+    HIPCHK(c, launch_jump(X, momB, nbf, N, h, p.m0, st), "jump");
     if (a.perm && s % c->locality_every == 0) {
       TRY(locality(c, N, X, st, &a.perm));
       ac.perm = a.perm;
@@ -546,16 +545,15 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   hipStream_t st = (hipStream_t)stream;
   const nbody_params &p = c->p;
   const int N = (int)n;
-  const int nb = nblocks(n);
   const size_t bytes = (size_t)n * sizeof(double4);
   // per step s: X_s (positions at its start), X1_s (before the drift), V1_s (after the first
   // half kick), V2_s (after the drift); plus the final positions
   double4 *S = (double4 *)ensure(c, B_ADJ_STATES, bytes * (4 * (size_t)nsteps + 1));
   double4 *XA = (double4 *)ensure(c, B_XA, bytes);
   double4 *VA = (double4 *)ensure(c, B_VA, bytes);
-  const int nbf = fin_blocks(n);   // momentum partials written by the finalize kernel
+  const int nbf = fin_blocks(n);   // momentum partials (one per 64 bodies)
   double4 *momA = (double4 *)ensure(c, B_MOM_A, (size_t)nbf * sizeof(double4));
-  double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nb * sizeof(double4));
+  double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nbf * sizeof(double4));
   if (!S || !XA || !VA || !momA || !momB)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (adjoint states)");
   auto Xs = [&](int s) { return S + (size_t)4 * s * N; };
@@ -582,7 +580,7 @@ int nbody_step_vjp(nbody_ctx *c, int64_t n, const double *xm0, const double *v0,
   for (int s = 0; s < nsteps; ++s) {
     HIPCHK(c, launch_jump_drift(XA, VA, momA, nbf, N, h, p.dt, p.m0, p.G * p.m0, nullptr, momB, st, X1(s),
                                 V2(s)), "jump+drift");
-    HIPCHK(c, launch_jump(XA, momB, nb, N, h, p.m0, st, s + 1 < nsteps ? Xs(s + 1) : Xend), "jump");
+    HIPCHK(c, launch_jump(XA, momB, nbf, N, h, p.m0, st, s + 1 < nsteps ? Xs(s + 1) : Xend), "jump");
     if (s + 1 < nsteps) {
       HIPCHK(c, launch_pairs(a, true, false, false, split, st), "pairs");
       HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 2, XA, VA, nullptr, nullptr, momA, st,

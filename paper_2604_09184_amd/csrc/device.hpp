@@ -136,6 +136,27 @@ __device__ __forceinline__ double wave_max_f64(double v) {
   return uniform_f64(v);
 }
 
+// Sum over the 64 lanes of a wave by butterfly: every lane ends with the same bits.
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&x)[NV]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) x[k] += __shfl_xor(x[k], o, 64);
+}
+
+// Total of nb momentum partials, read by a one-wave workgroup: lane l sums partials l, l+64, ...
+// in order, then the wave butterfly; the same bits in every workgroup.
+__device__ __forceinline__ void partials_total_wave(const double4 *__restrict__ mom, int nb,
+                                                    double (&P)[3]) {
+  P[0] = P[1] = P[2] = 0.0;
+  for (int b = threadIdx.x & 63; b < nb; b += 64) {
+    const double4 q = mom[b];
+    P[0] += q.x; P[1] += q.y; P[2] += q.z;
+  }
+  wave_sum<3>(P);
+}
+
 // Total momentum from per-block partials, summed in the same order by every workgroup.
 __device__ __forceinline__ void momentum_total(const double4 *__restrict__ mom, int nb, double (&P)[3],
                                                double *lds) {

@@ -84,7 +84,8 @@ int batched_max_group_n();
 int batched_max_wave_n();
 
 inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
-// workgroups (and momentum partials) of k_finalize: one per 64 bodies
+// momentum partials (and the workgroups of k_finalize and of the jump and drift kernels): one per
+// 64 bodies
 inline int fin_blocks(int64_t n) { return (int)((n + 63) / 64); }
 
 }  // namespace nbk

@@ -3,36 +3,36 @@
 // The drift advances each body on its two-body orbit about mu = G m0 with the f and g functions
 // in universal variables (Stumpff functions c_k), solved with the Laguerre-Conway iteration; one
 // body per lane, binary64 throughout. The jump shifts every position by h * P / m0; P is reduced
-// deterministically from per-workgroup partial sums by every workgroup in the same order.
+// deterministically from per-64-body partial sums by every workgroup in the same order.
 #include "internal.hpp"
 #include "kepler_core.hpp"
 
 namespace nbk {
 using namespace nbd;
 
-__global__ __launch_bounds__(kBlock) void k_momentum(const double4 *__restrict__ xm,
-                                                     const double4 *__restrict__ v, int n,
-                                                     double4 *__restrict__ mom) {
-  __shared__ double lds[3 * kBlock];
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+// One wave per workgroup: the per-body Kepler solve is long and latency-bound, so small n still
+// spreads over every compute unit. Momentum partials: one per 64 bodies (a wave butterfly).
+__global__ __launch_bounds__(64) void k_momentum(const double4 *__restrict__ xm,
+                                                 const double4 *__restrict__ v, int n,
+                                                 double4 *__restrict__ mom) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
   double P[3] = {0.0, 0.0, 0.0};
   if (i < n) {
     const double m = xm[i].w;
     const double4 q = v[i];
     P[0] = m * q.x; P[1] = m * q.y; P[2] = m * q.z;
   }
-  block_sum<3>(P, lds);
+  wave_sum<3>(P);
   if (threadIdx.x == 0) mom[blockIdx.x] = make_double4(P[0], P[1], P[2], 0.0);
 }
 
 // x_rec (may be null) receives a copy of the new positions.
-__global__ __launch_bounds__(kBlock) void k_jump(double4 *__restrict__ xm,
-                                                 const double4 *__restrict__ mom, int nb, int n,
-                                                 double h, double m0, double4 *__restrict__ x_rec) {
-  __shared__ double lds[3 * kBlock];
+__global__ __launch_bounds__(64) void k_jump(double4 *__restrict__ xm,
+                                             const double4 *__restrict__ mom, int nb, int n,
+                                             double h, double m0, double4 *__restrict__ x_rec) {
   double P[3];
-  momentum_total(mom, nb, P, lds);
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  partials_total_wave(mom, nb, P);
+  const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= n) return;
   const double sx = h * (P[0] / m0), sy = h * (P[1] / m0), sz = h * (P[2] / m0);
   double4 p = xm[i];
@@ -43,18 +43,17 @@ __global__ __launch_bounds__(kBlock) void k_jump(double4 *__restrict__ xm,
 
 // x_rec / v_rec (may be null) receive the positions after the jump (before the drift) and the
 // velocities after the drift.
-__global__ __launch_bounds__(kBlock) void k_jump_drift(double4 *__restrict__ xm,
-                                                       double4 *__restrict__ v,
-                                                       const double4 *__restrict__ mom_in, int nb,
-                                                       int n, double hjump, double dt, double m0,
-                                                       double mu, uint32_t *__restrict__ status,
-                                                       double4 *__restrict__ mom_out,
-                                                       double4 *__restrict__ x_rec,
-                                                       double4 *__restrict__ v_rec) {
-  __shared__ double lds[3 * kBlock];
+__global__ __launch_bounds__(64) void k_jump_drift(double4 *__restrict__ xm,
+                                                   double4 *__restrict__ v,
+                                                   const double4 *__restrict__ mom_in, int nb,
+                                                   int n, double hjump, double dt, double m0,
+                                                   double mu, uint32_t *__restrict__ status,
+                                                   double4 *__restrict__ mom_out,
+                                                   double4 *__restrict__ x_rec,
+                                                   double4 *__restrict__ v_rec) {
   double P[3];
-  momentum_total(mom_in, nb, P, lds);
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  partials_total_wave(mom_in, nb, P);
+  const int i = blockIdx.x * 64 + threadIdx.x;
   double Q[3] = {0.0, 0.0, 0.0};
   if (i < n) {
     const double sx = hjump * (P[0] / m0), sy = hjump * (P[1] / m0), sz = hjump * (P[2] / m0);
@@ -69,14 +68,14 @@ __global__ __launch_bounds__(kBlock) void k_jump_drift(double4 *__restrict__ xm,
     if (status) status[i] |= (uint32_t)st;
     Q[0] = p.w * q.x; Q[1] = p.w * q.y; Q[2] = p.w * q.z;
   }
-  block_sum<3>(Q, lds);
+  wave_sum<3>(Q);
   if (threadIdx.x == 0) mom_out[blockIdx.x] = make_double4(Q[0], Q[1], Q[2], 0.0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_drift(double4 *__restrict__ xm, double4 *__restrict__ v,
-                                                  int n, double dt, double mu,
-                                                  uint32_t *__restrict__ status) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(64) void k_drift(double4 *__restrict__ xm, double4 *__restrict__ v,
+                                              int n, double dt, double mu,
+                                              uint32_t *__restrict__ status) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= n) return;
   double4 p = xm[i];
   double4 q = v[i];
@@ -87,27 +86,27 @@ __global__ __launch_bounds__(kBlock) void k_drift(double4 *__restrict__ xm, doub
 }
 
 hipError_t launch_momentum(const double4 *xm, const double4 *v, int n, double4 *mom, hipStream_t st) {
-  hipLaunchKernelGGL(k_momentum, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, n, mom);
+  hipLaunchKernelGGL(k_momentum, dim3(fin_blocks(n)), dim3(64), 0, st, xm, v, n, mom);
   return hipGetLastError();
 }
 
 hipError_t launch_jump(double4 *xm, const double4 *mom, int nb, int n, double h, double m0,
                        hipStream_t st, double4 *x_rec) {
-  hipLaunchKernelGGL(k_jump, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, mom, nb, n, h, m0, x_rec);
+  hipLaunchKernelGGL(k_jump, dim3(fin_blocks(n)), dim3(64), 0, st, xm, mom, nb, n, h, m0, x_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_jump_drift(double4 *xm, double4 *v, const double4 *mom_in, int nb, int n,
                              double hjump, double dt, double m0, double mu, uint32_t *status,
                              double4 *mom_out, hipStream_t st, double4 *x_rec, double4 *v_rec) {
-  hipLaunchKernelGGL(k_jump_drift, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, mom_in, nb, n,
+  hipLaunchKernelGGL(k_jump_drift, dim3(fin_blocks(n)), dim3(64), 0, st, xm, v, mom_in, nb, n,
                      hjump, dt, m0, mu, status, mom_out, x_rec, v_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, uint32_t *status,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_drift, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, n, dt, mu, status);
+  hipLaunchKernelGGL(k_drift, dim3(fin_blocks(n)), dim3(64), 0, st, xm, v, n, dt, mu, status);
   return hipGetLastError();
 }
 
