@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch of the binary64 pair kernel from the FETCH_SIZE / WRITE_SIZE passes
 # (calibrated with a plain copy; see profiles/k_pairs_disk32768.md), valid for the kernel source
 # whose hash is stored beside it.
-PAIR_KERNEL_TRAFFIC = {"bytes": 95129580, "source_sha256": "7b24f9cbd78a7be6afe0be3ca8d0f3d57e7198d5985095e45b437ab255f65966"}
+PAIR_KERNEL_TRAFFIC = {"bytes": 84916895, "source_sha256": "c6d55da8f2013d92a83b07daf187384655325f969f5beb7bcaf2d5d60f0d84ef"}
 PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/pairs.hip", "paper_2604_09184_amd/csrc/device.hpp"]
 
 FLOP_PER_PAIR = 20                 # N-body convention: 3 sub, 5 for r^2, rsqrt, 3 for m r^-3, 6 accumulate, 2 slack
