@@ -29,6 +29,10 @@ sys.path.insert(0, ROOT)
 # whose hash is stored beside it.
 PAIR_KERNEL_TRAFFIC = {"bytes": 84916895, "source_sha256": "c6d55da8f2013d92a83b07daf187384655325f969f5beb7bcaf2d5d60f0d84ef"}
 PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/pairs.hip", "paper_2604_09184_amd/csrc/device.hpp"]
+# Binary64 flop the hardware executes per pair, 64 x (ADD + MUL + TRANS + 2 FMA) from the
+# SQ_INSTS_VALU_*_F64 counters of the same profile, for the same kernel source.
+PAIR_KERNEL_HW_FLOP = {"per_pair": 24.42, "source_sha256": PAIR_KERNEL_TRAFFIC["source_sha256"]}
+HBM_PEAK_GBPS = 8000.0             # MI355X HBM3E
 
 FLOP_PER_PAIR = 20                 # N-body convention: 3 sub, 5 for r^2, rsqrt, 3 for m r^-3, 6 accumulate, 2 slack
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 128 flop/clk x 2.4 GHz
@@ -46,6 +50,11 @@ def pair_kernel_sha():
 def traffic_bytes():
     t = PAIR_KERNEL_TRAFFIC
     return t["bytes"] if t["source_sha256"] == pair_kernel_sha() else None
+
+
+def hw_flop_per_pair():
+    t = PAIR_KERNEL_HW_FLOP
+    return t["per_pair"] if t["source_sha256"] == pair_kernel_sha() else None
 
 
 def timed(fn):
@@ -252,11 +261,22 @@ def main():
     # the dominant kernel alone: mean launch time of the pair kernel (HIP events on the stream)
     kernel_ms = ctx.bench_pairs(X, thr, reps=20)
     achieved = FLOP_PER_PAIR * n * (n - 1) / (kernel_ms / 1e3) / 1e12
+    traffic = traffic_bytes()
+    hwf = hw_flop_per_pair()
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic_bytes(), "kernel": "k_pairs (binary64)",
+                "traffic": traffic, "kernel": "k_pairs (binary64)",
                 "kernel_ms": round(kernel_ms, 4),
-                "pairs_per_s_kernel": n * (n - 1) / (kernel_ms / 1e3)}
+                "pairs_per_s_kernel": n * (n - 1) / (kernel_ms / 1e3),
+                # beside the algorithmic figure: the binary64 flop the hardware executes (counter
+                # profile of this kernel source) and the HBM rate of the counted traffic
+                "hw_fp64": None if hwf is None else {
+                    "flop_per_pair": hwf,
+                    "tflops": round(hwf * n * (n - 1) / (kernel_ms / 1e3) / 1e12, 3),
+                    "frac": round(hwf * n * (n - 1) / (kernel_ms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4)},
+                "hbm": None if traffic is None else {
+                    "GBps": round(traffic / (kernel_ms / 1e3) / 1e9, 1), "peak_GBps": HBM_PEAK_GBPS,
+                    "frac": round(traffic / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}}
 
     variants = {}
     if not args.no_variants:
