@@ -124,6 +124,20 @@ int nbody_step(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *t
                int32_t *pairs, int64_t cap, int64_t *count, int64_t *step_counts, void *stream);
 
 /*
+ * Close-encounter groups: the connected components of the graph whose edges are the close pairs,
+ * i.e. the sets of bodies that the hybrid method's close-encounter integration has to treat
+ * together (section "The hybrid symplectic integrator"). The edges are the first min(*count, cap)
+ * entries of pairs [cap][2] (device int32; count device int64), as written by nbody_encounters
+ * or nbody_step. labels [n] (device int32) receives for every body the smallest body index of its
+ * group (a body without close partners is its own group). out (device int64 [2]) receives
+ * {number of groups with at least two bodies, number of pairs ignored because an index lies
+ * outside 0..n-1 or i == j}. Lock-free union-find; the labels are unique, so the result does not
+ * depend on thread timing.
+ */
+int nbody_encounter_groups(nbody_ctx *ctx, int64_t n, const int32_t *pairs, int64_t cap,
+                           const int64_t *count, int32_t *labels, int64_t *out, void *stream);
+
+/*
  * Input check before integrating a state. The method has no softening, so a body at the central
  * mass (r_i = 0 in eq. Ha) or two bodies at one position (r_ij = 0 in eq. Hb) are invalid input.
  * result (device int64 [2]) receives {i, reason} for the smallest body index i with a problem

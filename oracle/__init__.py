@@ -46,6 +46,7 @@ def _lib():
         "or_kick_acc_q": (None, [I, P, P, P, P, P, P, P]),
         "or_kick_acc_rows": (None, [I, P, P, P, P, P, P, I, P, P, P]),
         "or_encounters": (I, [I, P, P, P, I, P]),
+        "or_groups": (I, [I, P, I, P, P]),
         "or_jump": (None, [I, P, P, P, P, D]),
         "or_drift": (ctypes.c_int, [I, P, P, P, D, P]),
         "or_drift_q": (ctypes.c_int, [I, P, P, P, D]),
@@ -138,6 +139,16 @@ def encounters(x, thr, cap=None):
     pairs = np.empty((max(cap, 1), 2), dtype=np.int32)
     cnt = _lib().or_encounters(n, _p(x), _p(H), _p(V), cap, _p(pairs))
     return pairs[:min(cnt, cap)].copy()
+
+
+def groups(n, pairs):
+    """Close-encounter groups: (labels, ngroups, ignored); labels[i] = smallest index in i's
+    connected component of the close-pair graph (breadth-first search, ascending start)."""
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    lab = np.empty(n, dtype=np.int32)
+    ign = ctypes.c_int64(0)
+    g = _lib().or_groups(n, _p(pr), pr.shape[0], _p(lab), ctypes.byref(ign))
+    return lab, int(g), int(ign.value)
 
 
 def jump(x, v, m, p, h):

@@ -456,6 +456,43 @@ int64_t or_encounters(int64_t n, const double *x, const double *H, const double 
   return encounters(n, x, H, V, cap, pairs);
 }
 
+// Close-encounter groups: the connected components of the graph whose edges are the close pairs
+// (the bodies that the hybrid method hands to its close-encounter integrator together). Every body
+// is labelled with the smallest index in its component: bodies are visited in ascending order and
+// a breadth-first search from each body not yet reached labels its whole component with it.
+// Returns the number of components with at least two bodies; pairs with an index outside 0..n-1
+// or with i == j are not edges and are counted in *ignored.
+int64_t or_groups(int64_t n, const int32_t *pairs, int64_t npairs, int32_t *label, int64_t *ignored) {
+  std::vector<std::vector<int64_t>> adj((size_t)n);
+  int64_t bad = 0;
+  for (int64_t k = 0; k < npairs; k++) {
+    const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j) {
+      bad++;
+      continue;
+    }
+    adj[(size_t)i].push_back(j);
+    adj[(size_t)j].push_back(i);
+  }
+  for (int64_t i = 0; i < n; i++) label[i] = -1;
+  int64_t groups = 0;
+  std::vector<int64_t> queue;
+  for (int64_t s = 0; s < n; s++) {
+    if (label[s] >= 0) continue;
+    label[s] = (int32_t)s;
+    queue.assign(1, s);
+    for (size_t q = 0; q < queue.size(); q++)
+      for (int64_t t : adj[(size_t)queue[q]])
+        if (label[t] < 0) {
+          label[t] = (int32_t)s;
+          queue.push_back(t);
+        }
+    if (queue.size() >= 2) groups++;
+  }
+  if (ignored) *ignored = bad;
+  return groups;
+}
+
 void or_jump(int64_t n, double *x, const double *v, const double *m, const double *prm, double h) {
   Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
   jump<double>(n, x, v, m, p, h);

@@ -60,6 +60,7 @@ EXPORTS = {
     "nbody_drift": [_I64, _P, _P, _D, _P, _P],
     "nbody_step": [_I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P],
     "nbody_validate": [_I64, _P, _P, _P, _P],
+    "nbody_encounter_groups": [_I64, _P, _I64, _P, _P, _P, _P],
     "nbody_energy": [_I64, _P, _P, _P, _P, _P],
     "nbody_bench_pairs": [_I64, _P, _P, _I32, _P, _P],
     "nbody_kick_vjp": [_I64, _P, _P, _D, _P, _P, _P],
@@ -220,6 +221,21 @@ class Context:
         c = int(count.item())
         res = (pairs[:min(c, pairs_cap)], c)
         return (res, sc) if step_counts else res
+
+    def encounter_groups(self, n, pairs, count):
+        """Close-encounter groups of an encounter list: (labels int32 [n] on the device, number
+        of groups with at least two bodies, number of ignored pairs). pairs: int32 (cap, 2) device
+        tensor; count: the true pair count, a device int64 tensor (or a host int)."""
+        if pairs.dtype != torch.int32 or pairs.dim() != 2 or pairs.shape[1] != 2 or not pairs.is_contiguous():
+            raise NBodyError("pairs must be a contiguous int32 (cap, 2) tensor")
+        if not torch.is_tensor(count):
+            count = torch.tensor([int(count)], dtype=torch.int64, device=pairs.device)
+        labels = torch.empty(int(n), dtype=torch.int32, device=pairs.device)
+        out = torch.empty(2, dtype=torch.int64, device=pairs.device)
+        self._check(lib().nbody_encounter_groups(self._h, int(n), _ptr(pairs), pairs.shape[0], _ptr(count),
+                                                 _ptr(labels), _ptr(out), _stream()), "nbody_encounter_groups")
+        o = out.cpu().tolist()
+        return labels, int(o[0]), int(o[1])
 
     def validate(self, xm, v):
         """(index, reason) of the first invalid body, or (-1, 0); reasons: 1 non-finite value,

@@ -26,7 +26,7 @@ struct Buf {
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
-             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_NUM };
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GMARK, B_NUM };
 
 }  // namespace
 
@@ -465,6 +465,23 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
            "step finalize");
   }
   if (emit) return emit_list(c, a, pairs, cap, count, st);
+  return NBODY_OK;
+}
+
+int nbody_encounter_groups(nbody_ctx *c, int64_t n, const int32_t *pairs, int64_t cap, const int64_t *count,
+                           int32_t *labels, int64_t *out, void *stream) {
+  TRY(check_n(c, n));
+  if (cap < 0) return fail(c, NBODY_E_INVAL, "cap < 0");
+  if (cap > 0) TRY(check_dev(c, pairs, "pairs", true));
+  TRY(check_dev(c, count, "count", true));
+  TRY(check_dev(c, labels, "labels", true));
+  TRY(check_dev(c, out, "out", true));
+  int *mark = (int *)ensure(c, B_GMARK, (size_t)n * sizeof(int));
+  if (!mark) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
+  const int64_t want = (cap + kBlock - 1) / kBlock;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
+  HIPCHK(c, launch_groups(pairs, cap, count, (int)n, labels, mark, out, blocks, (hipStream_t)stream),
+         "groups");
   return NBODY_OK;
 }
 

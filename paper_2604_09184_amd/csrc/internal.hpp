@@ -64,6 +64,11 @@ hipError_t launch_jump_vjp(const double4 *xm, const double4 *v, double h, double
 hipError_t launch_drift_vjp(const double4 *xm, const double4 *v, int n, double dt, double mu,
                             double4 *lam_x, double4 *lam_v, hipStream_t st);
 
+// groups.hip
+hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
+                         int32_t *labels, int *mark, int64_t *out, int union_blocks,
+                         hipStream_t st);
+
 // batched.hip
 constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048
 constexpr int kBatchedWaves = 8;   // waves per workgroup of the batched kernel

@@ -312,6 +312,43 @@ def test_step_counts_match_oracle(ctx, case):
     np.testing.assert_array_equal(sc0, ref[:1])
 
 
+def test_encounter_groups_from_lists(ctx):
+    """Groups of real encounter lists (the 2048 disk, a 400-body clump in N = 16384) equal the
+    oracle's breadth-first components of the same list, label for label."""
+    for name, d in (("disk2048", diskgen.workload("disk2048")), ("clump16384", cluster_disk(16384, 400))):
+        say(f"groups {name}")
+        X, V = to_dev(d)
+        thr = ctx.rcrit(X, V)
+        pairs, count = ctx.encounters(X, thr, cap=1 << 20)
+        lab, g, ign = ctx.encounter_groups(X.shape[0], pairs.contiguous(), count)
+        olab, og, oign = oracle.groups(X.shape[0], pairs.cpu().numpy())
+        np.testing.assert_array_equal(lab.cpu().numpy(), olab)
+        assert (g, ign) == (og, oign) and og > 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 70000])
+def test_encounter_groups_synthetic_edges(ctx, n):
+    """Random edges with repeats, self-pairs and out-of-range indices; a shuffled chain (the
+    deepest union-find trees); truncation by cap; an empty list."""
+    say(f"groups synthetic n={n}")
+    rng = np.random.default_rng(n)
+    cases = []
+    e = rng.integers(-2, n + 2, size=(max(1, n // 2), 2)).astype(np.int32)
+    cases.append(("random", e, len(e)))
+    if n > 1:
+        ch = np.stack([np.arange(n - 1), np.arange(1, n)], axis=1).astype(np.int32)
+        cases.append(("chain", ch[rng.permutation(n - 1)], n - 1))
+        cases.append(("truncated", ch[rng.permutation(n - 1)], (n - 1) // 3))
+    cases.append(("empty", np.zeros((4, 2), dtype=np.int32), 0))
+    for label, edges, cap in cases:
+        P = torch.tensor(edges, device=DEV)
+        count = torch.tensor([len(edges)], dtype=torch.int64, device=DEV)
+        lab, g, ign = ctx.encounter_groups(n, P[:max(cap, 1)].contiguous() if cap else P[:0].contiguous(), count)
+        olab, og, oign = oracle.groups(n, edges[:cap])
+        np.testing.assert_array_equal(lab.cpu().numpy(), olab, err_msg=label)
+        assert (g, ign) == (og, oign), label
+
+
 def test_validate_reports_first_problem(ctx):
     say("validate")
     d = diskgen.workload("disk2048", n=1000)
@@ -438,3 +475,17 @@ def test_tuning_knobs_validate(nb):
         ctx.tune("no_such_knob", 3)
     with pytest.raises(nb.NBodyError):
         ctx.tune("emit_slots", 0)
+
+
+def test_encounter_groups_full_size(ctx, big):
+    """The N = 32768 disk's list at its initial positions."""
+    say("groups disk32768")
+    d, _ = big
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    pairs, count = ctx.encounters(X, thr, cap=1 << 20)
+    lab, g, ign = ctx.encounter_groups(X.shape[0], pairs.contiguous(), count)
+    olab, og, oign = oracle.groups(X.shape[0], pairs.cpu().numpy())
+    np.testing.assert_array_equal(lab.cpu().numpy(), olab)
+    assert (g, ign) == (og, oign)
+    say(f"  {count} pairs, {g} groups, largest {np.bincount(olab).max()}")

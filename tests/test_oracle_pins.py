@@ -390,3 +390,51 @@ def test_step_is_symplectic(params):
     Om = np.block([[np.zeros((3 * n, 3 * n)), np.eye(3 * n)], [-np.eye(3 * n), np.zeros((3 * n, 3 * n))]])
     S = J.T @ Om @ J
     assert np.abs(S - Om).max() < 1e-9 * np.abs(J).max() ** 2
+
+
+# ------------------------------------------------------------------ close-encounter groups
+def test_groups_hand_cases():
+    """Connected components of the close-pair graph, labelled by the smallest index."""
+    lab, g, ign = oracle.groups(6, [[0, 1], [1, 2], [4, 5]])            # chain and a pair
+    assert lab.tolist() == [0, 0, 0, 3, 4, 4] and g == 2 and ign == 0
+    lab, g, ign = oracle.groups(5, [[4, 0], [4, 1], [4, 2], [4, 3]])    # star, edges given (j, i)
+    assert lab.tolist() == [0] * 5 and g == 1
+    lab, g, ign = oracle.groups(4, [[2, 3], [3, 2], [2, 3]])            # repeated edges
+    assert lab.tolist() == [0, 1, 2, 2] and g == 1
+    lab, g, ign = oracle.groups(3, [])                                  # no pairs: singletons
+    assert lab.tolist() == [0, 1, 2] and g == 0
+    lab, g, ign = oracle.groups(4, [[1, 1], [0, 7], [-1, 2], [3, 0]])   # not edges: ignored
+    assert lab.tolist() == [0, 1, 2, 0] and g == 1 and ign == 3
+
+
+def _closure_labels(n, edges):
+    """Brute force: reachability by repeated boolean squaring, label = smallest reachable index."""
+    A = np.eye(n, dtype=bool)
+    for i, j in edges:
+        A[i, j] = A[j, i] = True
+    while True:
+        B = (A.astype(np.int64) @ A.astype(np.int64)) > 0
+        if (B == A).all():
+            break
+        A = B
+    return np.array([np.flatnonzero(A[i])[0] for i in range(n)])
+
+
+def test_groups_against_brute_force_and_library():
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(3)
+    for n, ne in ((1, 0), (2, 1), (9, 5), (40, 30), (200, 150), (500, 700)):
+        e = rng.integers(0, n, size=(ne, 2)) if ne else np.zeros((0, 2), dtype=np.int64)
+        e = e[e[:, 0] != e[:, 1]]
+        lab, g, ign = oracle.groups(n, e)
+        assert ign == 0
+        if n <= 200:
+            np.testing.assert_array_equal(lab, _closure_labels(n, e.tolist()))
+        ncomp, comp = connected_components(coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n)),
+                                           directed=False)
+        # same partition: equal labels exactly when the library puts bodies in one component
+        np.testing.assert_array_equal(lab[:, None] == lab[None, :], comp[:, None] == comp[None, :])
+        sizes = np.bincount(comp, minlength=ncomp)
+        assert g == int((sizes >= 2).sum())
+        assert (lab <= np.arange(n)).all() and (lab[lab] == lab).all()
