@@ -123,3 +123,29 @@ def test_autotune_and_rejections(nb):
         ctx.step_batched(np.array([1, 5]), X, V, 1)
     with pytest.raises(nb.NBodyError):
         ctx.set_batched_tiles([2] * 6)
+
+
+def test_full_ensemble_in_bench_configuration(nb):
+    """The whole 4096-system ensemble, autotuned, 100 steps in one launch (as the benchmark runs
+    it); six systems (the largest, the smallest and four drawn at random) against the oracle's
+    100 steps, with close-pair counts at the final positions."""
+    say("batched ensemble4096 x100 vs oracle on sampled systems")
+    p = diskgen.PARAMS
+    offs, x, v, m = diskgen.ensemble()
+    X, V = to_dev(x, v, m)
+    ctx = nb.Context(nb.Params(**p))
+    ctx.autotune_batched(offs, X, V, nsteps=10)
+    npairs = ctx.step_batched(offs, X, V, 100, count_pairs=True).cpu().numpy()
+    Xb, Vb = X.cpu().numpy(), V.cpu().numpy()
+    sizes = offs[1:] - offs[:-1]
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))]
+    pick += [int(s) for s in np.random.default_rng(8).choice(len(sizes), 4, replace=False)]
+    for s in pick:
+        a, b = offs[s], offs[s + 1]
+        othr = oracle.thresholds(x[a:b], v[a:b], m[a:b], p)
+        ox, ov, _ = oracle.step(x[a:b], v[a:b], m[a:b], p, 100, thr=othr)
+        ex, ev = rel_state_err(Xb[a:b, :3], ox), rel_state_err(Vb[a:b, :3], ov)
+        say(f"  system {s} (N = {b - a}): state rel err x {ex:.1e} v {ev:.1e}, pairs {npairs[s]}")
+        # rounding differences grow by about 1e3 over 100 steps of these disks
+        assert ex < 1e-10 and ev < 1e-10
+        assert npairs[s] == len(oracle.encounters(ox, othr))

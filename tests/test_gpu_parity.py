@@ -489,3 +489,34 @@ def test_encounter_groups_full_size(ctx, big):
     np.testing.assert_array_equal(lab.cpu().numpy(), olab)
     assert (g, ign) == (og, oign)
     say(f"  {count} pairs, {g} groups, largest {np.bincount(olab).max()}")
+
+
+# ------------------------------------------------------------------ full size ring (N = 131072)
+def test_full_size_ring_f64_and_split(nb):
+    """The 131072-body ring in the launch configuration the benchmark times: binary64 and split
+    kicks on 48 sampled rows against the oracle; the full encounter list at the initial
+    positions bit-exact."""
+    say("ring131072 kick f64/split sampled rows + list")
+    p = diskgen.PARAMS
+    d = diskgen.workload("ring131072")
+    n = len(d["m"])
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    rows = np.concatenate([np.random.default_rng(21).choice(n, 44, replace=False), [0, 1, n // 2, n - 1]])
+    oacc, l1 = oracle.kick_acc_rows(d["x"], d["m"], othr, p, rows)
+    X, V = to_dev(d)
+    for prec, bound in ((nb.PREC_F64, 1e-12), (nb.PREC_SPLIT, 1e-6)):
+        ctx = nb.Context(nb.Params(**p, precision=prec))
+        thr = ctx.rcrit(X, V)
+        acc = ctx.accelerations(X, thr).cpu().numpy()[:, :3]
+        err = (np.abs(acc[rows] - oacc).max(1) / np.maximum(np.abs(oacc).max(1), l1)).max()
+        say(f"  precision {prec}: max rel err {err:.2e}")
+        assert err < bound
+        if prec == nb.PREC_SPLIT:
+            assert err > 1e-12           # really the binary32 core
+    ctx = nb.Context(nb.Params(**p))
+    thr = ctx.rcrit(X, V)
+    pairs, count = ctx.encounters(X, thr, cap=1 << 25)
+    ref = oracle.encounters(d["x"], othr)
+    say(f"  {count} pairs")
+    assert count == len(ref)
+    np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
