@@ -47,6 +47,8 @@ def _lib():
         "or_kick_acc_rows": (None, [I, P, P, P, P, P, P, I, P, P, P]),
         "or_encounters": (I, [I, P, P, P, I, P]),
         "or_groups": (I, [I, P, I, P, P]),
+        "or_ce_drift_group": (ctypes.c_int, [P, ctypes.c_int, P, P, P, P, P, D, D]),
+        "or_step_hybrid": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P]),
         "or_jump": (None, [I, P, P, P, P, D]),
         "or_drift": (ctypes.c_int, [I, P, P, P, D, P]),
         "or_drift_q": (ctypes.c_int, [I, P, P, P, D]),
@@ -149,6 +151,27 @@ def groups(n, pairs):
     ign = ctypes.c_int64(0)
     g = _lib().or_groups(n, _p(pr), pr.shape[0], _p(lab), ctypes.byref(ign))
     return lab, int(g), int(ign.value)
+
+
+def ce_drift_group(x, v, m, rc, p, idx, h, tol=1e-17):
+    """Close-encounter drift of the group idx (H_A in full, Gragg-Bulirsch-Stoer in long double);
+    returns new copies of x, v and the status."""
+    x = _f64(x).copy(); v = _f64(v).copy()
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    st = _lib().or_ce_drift_group(_p(idx), len(idx), _p(x), _p(v), _p(_f64(m)), _p(_f64(rc)), _p(_prm(p)),
+                                  float(h), float(tol))
+    return x, v, st
+
+
+def step_hybrid(x, v, m, p, nsteps, thr=None, tol=1e-17):
+    """nsteps hybrid steps: the drift integrates every close-encounter group in full (H_A with its
+    [1 - K] part); returns x, v, status, stats = (groups integrated, largest group, bodies)."""
+    x = _f64(x).copy(); v = _f64(v).copy(); m = _f64(m)
+    rc, H, V = (None, None, None) if thr is None else (_f64(t) for t in thr)
+    stats = np.zeros(3, dtype=np.int64)
+    st = _lib().or_step_hybrid(len(m), _p(x), _p(v), _p(m), _p(_prm(p)), int(nsteps), _p(rc), _p(H), _p(V),
+                               float(tol), _p(stats))
+    return x, v, st, tuple(int(s) for s in stats)
 
 
 def jump(x, v, m, p, h):

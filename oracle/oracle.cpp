@@ -360,6 +360,225 @@ template <> int drift_all<double>(int64_t n, double *x, double *v, const Params 
 
 // ---------------------------------------------------------------- one call of nsteps steps
 // B(h) C(h) A(dt) C(h) B(h) per step, h = dt/2, thresholds from the state at call start.
+// Close-encounter groups: the connected components of the graph whose edges are the close pairs
+// (the bodies that the hybrid method hands to its close-encounter integrator together). Every body
+// is labelled with the smallest index in its component: bodies are visited in ascending order and
+// a breadth-first search from each body not yet reached labels its whole component with it.
+// Returns the number of components with at least two bodies; pairs with an index outside 0..n-1
+// or with i == j are not edges and are counted in *ignored.
+static int64_t groups_bfs(int64_t n, const int32_t *pairs, int64_t npairs, int32_t *label, int64_t *ignored) {
+  std::vector<std::vector<int64_t>> adj((size_t)n);
+  int64_t bad = 0;
+  for (int64_t k = 0; k < npairs; k++) {
+    const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j) {
+      bad++;
+      continue;
+    }
+    adj[(size_t)i].push_back(j);
+    adj[(size_t)j].push_back(i);
+  }
+  for (int64_t i = 0; i < n; i++) label[i] = -1;
+  int64_t groups = 0;
+  std::vector<int64_t> queue;
+  for (int64_t s = 0; s < n; s++) {
+    if (label[s] >= 0) continue;
+    label[s] = (int32_t)s;
+    queue.assign(1, s);
+    for (size_t q = 0; q < queue.size(); q++)
+      for (int64_t t : adj[(size_t)queue[q]])
+        if (label[t] < 0) {
+          label[t] = (int32_t)s;
+          queue.push_back(t);
+        }
+    if (queue.size() >= 2) groups++;
+  }
+  if (ignored) *ignored = bad;
+  return groups;
+}
+
+// ---------------------------------------------------------------- close-encounter drift (eq. Ha)
+// H_A in full: sum_i (p_i^2/2m_i - G m0 m_i/r_i) - sum_{i<j} G m_i m_j [1 - K(r_ij)]/r_ij. The
+// bodies of a close-encounter group move under the equations of motion of H_A restricted to the
+// group:
+//   dx_i/dt = v_i,
+//   dv_i/dt = -G m0 x_i/|x_i|^3 + G sum_{j in group, j != i} m_j ((1 - K)/r^3 + K'(r)/r^2) d_ij,
+// with d_ij = x_j - x_i: the pair term is minus the gradient of the [1 - K] part of the pair
+// potential, the complement of the kick's weight, and vanishes for r >= rc_ij. Bodies in no group
+// keep the Kepler drift.
+template <class T>
+static void ce_rhs(int k, const T *y, const double *m, const double *rc, const Params &p, T *f) {
+  const T *x = y, *v = y + 3 * k;
+  for (int i = 0; i < k; i++) {
+    T r2 = x[3 * i] * x[3 * i] + x[3 * i + 1] * x[3 * i + 1] + x[3 * i + 2] * x[3 * i + 2];
+    T r = msqrt(r2);
+    T s = T(0) - T(p.G * p.m0) / (r2 * r);
+    T a[3] = {s * x[3 * i], s * x[3 * i + 1], s * x[3 * i + 2]};
+    for (int j = 0; j < k; j++) {
+      if (j == i) continue;
+      T d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+      T q2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      T q = msqrt(q2);
+      double rcij = std::max(rc[i], rc[j]);
+      T yc = (q - T(p.f_in * rcij)) / T((1.0 - p.f_in) * rcij);
+      if (val(yc) >= 1) continue;
+      T K, dKdy;
+      changeover(yc, &K, &dKdy);
+      T dKdr = dKdy / T((1.0 - p.f_in) * rcij);
+      T c = T(p.G * m[j]) * ((T(1) - K) / (q2 * q) + dKdr / q2);
+      for (int l = 0; l < 3; l++) a[l] = a[l] + c * d[l];
+    }
+    for (int l = 0; l < 3; l++) {
+      f[3 * i + l] = v[3 * i + l];
+      f[3 * k + 3 * i + l] = a[l];
+    }
+  }
+}
+
+// Gragg-Bulirsch-Stoer integration of one group over time h: a macro step H is covered by
+// modified-midpoint sweeps with n = 2, 4, ..., 16 substeps, and the sweeps are extrapolated to
+// zero substep length as a polynomial in (H/n)^2 (Aitken-Neville). A step is accepted when the
+// last two extrapolants agree to tol, relative to the group's largest position and velocity;
+// otherwise H is halved. y = [x (3k), v (3k)] in and out. Returns 0, or 1 if H had to be halved
+// more than 60 times in a row.
+template <class T>
+static int ce_drift_group(int k, T *y, const double *m, const double *rc, const Params &p, double h,
+                          double tol) {
+  const int seq[8] = {2, 4, 6, 8, 10, 12, 14, 16};
+  const int D = 6 * k;
+  std::vector<T> R(8 * (size_t)D), zm(D), zc(D), zn(D), f(D), est(D);
+  T t = T(0), H = T(h);
+  const T hT = T(h);
+  int halvings = 0;
+  while (val(mabs(hT - t)) > 0) {
+    if (val(mabs(H)) > val(mabs(hT - t))) H = hT - t;
+    T sx = T(0), sv = T(0);
+    for (int i = 0; i < 3 * k; i++) {
+      sx = mmax(sx, mabs(y[i]));
+      sv = mmax(sv, mabs(y[3 * k + i]));
+    }
+    int accepted = -1;
+    for (int c = 0; c < 8 && accepted < 0; c++) {
+      const int ns = seq[c];
+      const T hs = H / T(ns);
+      // modified midpoint: z1 = z0 + hs f(z0); z_{s+1} = z_{s-1} + 2 hs f(z_s); end value
+      // (z_n + z_{n-1} + hs f(z_n)) / 2
+      for (int i = 0; i < D; i++) zm[i] = y[i];
+      ce_rhs<T>(k, zm.data(), m, rc, p, f.data());
+      for (int i = 0; i < D; i++) zc[i] = zm[i] + hs * f[i];
+      for (int s = 1; s < ns; s++) {
+        ce_rhs<T>(k, zc.data(), m, rc, p, f.data());
+        for (int i = 0; i < D; i++) {
+          zn[i] = zm[i] + T(2) * hs * f[i];
+          zm[i] = zc[i];
+          zc[i] = zn[i];
+        }
+      }
+      ce_rhs<T>(k, zc.data(), m, rc, p, f.data());
+      for (int i = 0; i < D; i++) est[i] = (zc[i] + zm[i] + hs * f[i]) / T(2);
+      // Aitken-Neville in (H/n)^2: row c from row c - 1
+      for (int i = 0; i < D; i++) {
+        T cur = est[i];
+        for (int j = 1; j <= c; j++) {
+          const T old = R[(size_t)(j - 1) * D + i];
+          R[(size_t)(j - 1) * D + i] = cur;
+          const T ratio = T(seq[c]) / T(seq[c - j]);
+          cur = cur + (cur - old) / (ratio * ratio - T(1));
+        }
+        R[(size_t)c * D + i] = cur;
+      }
+      if (c >= 2) {
+        double err = 0;
+        for (int i = 0; i < D; i++) {
+          const T sc = i < 3 * k ? sx : sv;
+          err = std::max(err, val(mabs(R[(size_t)c * D + i] - R[(size_t)(c - 1) * D + i]) / sc));
+        }
+        if (err <= tol) accepted = c;
+      }
+    }
+    if (accepted < 0) {
+      H = H / T(2);
+      if (++halvings > 60) return 1;
+      continue;
+    }
+    halvings = 0;
+    for (int i = 0; i < D; i++) y[i] = R[(size_t)accepted * D + i];
+    t = t + H;
+    if (accepted <= 4) H = H * T(2);
+  }
+  return 0;
+}
+
+// Drift of every body over h with the close-encounter groups given by labels (smallest index of
+// each body's group; a body alone in its group keeps the Kepler drift).
+template <class T>
+static int drift_groups(int64_t n, T *x, T *v, const T *m, const double *rc, const int32_t *label,
+                        const Params &p, double h, double tol, int64_t *stats) {
+  std::vector<std::vector<int64_t>> members((size_t)n);
+  for (int64_t i = 0; i < n; i++) members[(size_t)label[i]].push_back(i);
+  int worst = 0;
+  for (int64_t r = 0; r < n; r++) {
+    const auto &g = members[(size_t)r];
+    if (g.empty()) continue;
+    if (g.size() == 1) {
+      const int64_t i = g[0];
+      worst = std::max(worst, kepler<T>(x + 3 * i, v + 3 * i, p.G * p.m0, h));
+      continue;
+    }
+    const int k = (int)g.size();
+    std::vector<T> y(6 * (size_t)k);
+    std::vector<double> mg(k), rcg(k);
+    for (int a = 0; a < k; a++) {
+      for (int l = 0; l < 3; l++) {
+        y[3 * a + l] = x[3 * g[a] + l];
+        y[3 * k + 3 * a + l] = v[3 * g[a] + l];
+      }
+      mg[a] = val(m[g[a]]);
+      rcg[a] = rc[g[a]];
+    }
+    const int st = ce_drift_group<T>(k, y.data(), mg.data(), rcg.data(), p, h, tol);
+    worst = std::max(worst, st);
+    for (int a = 0; a < k; a++)
+      for (int l = 0; l < 3; l++) {
+        x[3 * g[a] + l] = y[3 * a + l];
+        v[3 * g[a] + l] = y[3 * k + 3 * a + l];
+      }
+    if (stats) {
+      stats[0] += 1;
+      stats[1] = std::max<int64_t>(stats[1], k);
+      stats[2] += k;
+    }
+  }
+  return worst;
+}
+
+// nsteps hybrid steps: as steps() but the drift integrates H_A in full, every close-encounter
+// group (from the close pairs at the positions of the step's first kick) with ce_drift_group.
+static int steps_hybrid(int64_t n, double *x, double *v, const double *m, const Params &p, int nsteps,
+                        const double *rc, const double *H, const double *V, double tol, int64_t *stats) {
+  std::vector<double> acc(3 * n);
+  std::vector<int32_t> label(n);
+  const double h = 0.5 * p.dt;
+  int worst = 0;
+  for (int s = 0; s < nsteps; s++) {
+    kick_acc<double>(n, x, m, rc, H, V, p, acc.data(), nullptr, nullptr);
+    for (int64_t i = 0; i < 3 * n; i++) v[i] = v[i] + h * acc[i];
+    const int64_t np = encounters(n, x, H, V, 0, nullptr);
+    std::vector<int32_t> pairs(2 * (size_t)std::max<int64_t>(np, 1));
+    encounters(n, x, H, V, np, pairs.data());
+    groups_bfs(n, pairs.data(), np, label.data(), nullptr);
+    jump<double>(n, x, v, m, p, h);
+    std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n), ml(m, m + n);
+    worst = std::max(worst, drift_groups<long double>(n, xl.data(), vl.data(), ml.data(), rc, label.data(),
+                                                      p, p.dt, tol, stats));
+    for (int64_t i = 0; i < 3 * n; i++) { x[i] = (double)xl[i]; v[i] = (double)vl[i]; }
+    jump<double>(n, x, v, m, p, h);
+    kick_acc<double>(n, x, m, rc, H, V, p, acc.data(), nullptr, nullptr);
+    for (int64_t i = 0; i < 3 * n; i++) v[i] = v[i] + h * acc[i];
+  }
+  return worst;
+}
+
 template <class T>
 static int steps(int64_t n, T *x, T *v, const T *m, const Params &p, int nsteps,
                  const double *rc, const double *H, const double *V) {
@@ -456,41 +675,48 @@ int64_t or_encounters(int64_t n, const double *x, const double *H, const double 
   return encounters(n, x, H, V, cap, pairs);
 }
 
-// Close-encounter groups: the connected components of the graph whose edges are the close pairs
-// (the bodies that the hybrid method hands to its close-encounter integrator together). Every body
-// is labelled with the smallest index in its component: bodies are visited in ascending order and
-// a breadth-first search from each body not yet reached labels its whole component with it.
-// Returns the number of components with at least two bodies; pairs with an index outside 0..n-1
-// or with i == j are not edges and are counted in *ignored.
 int64_t or_groups(int64_t n, const int32_t *pairs, int64_t npairs, int32_t *label, int64_t *ignored) {
-  std::vector<std::vector<int64_t>> adj((size_t)n);
-  int64_t bad = 0;
-  for (int64_t k = 0; k < npairs; k++) {
-    const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
-    if (i < 0 || j < 0 || i >= n || j >= n || i == j) {
-      bad++;
-      continue;
+  return groups_bfs(n, pairs, npairs, label, ignored);
+}
+
+// Close-encounter drift of one group (member indices idx[0..k-1] into x, v, m, rc) over time h,
+// in long double, to the relative tolerance tol. Returns the integrator status.
+int or_ce_drift_group(const int64_t *idx, int k, double *x, double *v, const double *m, const double *rc,
+                      const double *prm, double h, double tol) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<long double> y(6 * (size_t)k);
+  std::vector<double> mg(k), rcg(k);
+  for (int a = 0; a < k; a++) {
+    for (int l = 0; l < 3; l++) {
+      y[3 * a + l] = x[3 * idx[a] + l];
+      y[3 * k + 3 * a + l] = v[3 * idx[a] + l];
     }
-    adj[(size_t)i].push_back(j);
-    adj[(size_t)j].push_back(i);
+    mg[a] = m[idx[a]];
+    rcg[a] = rc[idx[a]];
   }
-  for (int64_t i = 0; i < n; i++) label[i] = -1;
-  int64_t groups = 0;
-  std::vector<int64_t> queue;
-  for (int64_t s = 0; s < n; s++) {
-    if (label[s] >= 0) continue;
-    label[s] = (int32_t)s;
-    queue.assign(1, s);
-    for (size_t q = 0; q < queue.size(); q++)
-      for (int64_t t : adj[(size_t)queue[q]])
-        if (label[t] < 0) {
-          label[t] = (int32_t)s;
-          queue.push_back(t);
-        }
-    if (queue.size() >= 2) groups++;
+  const int st = ce_drift_group<long double>(k, y.data(), mg.data(), rcg.data(), p, h, tol);
+  for (int a = 0; a < k; a++)
+    for (int l = 0; l < 3; l++) {
+      x[3 * idx[a] + l] = (double)y[3 * a + l];
+      v[3 * idx[a] + l] = (double)y[3 * k + 3 * a + l];
+    }
+  return st;
+}
+
+// nsteps hybrid steps (the drift integrates the close-encounter groups). stats[3] = {groups
+// integrated, largest group, bodies in groups}, accumulated over the steps (may be NULL).
+int or_step_hybrid(int64_t n, double *x, double *v, const double *m, const double *prm, int nsteps,
+                   const double *rc_in, const double *H_in, const double *V_in, double tol, int64_t *stats) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<double> rc(n), H(n), V(n);
+  if (rc_in && H_in && V_in) {
+    std::copy(rc_in, rc_in + n, rc.begin()); std::copy(H_in, H_in + n, H.begin());
+    std::copy(V_in, V_in + n, V.begin());
+  } else {
+    thresholds(n, x, v, m, p, rc.data(), H.data(), V.data());
   }
-  if (ignored) *ignored = bad;
-  return groups;
+  if (stats) stats[0] = stats[1] = stats[2] = 0;
+  return steps_hybrid(n, x, v, m, p, nsteps, rc.data(), H.data(), V.data(), tol, stats);
 }
 
 void or_jump(int64_t n, double *x, const double *v, const double *m, const double *prm, double h) {

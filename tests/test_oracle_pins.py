@@ -438,3 +438,114 @@ def test_groups_against_brute_force_and_library():
         sizes = np.bincount(comp, minlength=ncomp)
         assert g == int((sizes >= 2).sum())
         assert (lab <= np.arange(n)).all() and (lab[lab] == lab).all()
+
+
+# ------------------------------------------------------------------ close-encounter drift (full H_A)
+@pytest.fixture(scope="module")
+def disk2048_groups(params):
+    d = diskgen.workload("disk2048")
+    thr = oracle.thresholds(d["x"], d["v"], d["m"], params)
+    lab, g, _ = oracle.groups(len(d["m"]), oracle.encounters(d["x"], thr))
+    return d, thr, lab
+
+
+def test_ce_drift_far_group_is_kepler(params, disk2048_groups):
+    """Two bodies far outside each other's critical radius: the [1 - K] term is zero and the group
+    integration must reproduce two independent Kepler drifts (closed-form f and g functions)."""
+    d, (rc, H, V), _ = disk2048_groups
+    idx = np.array([3, 1700])
+    assert np.linalg.norm(d["x"][3] - d["x"][1700]) > 10 * max(rc[3], rc[1700])
+    xa, va, st = oracle.ce_drift_group(d["x"], d["v"], d["m"], rc, params, idx, params["dt"])
+    xk, vk, _ = oracle.drift(d["x"][idx], d["v"][idx], params, params["dt"])
+    assert st == 0
+    np.testing.assert_allclose(xa[idx], xk, rtol=0, atol=1e-15 * np.abs(xk).max())
+    np.testing.assert_allclose(va[idx], vk, rtol=0, atol=1e-15 * np.abs(vk).max())
+
+
+def _energy_A(x, v, m, rc, idx, p):
+    """H_A of the group idx from its definition: Kepler energies minus the [1 - K] pair part."""
+    E = 0.0
+    for a in idx:
+        E += 0.5 * m[a] * (v[a] ** 2).sum() - p["G"] * p["m0"] * m[a] / np.linalg.norm(x[a])
+    for k, a in enumerate(idx):
+        for b in idx[k + 1:]:
+            q = np.linalg.norm(x[b] - x[a])
+            rcij = max(rc[a], rc[b])
+            y = (q - p["f_in"] * rcij) / ((1 - p["f_in"]) * rcij)
+            K, _ = oracle.changeover(min(max(y, 0.0), 1.0))
+            E -= p["G"] * m[a] * m[b] * (1 - K) / q
+    return E
+
+
+def test_ce_drift_conserves_HA_and_reverses(params, disk2048_groups):
+    """The largest group of the 2048 disk (10 bodies): H_A and the group's angular momentum are
+    conserved, the integration is time-reversible, and the [1 - K] term does act."""
+    d, (rc, H, V), lab = disk2048_groups
+    idx = np.flatnonzero(lab == np.argmax(np.bincount(lab)))
+    assert len(idx) == 10
+    x, v, m = d["x"], d["v"], d["m"]
+    xa, va, st = oracle.ce_drift_group(x, v, m, rc, params, idx, params["dt"])
+    assert st == 0
+    e0, e1 = _energy_A(x, v, m, rc, idx, params), _energy_A(xa, va, m, rc, idx, params)
+    assert abs(e1 - e0) < 1e-14 * abs(e0)
+    L0 = (m[idx, None] * np.cross(x[idx], v[idx])).sum(0)
+    L1 = (m[idx, None] * np.cross(xa[idx], va[idx])).sum(0)
+    assert np.abs(L1 - L0).max() < 1e-15 * np.abs(L0).max()
+    xb, vb, _ = oracle.ce_drift_group(xa, va, m, rc, params, idx, -params["dt"])
+    assert np.abs(xb[idx] - x[idx]).max() < 1e-14 * np.abs(x[idx]).max()
+    assert np.abs(vb[idx] - v[idx]).max() < 1e-14 * np.abs(v[idx]).max()
+    xk, vk, _ = oracle.drift(x[idx], v[idx], params, params["dt"])
+    assert np.abs(xa[idx] - xk).max() > 1e-9                        # the pair term is not zero
+
+
+def test_ce_drift_tight_binary_is_two_body_kepler(params):
+    """A bound binary well inside f_in rc (K = 0: full Newtonian pull) with a negligible central
+    mass: the relative orbit is the two-body Kepler orbit with mu = G (m1 + m2) and the centre of
+    mass moves uniformly (closed forms)."""
+    p = dict(params, m0=1e-30)
+    m = np.array([3e-6, 1e-6])
+    sep = 2e-3
+    x = np.array([[1.0, 0.0, 0.0], [1.0 + sep, 5e-5, 0.0]])
+    vrel = np.sqrt(p["G"] * m.sum() / sep) * 0.8
+    v = np.array([[0.01, 0.02, 0.0], [0.01, 0.02 + vrel, 1e-3 * vrel]])
+    rc = np.array([5e-2, 5e-2])
+    h = 1.0                                   # about 3.5 orbits of the binary
+    xa, va, st = oracle.ce_drift_group(x, v, m, rc, p, np.array([0, 1]), h)
+    assert st == 0
+    assert np.linalg.norm(xa[1] - xa[0]) < 0.1 * rc[0]              # stayed where K = 0
+    M = m.sum()
+    xc0, vc0 = (m[:, None] * x).sum(0) / M, (m[:, None] * v).sum(0) / M
+    xr, vr, _ = oracle.drift((x[1] - x[0])[None], (v[1] - v[0])[None], dict(p, m0=M), h)
+    xc1, vc1 = (m[:, None] * xa).sum(0) / M, (m[:, None] * va).sum(0) / M
+    np.testing.assert_allclose(xc1, xc0 + h * vc0, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(vc1, vc0, rtol=0, atol=1e-15 * vrel)   # rounding of velocities of size vrel
+    # the integration error is relative to the heliocentric scale (1 AU), so against the
+    # separation it is looser by 1/sep
+    np.testing.assert_allclose(xa[1] - xa[0], xr[0], rtol=0, atol=1e-11 * sep)
+    np.testing.assert_allclose(va[1] - va[0], vr[0], rtol=0, atol=1e-11 * vrel)
+
+
+def test_hybrid_step_conserves_full_energy(params, disk2048_groups):
+    """The hybrid step integrates H_A in full, so it conserves the full energy E (the plain step
+    conserves the K-weighted E' instead): over 20 steps of the 2048 disk, E drifts at ~1e-10 in
+    the hybrid step and ~1e-9 in the plain one; with no close pairs the two steps coincide."""
+    d, thr, _ = disk2048_groups
+    x, v, m = d["x"], d["v"], d["m"]
+    E0 = oracle.energy(x, v, m, params, thr)
+    xh, vh, st, stats = oracle.step_hybrid(x, v, m, params, 20, thr=thr)
+    xp, vp, _ = oracle.step(x, v, m, params, 20, thr=thr)
+    Eh, Ep = oracle.energy(xh, vh, m, params, thr), oracle.energy(xp, vp, m, params, thr)
+    dEh = abs(Eh["E"] - E0["E"]) / abs(E0["E"])
+    dEp = abs(Ep["E"] - E0["E"]) / abs(E0["E"])
+    assert st == 0 and stats[0] > 0
+    assert dEh < 3e-10 and dEp > 10 * dEh
+    assert abs(Ep["Eprime"] - E0["Eprime"]) / abs(E0["Eprime"]) < 1e-10
+    # far-apart bodies only: identical to the plain step
+    far = diskgen.workload("disk2048", n=40)
+    fthr = oracle.thresholds(far["x"], far["v"], far["m"], params)
+    assert len(oracle.encounters(far["x"], fthr)) == 0
+    a = oracle.step_hybrid(far["x"], far["v"], far["m"], params, 3, thr=fthr)
+    b = oracle.step(far["x"], far["v"], far["m"], params, 3, thr=fthr)
+    if a[3][0] == 0:
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
