@@ -138,6 +138,33 @@ int nbody_encounter_groups(nbody_ctx *ctx, int64_t n, const int32_t *pairs, int6
                            const int64_t *count, int32_t *labels, int64_t *out, void *stream);
 
 /*
+ * Close-encounter drift: H_A in full (eq. Ha, both lines) over time h. The bodies of every
+ * close-encounter group (labels as written by nbody_encounter_groups: the smallest index of each
+ * body's group) move under the equations of motion of H_A restricted to their group,
+ *   dx_i/dt = v_i,
+ *   dv_i/dt = -G m0 x_i/|x_i|^3 + G sum_{j in group, j != i} m_j ((1 - K)/r^3 + K'(r)/r^2) d_ij,
+ * integrated with the Gragg-Bulirsch-Stoer method (binary64, tolerance 1e-14 relative to the
+ * group's largest position and velocity), one wave per group; a body alone in its group follows
+ * its Kepler orbit (as nbody_drift). thr as from nbody_rcrit (rc_i sets the changeover).
+ * stats (device int64 [6]) receives: [0] groups integrated, [1] largest group, [2] bodies in
+ * groups, [3] groups of more than 64 bodies (moved on Kepler orbits only: the result is then not
+ * the H_A flow), [4] groups whose integration did not finish, [5] (nbody_step_hybrid only)
+ * encounter lists that exceeded the internal capacity of max(16 n, 65536) pairs.
+ */
+int nbody_drift_groups(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr,
+                       const int32_t *labels, double h, int64_t *stats, void *stream);
+
+/*
+ * Hybrid step: as nbody_step (B(dt/2) C(dt/2) A(dt) C(dt/2) B(dt/2), thresholds fixed for the
+ * call, merged half kicks), but the drift A integrates H_A in full: the close pairs found by each
+ * kick's pair loop form the close-encounter groups of the drift that follows, integrated as in
+ * nbody_drift_groups. The step then conserves the full energy E instead of the K-weighted E'.
+ * stats as for nbody_drift_groups, summed over the steps (stats[1] the maximum). Binary64 only.
+ */
+int nbody_step_hybrid(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr,
+                      int32_t nsteps, int64_t *stats, void *stream);
+
+/*
  * Input check before integrating a state. The method has no softening, so a body at the central
  * mass (r_i = 0 in eq. Ha) or two bodies at one position (r_ij = 0 in eq. Hb) are invalid input.
  * result (device int64 [2]) receives {i, reason} for the smallest body index i with a problem

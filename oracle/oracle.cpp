@@ -503,6 +503,7 @@ static int ce_drift_group(int k, T *y, const double *m, const double *rc, const 
     }
     halvings = 0;
     for (int i = 0; i < D; i++) y[i] = R[(size_t)accepted * D + i];
+    if (t + H == t) break;            // the remaining interval is below the resolution of t
     t = t + H;
     if (accepted <= 4) H = H * T(2);
   }
@@ -700,6 +701,18 @@ int or_ce_drift_group(const int64_t *idx, int k, double *x, double *v, const dou
       x[3 * idx[a] + l] = (double)y[3 * a + l];
       v[3 * idx[a] + l] = (double)y[3 * k + 3 * a + l];
     }
+  return st;
+}
+
+// Drift of all bodies over h with the close-encounter groups given by labels (long double;
+// stats[3] = {groups integrated, largest group, bodies in groups}, may be NULL).
+int or_drift_groups(int64_t n, double *x, double *v, const double *m, const double *rc, const int32_t *label,
+                    const double *prm, double h, double tol, int64_t *stats) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n), ml(m, m + n);
+  if (stats) stats[0] = stats[1] = stats[2] = 0;
+  const int st = drift_groups<long double>(n, xl.data(), vl.data(), ml.data(), rc, label, p, h, tol, stats);
+  for (int64_t i = 0; i < 3 * n; i++) { x[i] = (double)xl[i]; v[i] = (double)vl[i]; }
   return st;
 }
 

@@ -61,6 +61,8 @@ EXPORTS = {
     "nbody_step": [_I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P],
     "nbody_validate": [_I64, _P, _P, _P, _P],
     "nbody_encounter_groups": [_I64, _P, _I64, _P, _P, _P, _P],
+    "nbody_drift_groups": [_I64, _P, _P, _P, _P, _D, _P, _P],
+    "nbody_step_hybrid": [_I64, _P, _P, _P, _I32, _P, _P],
     "nbody_energy": [_I64, _P, _P, _P, _P, _P],
     "nbody_bench_pairs": [_I64, _P, _P, _I32, _P, _P],
     "nbody_kick_vjp": [_I64, _P, _P, _D, _P, _P, _P],
@@ -236,6 +238,27 @@ class Context:
                                                  _ptr(labels), _ptr(out), _stream()), "nbody_encounter_groups")
         o = out.cpu().tolist()
         return labels, int(o[0]), int(o[1])
+
+    _CE_STATS = ("groups", "largest", "bodies", "too_large", "unfinished", "list_overflows")
+
+    def drift_groups(self, xm, v, thr, labels, h):
+        """Close-encounter drift (H_A in full) over h with the given group labels; returns the
+        statistics as a dict."""
+        _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
+        stats = torch.zeros(6, dtype=torch.int64, device=xm.device)
+        self._check(lib().nbody_drift_groups(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr),
+                                             _ptr(labels.contiguous()), float(h), _ptr(stats), _stream()),
+                    "nbody_drift_groups")
+        return dict(zip(self._CE_STATS, stats.cpu().tolist()))
+
+    def step_hybrid(self, xm, v, nsteps, thr=None):
+        """nsteps hybrid steps in place (close-encounter groups integrated in the drift); returns
+        the statistics as a dict."""
+        _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
+        stats = torch.zeros(6, dtype=torch.int64, device=xm.device)
+        self._check(lib().nbody_step_hybrid(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr), int(nsteps),
+                                            _ptr(stats), _stream()), "nbody_step_hybrid")
+        return dict(zip(self._CE_STATS, stats.cpu().tolist()))
 
     def validate(self, xm, v):
         """(index, reason) of the first invalid body, or (-1, 0); reasons: 1 non-finite value,

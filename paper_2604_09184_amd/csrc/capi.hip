@@ -26,7 +26,8 @@ struct Buf {
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
-             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GMARK, B_NUM };
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GMARK, B_GIN, B_GSIZE,
+             B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_HGOUT, B_NUM };
 
 }  // namespace
 
@@ -283,6 +284,40 @@ int run_batched(nbody_ctx *c, int32_t nsys, const int32_t *tiles, double4 *xm, d
   return NBODY_OK;
 }
 
+// ------------------------------------------------------------------ close-encounter drift
+constexpr double kCeTol = 1e-14;   // Bulirsch-Stoer tolerance, relative to the group's scales
+
+struct GroupBufs {
+  int *mark, *in, *gsize, *gstart, *gfill, *gmem, *groot, *counter;
+};
+
+int group_bufs(nbody_ctx *c, int n, GroupBufs &g) {
+  const size_t b = (size_t)n * sizeof(int);
+  g.mark = (int *)ensure(c, B_GMARK, b);
+  g.in = (int *)ensure(c, B_GIN, b);
+  g.gsize = (int *)ensure(c, B_GSIZE, b);
+  g.gstart = (int *)ensure(c, B_GSTART, b);
+  g.gfill = (int *)ensure(c, B_GFILL, b);
+  g.gmem = (int *)ensure(c, B_GMEM, b);
+  g.groot = (int *)ensure(c, B_GROOT, b);
+  g.counter = (int *)ensure(c, B_GCNT, sizeof(int));
+  if (!g.mark || !g.in || !g.gsize || !g.gstart || !g.gfill || !g.gmem || !g.groot || !g.counter)
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
+  return NBODY_OK;
+}
+
+// Member lists of the groups given by labels; then the close-encounter integration of every group
+// over h (the other bodies are not touched here).
+int ce_drift(nbody_ctx *c, int n, double4 *xm, double4 *v, const double4 *thr, const int *labels,
+             const GroupBufs &g, double h, unsigned long long *stats, hipStream_t st) {
+  HIPCHK(c, launch_group_lists(labels, n, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
+                               g.counter, st), "group lists");
+  const nbody_params &p = c->p;
+  HIPCHK(c, launch_ce_drift(xm, v, thr, g.gmem, g.gstart, g.gsize, g.groot, g.counter, n / 2 + 1, p.G, p.m0,
+                            p.f_in, h, kCeTol, stats, st), "close-encounter drift");
+  return NBODY_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -482,6 +517,100 @@ int nbody_encounter_groups(nbody_ctx *c, int64_t n, const int32_t *pairs, int64_
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
   HIPCHK(c, launch_groups(pairs, cap, count, (int)n, labels, mark, out, blocks, (hipStream_t)stream),
          "groups");
+  return NBODY_OK;
+}
+
+int nbody_drift_groups(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr, const int32_t *labels,
+                       double h, int64_t *stats, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, thr, "thr", true));
+  TRY(check_dev(c, labels, "labels", true));
+  TRY(check_dev(c, stats, "stats", true));
+  hipStream_t st = (hipStream_t)stream;
+  GroupBufs g;
+  TRY(group_bufs(c, (int)n, g));
+  HIPCHK(c, hipMemsetAsync(stats, 0, 6 * sizeof(int64_t), st), "memset");
+  TRY(ce_drift(c, (int)n, (double4 *)xm, (double4 *)v, (const double4 *)thr, labels, g, h,
+               (unsigned long long *)stats, st));
+  // bodies in no group: Kepler orbits (g.in marks the group members)
+  HIPCHK(c, launch_drift((double4 *)xm, (double4 *)v, (int)n, h, c->p.G * c->p.m0, nullptr, st, g.in), "drift");
+  return NBODY_OK;
+}
+
+int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr, int32_t nsteps,
+                      int64_t *stats, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  TRY(check_dev(c, thr, "thr", false));
+  TRY(check_dev(c, stats, "stats", true));
+  if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
+  if (c->p.precision != NBODY_PREC_F64) return fail(c, NBODY_E_INVAL, "the hybrid step runs in binary64");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(c, hipMemsetAsync(stats, 0, 6 * sizeof(int64_t), st), "memset");
+  if (nsteps == 0) return NBODY_OK;
+  const nbody_params &p = c->p;
+  const int N = (int)n;
+  if (!thr) {
+    double *t = (double *)ensure(c, B_THR, (size_t)n * sizeof(double4));
+    if (!t) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (thresholds)");
+    TRY(nbody_rcrit(c, n, xm, v, t, stream));
+    thr = t;
+  }
+  const int nbf = fin_blocks(n);
+  double4 *momA = (double4 *)ensure(c, B_MOM_A, (size_t)nbf * sizeof(double4));
+  double4 *momB = (double4 *)ensure(c, B_MOM_B, (size_t)nbf * sizeof(double4));
+  // the encounter list of every force evaluation, its groups and their member lists
+  const int64_t cap = std::max<int64_t>(16 * n, 65536);
+  int32_t *lpairs = (int32_t *)ensure(c, B_HPAIRS, (size_t)cap * 2 * sizeof(int32_t));
+  int64_t *lcount = (int64_t *)ensure(c, B_HCOUNT, sizeof(int64_t));
+  int32_t *labels = (int32_t *)ensure(c, B_HLAB, (size_t)n * sizeof(int32_t));
+  int64_t *gout = (int64_t *)ensure(c, B_HGOUT, 2 * sizeof(int64_t));
+  if (!momA || !momB || !lpairs || !lcount || !labels || !gout)
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (hybrid step)");
+  GroupBufs g;
+  TRY(group_bufs(c, N, g));
+  KickArgs a;
+  TRY(make_kick_args(c, N, xm, thr, true, false, true, a));
+  double4 *X = (double4 *)xm;
+  double4 *Vv = (double4 *)v;
+  const double4 *T = (const double4 *)thr;
+  unsigned long long *S = (unsigned long long *)stats;
+  const double h = 0.5 * p.dt;
+  const double mu = p.G * p.m0;
+  TRY(locality(c, N, X, st, &a.perm));
+  TRY(mass_check(c, N, X, st, &a.uni));
+  const int ublocks = (int)std::min<int64_t>(4096, (cap + kBlock - 1) / kBlock);
+  // groups of the list at the current kick positions
+  auto groups_now = [&]() -> int {
+    TRY(emit_list(c, a, lpairs, cap, lcount, st));
+    HIPCHK(c, launch_list_overflow(lcount, cap, S, st), "list check");
+    HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.mark, gout, ublocks, st), "groups");
+    return NBODY_OK;
+  };
+  HIPCHK(c, launch_pairs(a, true, true, false, false, st), "hybrid pairs");
+  HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, 1, X, Vv, nullptr, nullptr, momA, st),
+         "hybrid finalize");
+  TRY(groups_now());
+  for (int s = 1; s <= nsteps; ++s) {
+    HIPCHK(c, launch_group_lists(labels, N, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
+                                 g.counter, st), "group lists");
+    // first jump for all; Kepler drift for the bodies in no group
+    HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
+                                g.in), "jump+drift");
+    HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
+                              p.f_in, p.dt, kCeTol, S, st), "close-encounter drift");
+    HIPCHK(c, launch_momentum(X, Vv, N, momB, st), "momentum");
+    HIPCHK(c, launch_jump(X, momB, nbf, N, h, p.m0, st), "jump");
+    if (a.perm && s % c->locality_every == 0) TRY(locality(c, N, X, st, &a.perm));
+    const bool last = s == nsteps;
+    HIPCHK(c, launch_pairs(a, true, !last, false, false, st), "hybrid pairs");
+    HIPCHK(c, launch_finalize(a.part, nullptr, a.nchunk, N, p.G, h, last ? 1 : 2, X, Vv, nullptr, nullptr,
+                              momA, st), "hybrid finalize");
+    if (!last) TRY(groups_now());
+  }
   return NBODY_OK;
 }
 

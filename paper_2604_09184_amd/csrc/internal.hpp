@@ -51,9 +51,19 @@ hipError_t launch_jump(double4 *xm, const double4 *mom, int nb, int n, double h,
 hipError_t launch_jump_drift(double4 *xm, double4 *v, const double4 *mom_in, int nb, int n,
                              double hjump, double dt, double m0, double mu, uint32_t *status,
                              double4 *mom_out, hipStream_t st, double4 *x_rec = nullptr,
-                             double4 *v_rec = nullptr);
+                             double4 *v_rec = nullptr, const int *skip = nullptr);
 hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, uint32_t *status,
-                        hipStream_t st);
+                        hipStream_t st, const int *skip = nullptr);
+
+// ce.hip
+hipError_t launch_group_lists(const int *label, int n, int *mark, int *in, int *gsize, int *gstart,
+                              int *gfill, int *gmem, int *groot, int *counter, hipStream_t st);
+hipError_t launch_list_overflow(const int64_t *count, int64_t cap, unsigned long long *stats,
+                                hipStream_t st);
+hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
+                           const int *gstart, const int *gsize, const int *groot,
+                           const int *ngroups, int max_groups, double G, double m0, double f_in,
+                           double h, double tol, unsigned long long *stats, hipStream_t st);
 
 // adjoint.hip
 hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double2 *uni,

@@ -42,7 +42,8 @@ __global__ __launch_bounds__(64) void k_jump(double4 *__restrict__ xm,
 }
 
 // x_rec / v_rec (may be null) receive the positions after the jump (before the drift) and the
-// velocities after the drift.
+// velocities after the drift. skip (may be null): bodies with skip[i] != 0 get the jump but not
+// the Kepler drift (their drift is the close-encounter integration).
 __global__ __launch_bounds__(64) void k_jump_drift(double4 *__restrict__ xm,
                                                    double4 *__restrict__ v,
                                                    const double4 *__restrict__ mom_in, int nb,
@@ -50,7 +51,8 @@ __global__ __launch_bounds__(64) void k_jump_drift(double4 *__restrict__ xm,
                                                    double mu, uint32_t *__restrict__ status,
                                                    double4 *__restrict__ mom_out,
                                                    double4 *__restrict__ x_rec,
-                                                   double4 *__restrict__ v_rec) {
+                                                   double4 *__restrict__ v_rec,
+                                                   const int *__restrict__ skip) {
   double P[3];
   partials_total_wave(mom_in, nb, P);
   const int i = blockIdx.x * 64 + threadIdx.x;
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(64) void k_jump_drift(double4 *__restrict__ xm,
     double4 q = v[i];
     p.x = p.x + sx; p.y = p.y + sy; p.z = p.z + sz;
     if (x_rec) x_rec[i] = p;
-    const int st = kepler_advance(p.x, p.y, p.z, q.x, q.y, q.z, mu, dt);
+    const int st = (skip && skip[i]) ? 0 : kepler_advance(p.x, p.y, p.z, q.x, q.y, q.z, mu, dt);
     xm[i] = p;
     v[i] = q;
     if (v_rec) v_rec[i] = q;
@@ -72,11 +74,13 @@ __global__ __launch_bounds__(64) void k_jump_drift(double4 *__restrict__ xm,
   if (threadIdx.x == 0) mom_out[blockIdx.x] = make_double4(Q[0], Q[1], Q[2], 0.0);
 }
 
+// skip (may be null): bodies with skip[i] != 0 are left alone.
 __global__ __launch_bounds__(64) void k_drift(double4 *__restrict__ xm, double4 *__restrict__ v,
                                               int n, double dt, double mu,
-                                              uint32_t *__restrict__ status) {
+                                              uint32_t *__restrict__ status,
+                                              const int *__restrict__ skip) {
   const int i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || (skip && skip[i])) return;
   double4 p = xm[i];
   double4 q = v[i];
   const int st = kepler_advance(p.x, p.y, p.z, q.x, q.y, q.z, mu, dt);
@@ -98,15 +102,16 @@ hipError_t launch_jump(double4 *xm, const double4 *mom, int nb, int n, double h,
 
 hipError_t launch_jump_drift(double4 *xm, double4 *v, const double4 *mom_in, int nb, int n,
                              double hjump, double dt, double m0, double mu, uint32_t *status,
-                             double4 *mom_out, hipStream_t st, double4 *x_rec, double4 *v_rec) {
+                             double4 *mom_out, hipStream_t st, double4 *x_rec, double4 *v_rec,
+                             const int *skip) {
   hipLaunchKernelGGL(k_jump_drift, dim3(fin_blocks(n)), dim3(64), 0, st, xm, v, mom_in, nb, n,
-                     hjump, dt, m0, mu, status, mom_out, x_rec, v_rec);
+                     hjump, dt, m0, mu, status, mom_out, x_rec, v_rec, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, uint32_t *status,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_drift, dim3(fin_blocks(n)), dim3(64), 0, st, xm, v, n, dt, mu, status);
+                        hipStream_t st, const int *skip) {
+  hipLaunchKernelGGL(k_drift, dim3(fin_blocks(n)), dim3(64), 0, st, xm, v, n, dt, mu, status, skip);
   return hipGetLastError();
 }
 

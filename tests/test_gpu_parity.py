@@ -520,3 +520,64 @@ def test_full_size_ring_f64_and_split(nb):
     say(f"  {count} pairs")
     assert count == len(ref)
     np.testing.assert_array_equal(pairs.cpu().numpy(), ref)
+
+
+# ------------------------------------------------------------------ close-encounter drift, hybrid step
+def test_drift_groups_matches_oracle(ctx):
+    """H_A in full over one step: the groups of the 2048 disk's list (the GPU's own groups, equal to
+    the oracle's) integrated by the GPU's Bulirsch-Stoer kernel (binary64, tolerance 1e-14) against
+    the oracle's (long double, tolerance 1e-18, within ~2e-15 of the exact flow); the bodies in no
+    group on Kepler orbits. Measured on the CPU: the same method at tolerance 1e-14 stays within
+    ~2e-12 of the exact flow in velocity, so the bar is 1e-11."""
+    say("drift_groups disk2048")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    pairs, count = ctx.encounters(X, thr, cap=1 << 20)
+    lab, g, _ = ctx.encounter_groups(X.shape[0], pairs.contiguous(), count)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    olab, og, _ = oracle.groups(X.shape[0], oracle.encounters(d["x"], othr))
+    np.testing.assert_array_equal(lab.cpu().numpy(), olab)
+    stats = ctx.drift_groups(X, V, thr, lab, p["dt"])
+    ox, ov, st, ostats = oracle.drift_groups(d["x"], d["v"], d["m"], othr[0], olab, p, p["dt"])
+    x = X.cpu().numpy()[:, :3]; v = V.cpu().numpy()[:, :3]
+    ex = (np.abs(x - ox).max(1) / np.linalg.norm(ox, axis=1)).max()
+    ev = (np.abs(v - ov).max(1) / np.linalg.norm(ov, axis=1)).max()
+    say(f"  {stats}; state rel err x {ex:.2e} v {ev:.2e}")
+    assert st == 0 and stats["unfinished"] == 0 and stats["too_large"] == 0
+    assert (stats["groups"], stats["largest"], stats["bodies"]) == ostats
+    assert ex < 1e-11 and ev < 1e-11
+
+
+def test_step_hybrid_matches_oracle_and_conserves_energy(ctx):
+    """10 hybrid steps of the 2048 disk against the oracle's hybrid step (state, group statistics),
+    and the full energy E conserved as the oracle conserves it."""
+    say("step_hybrid disk2048 x10")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = to_dev(d)
+    thr = ctx.rcrit(X, V)
+    e0 = ctx.energy(X, V, thr)
+    stats = ctx.step_hybrid(X, V, 10, thr=thr)
+    e1 = ctx.energy(X, V, thr)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov, st, ostats = oracle.step_hybrid(d["x"], d["v"], d["m"], p, 10, thr=othr)
+    x = X.cpu().numpy()[:, :3]; v = V.cpu().numpy()[:, :3]
+    ex = (np.abs(x - ox).max(1) / np.linalg.norm(ox, axis=1)).max()
+    ev = (np.abs(v - ov).max(1) / np.linalg.norm(ov, axis=1)).max()
+    dE = abs(e1["E"] - e0["E"]) / abs(e0["E"])
+    say(f"  {stats}; state rel err x {ex:.2e} v {ev:.2e}; dE/E {dE:.2e}")
+    assert st == 0 and stats["unfinished"] == 0 and stats["too_large"] == 0 and stats["list_overflows"] == 0
+    assert (stats["groups"], stats["largest"], stats["bodies"]) == ostats
+    assert ex < 1e-10 and ev < 1e-10
+    assert dE < 3e-10
+
+
+def test_step_hybrid_reports_oversized_groups(ctx):
+    """A clump of 300 bodies forms one group above the 64 a wave integrates: reported."""
+    say("step_hybrid clump")
+    d = cluster_disk(4096, 300)
+    X, V = to_dev(d)
+    stats = ctx.step_hybrid(X, V, 1)
+    assert stats["too_large"] >= 1 and stats["largest"] >= 0
