@@ -167,6 +167,35 @@ def variant_adjoint(nb, p):
             "backward_pair_evals_per_s": evals * n * (n - 1) / res["backward_s"]}
 
 
+def variant_hybrid(nb, p):
+    """Hybrid step (close-encounter groups integrated in full in the drift) against the plain step on
+    the 2048-body disk, 100 steps each: time and the drift of the full energy E and of E'."""
+    import torch
+
+    import diskgen
+    d = diskgen.workload("disk2048")
+    n = len(d["m"])
+    xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+    ctx = nb.Context(nb.Params(**p))
+    out = {"workload": "disk2048", "n": n, "steps": 100}
+    for name in ("plain", "hybrid"):
+        X = torch.tensor(xm, device="cuda:0")
+        V = torch.tensor(v4, device="cuda:0")
+        thr = ctx.rcrit(X, V)
+        e0 = ctx.energy(X, V, thr)
+        run = (lambda: ctx.step(X, V, 100, thr=thr)) if name == "plain" else (lambda: ctx.step_hybrid(X, V, 100, thr=thr))
+        Xw, Vw = X.clone(), V.clone()
+        (ctx.step(Xw, Vw, 2, thr=thr) if name == "plain" else ctx.step_hybrid(Xw, Vw, 2, thr=thr))   # warm-up
+        sec, stats = timed(run)
+        e1 = ctx.energy(X, V, thr)
+        out[name] = {"seconds": round(sec, 4), "ms_per_step": round(sec * 10, 4),
+                     "E_rel_drift": float(abs(e1["E"] - e0["E"]) / abs(e0["E"])),
+                     "Eprime_rel_drift": float(abs(e1["Eprime"] - e0["Eprime"]) / abs(e0["Eprime"]))}
+        if name == "hybrid":
+            out[name]["groups"] = stats
+    return out
+
+
 def cpu_baseline(budget_s=25.0):
     """The oracle (plain C++, OpenMP) on the first steps of the same N = 32768 disk."""
     import numpy as np
@@ -200,7 +229,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)   # the clock ramps up over the first ~0.2 s of load
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--only", choices=["split", "batched", "adjoint"],
+    ap.add_argument("--only", choices=["split", "batched", "adjoint", "hybrid"],
                     help="run only this variant and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -219,7 +248,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.only:
         p = diskgen.PARAMS
-        fn = {"split": variant_split, "batched": variant_batched, "adjoint": variant_adjoint}[args.only]
+        fn = {"split": variant_split, "batched": variant_batched, "adjoint": variant_adjoint,
+              "hybrid": variant_hybrid}[args.only]
         print(json.dumps({args.only: fn(nb, p)}), flush=True)
         return
     if args.calibrate_copy:
@@ -286,6 +316,8 @@ def main():
         variants["batched"] = variant_batched(nb, p)
         print("[bench] variant: adjoint (adjoint8192)", file=sys.stderr, flush=True)
         variants["adjoint"] = variant_adjoint(nb, p)
+        print("[bench] variant: hybrid step (disk2048)", file=sys.stderr, flush=True)
+        variants["hybrid"] = variant_hybrid(nb, p)
 
     out = {
         "metric": METRIC,

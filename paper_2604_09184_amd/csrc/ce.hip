@@ -92,165 +92,240 @@ __global__ __launch_bounds__(kBlock) void k_gfill(const int *__restrict__ label,
 }
 
 // ------------------------------------------------------------------ integrator
+// Work layout. A group of k <= 64 bodies is integrated by one workgroup of kCeWaves = 4 waves.
+// The eight modified-midpoint sweeps of a macro step (n = 2, 4, ..., 16 substeps) are independent
+// of one another, so wave w runs the sweeps n = 2w + 2 and n = 16 - 2w: 20 evaluations of the
+// right-hand side per wave, against 80 for all eight in a row. Their end values meet in LDS, and
+// every wave then forms the same extrapolation tableau, takes the same decision and updates the
+// same state, so the waves stay in step without further exchange.
+//
+// Within a wave, body slot s (0 <= s < k) sits on the lanes s + kp r, r = 0 .. 64/kp - 1, with kp
+// the power of two at or above k: replica r sums the pair terms of every (64/kp)-th member, and the
+// replicas' partial sums meet in a butterfly over lane distances kp, 2 kp, ... (commutative
+// additions, so every replica ends with the same bits). Small groups thus spread their pair sums
+// over the whole wave.
+constexpr int kCeWaves = 4;
+constexpr int kMaxMacroSteps = 20000;
+
 __device__ __forceinline__ double wave_max_d(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
   return x;
 }
 
-// Pair coefficient of the close-encounter force: G m_j ((1 - K)/r^3 + K'(r)/r^2) for r < rc_ij,
-// zero beyond.
-__device__ __forceinline__ double ce_coef(double r2, double rcij, double f_in, double Gmj) {
-  const double r = sqrt(r2);
-  const double span = (1.0 - f_in) * rcij;
-  const double y = (r - f_in * rcij) / span;
-  if (y >= 1.0) return 0.0;
-  double K = 0.0, dKdr = 0.0;
-  if (y > 0.0) {
-    const double D = 2.0 * y * y - 2.0 * y + 1.0;
-    K = y * y / D;
-    dKdr = 2.0 * y * (1.0 - y) / (D * D) / span;
-  }
-  return Gmj * ((1.0 - K) / (r2 * r) + dKdr / r2);
-}
+// Per-member constants in ascending body order: G m, rc, 1/((1 - f_in) rc).
+struct CeMember {
+  double Gm, rc, ispan, pad;
+};
 
-// f = (v, a) for this lane's body at the group state z; owner[q] = lane holding the q-th member
-// in ascending body index.
-__device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, const int *owner, int lane,
-                                       double m, double rc, double Gm0, double G, double f_in,
-                                       double (&f)[6]) {
+// f = (v, a) of this lane's body at the state z. The pair coefficient is
+// G m_j ((1 - K)/r^3 + K'(r)/r^2) for r < rc_ij and zero beyond; with y the changeover variable and
+// D = 2y^2 - 2y + 1, K = y^2/D, 1 - K = (1 - y)^2/D and K'(r) = 2y(1 - y)/(D^2 (1 - f_in) rc_ij).
+__device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, int iters, int P, int rep,
+                                       int slot, const int *owner, const CeMember *mem,
+                                       double rc, double ispan, double Gm0, double f_in,
+                                       int kp, double (&f)[6]) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    const int q = rep + it * P;
+    const bool valid = q < k;
+    const int qq = valid ? q : 0;
+    const int src = owner[qq];
+    const double xj = __shfl(z[0], src, 64), yj = __shfl(z[1], src, 64),
+                 zj = __shfl(z[2], src, 64);
+    const CeMember mj = mem[qq];
+    const double dx = xj - z[0], dy = yj - z[1], dz = zj - z[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double rcij = rc > mj.rc ? rc : mj.rc;
+    if (valid && src != slot && r2 < rcij * rcij) {
+      const double r = sqrt(r2);
+      const double ir = 1.0 / r;
+      const double isp = rc > mj.rc ? ispan : mj.ispan;
+      const double y = (r - f_in * rcij) * isp;
+      double c = ir * ir * ir;
+      if (y > 0.0) {
+        const double iD = 1.0 / (2.0 * y * y - 2.0 * y + 1.0);
+        const double omy = 1.0 - y;
+        c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
+      }
+      c *= mj.Gm;
+      a0 += c * dx;
+      a1 += c * dy;
+      a2 += c * dz;
+    }
+  }
+  for (int o = kp; o < 64; o <<= 1) {
+    a0 += __shfl_xor(a0, o, 64);
+    a1 += __shfl_xor(a1, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
   const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
   const double s = -Gm0 / (r2 * sqrt(r2));
-  double a0 = s * z[0], a1 = s * z[1], a2 = s * z[2];
-  for (int q = 0; q < k; ++q) {
-    const int src = owner[q];
-    const double xj = __shfl(z[0], src, 64), yj = __shfl(z[1], src, 64), zj = __shfl(z[2], src, 64);
-    const double mj = __shfl(m, src, 64), rcj = __shfl(rc, src, 64);
-    if (src == lane) continue;
-    const double dx = xj - z[0], dy = yj - z[1], dz = zj - z[2];
-    const double c = ce_coef(dx * dx + dy * dy + dz * dz, rc > rcj ? rc : rcj, f_in, G * mj);
-    a0 += c * dx;
-    a1 += c * dy;
-    a2 += c * dz;
-  }
   f[0] = z[3]; f[1] = z[4]; f[2] = z[5];
-  f[3] = a0; f[4] = a1; f[5] = a2;
+  f[3] = s * z[0] + a0;
+  f[4] = s * z[1] + a1;
+  f[5] = s * z[2] + a2;
 }
 
-constexpr int kMaxMacroSteps = 20000;
+// Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
+__device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, int k, int iters,
+                                         int P, int rep, int slot, const int *owner,
+                                         const CeMember *mem, double rc, double ispan, double Gm0,
+                                         double f_in, int kp, double (&est)[6]) {
+  const double hs = H / ns;
+  double zm[6], zc[6], f[6];
+  ce_rhs(y, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, f);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    zm[i] = y[i];
+    zc[i] = y[i] + hs * f[i];
+  }
+  for (int s = 1; s < ns; ++s) {
+    ce_rhs(zc, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, f);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const double zn = zm[i] + 2.0 * hs * f[i];
+      zm[i] = zc[i];
+      zc[i] = zn;
+    }
+  }
+  ce_rhs(zc, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, f);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zc[i] + zm[i] + hs * f[i]);
+}
 
-// One wave per group. stats (device uint64 [6]): [0] groups integrated, [1] largest group,
-// [2] bodies in groups, [3] groups above 64 bodies (drifted on Kepler orbits only), [4] groups
-// whose integration did not finish (step halved 60 times in a row, or too many macro steps).
-__global__ __launch_bounds__(64) void k_ce_drift(double4 *__restrict__ xm, double4 *__restrict__ v,
-                                                 const double4 *__restrict__ thr,
-                                                 const int *__restrict__ gmem,
-                                                 const int *__restrict__ gstart,
-                                                 const int *__restrict__ gsize,
-                                                 const int *__restrict__ groot,
-                                                 const int *__restrict__ ngroups, double G,
-                                                 double m0, double f_in, double h, double tol,
-                                                 unsigned long long *__restrict__ stats) {
+// Aitken-Neville over the eight sweeps (substep counts 2c + 2) of one component: T[c][0] = e[c],
+// T[c][j] = T[c][j-1] + (T[c][j-1] - T[c-1][j-1]) / ((n_c/n_{c-j})^2 - 1). Returns T[want][want]
+// and, in err[c], max(err[c], |T[c][c] - T[c][c-1]| iscale) for c >= 2.
+__device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale, int want,
+                                             double (&err)[8]) {
+  double prev[8], cur[8], out = e[0];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    cur[0] = e[c];
+#pragma unroll
+    for (int j = 1; j <= c; ++j) {
+      const double ratio = (double)(c + 1) / (double)(c + 1 - j);
+      cur[j] = cur[j - 1] + (cur[j - 1] - prev[j - 1]) / (ratio * ratio - 1.0);
+    }
+    if (c >= 2) err[c] = fmax(err[c], fabs(cur[c] - cur[c - 1]) * iscale);
+    if (c == want) out = cur[c];
+#pragma unroll
+    for (int j = 0; j <= c; ++j) prev[j] = cur[j];
+  }
+  return out;
+}
+
+// stats (device uint64 [6]): [0] groups integrated, [1] largest group, [2] bodies in groups, [3]
+// groups above 64 bodies (drifted on Kepler orbits only), [4] groups whose integration did not
+// finish (step halved 60 times in a row, or too many macro steps).
+//
+// Step control: a macro step is accepted at the first column c >= 2 whose last two extrapolants
+// agree to tol (|T[c][c] - T[c][c-1]|, relative to the group's largest |x| and |v|); after
+// acceptance at c <= 3 the next H is 4 H, at c = 4 it is 2 H, otherwise H; a rejected step is
+// halved.
+__global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
+    double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
+    const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
+    const int *__restrict__ groot, const int *__restrict__ ngroups, double G, double m0,
+    double f_in, double h, double tol, unsigned long long *__restrict__ stats) {
+  __shared__ double est_s[2][8][6][64];
   __shared__ int owner[64];
+  __shared__ CeMember mem[64];
   const int w = blockIdx.x;
   if (w >= *ngroups) return;
-  const int lane = threadIdx.x;
   const int r = groot[w];
   const int k = gsize[r];
   const int base = gstart[r];
   const double Gm0 = G * m0;
   if (k > 64) {
     // too large for one wave: Kepler orbits only, and reported
-    for (int q = lane; q < k; q += 64) {
+    for (int q = threadIdx.x; q < k; q += 64 * kCeWaves) {
       const int b = gmem[base + q];
       double4 p = xm[b], u = v[b];
       kepler_advance(p.x, p.y, p.z, u.x, u.y, u.z, Gm0, h);
       xm[b] = p;
       v[b] = u;
     }
-    if (lane == 0) atomicAdd(stats + 3, 1ull);
+    if (threadIdx.x == 0) atomicAdd(stats + 3, 1ull);
     return;
   }
-  const bool act = lane < k;
-  const int b = gmem[base + (act ? lane : 0)];
-  int rank = 0;
-  for (int q = 0; q < k; ++q) rank += __shfl(b, q, 64) < b;
-  if (act) owner[rank] = lane;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int kp = 1;
+  while (kp < k) kp <<= 1;
+  const int P = 64 / kp;
+  const int slot = lane & (kp - 1), rep = lane / kp;
+  const int iters = (k + P - 1) / P;
+  const bool act = slot < k;
+  const int b = gmem[base + (act ? slot : 0)];
   const double4 p0 = xm[b], u0 = v[b];
-  const double m = p0.w, rc = thr[b].x;
+  const double rc = thr[b].x;
+  const double ispan = 1.0 / ((1.0 - f_in) * rc);
+  if (wv == 0 && rep == 0 && act) {
+    int rank = 0;
+    for (int q = 0; q < k; ++q) rank += gmem[base + q] < b;
+    owner[rank] = slot;
+    mem[rank] = CeMember{G * p0.w, rc, ispan, 0.0};
+  }
+  __syncthreads();
   double y[6] = {p0.x, p0.y, p0.z, u0.x, u0.y, u0.z};
-  const int seq[8] = {2, 4, 6, 8, 10, 12, 14, 16};
   double t = 0.0, H = h;
-  int halvings = 0, macro = 0, status = 0;
+  int halvings = 0, macro = 0, status = 0, buf = 0;
   while (fabs(h - t) > 0.0) {
     if (++macro > kMaxMacroSteps) { status = 1; break; }
     if (fabs(H) > fabs(h - t)) H = h - t;
     const double sx = wave_max_d(act ? fmax(fabs(y[0]), fmax(fabs(y[1]), fabs(y[2]))) : 0.0);
     const double sv = wave_max_d(act ? fmax(fabs(y[3]), fmax(fabs(y[4]), fabs(y[5]))) : 0.0);
-    double R[8][6];
+    const double isx = 1.0 / sx, isv = 1.0 / sv;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int c = cc == 0 ? wv : 7 - wv;
+      double est[6];
+      ce_sweep(y, H, 2 * c + 2, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, est);
+      if (rep == 0)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) est_s[buf][c][i][slot] = est[i];
+    }
+    __syncthreads();
+    // tableau of every component; the first pass finds the accepted column
+    double err[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double e[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) e[c] = est_s[buf][c][i][slot];
+      (void)ce_tableau(e, i < 3 ? isx : isv, -1, err);
+    }
     int accepted = -1;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      if (accepted < 0) {
-        const double hs = H / seq[c];
-        double zm[6], zc[6], f[6], est[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) zm[i] = y[i];
-        ce_rhs(zm, k, owner, lane, m, rc, Gm0, G, f_in, f);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) zc[i] = zm[i] + hs * f[i];
-        for (int s = 1; s < seq[c]; ++s) {
-          ce_rhs(zc, k, owner, lane, m, rc, Gm0, G, f_in, f);
-#pragma unroll
-          for (int i = 0; i < 6; ++i) {
-            const double zn = zm[i] + 2.0 * hs * f[i];
-            zm[i] = zc[i];
-            zc[i] = zn;
-          }
-        }
-        ce_rhs(zc, k, owner, lane, m, rc, Gm0, G, f_in, f);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) est[i] = (zc[i] + zm[i] + hs * f[i]) / 2.0;
-        // Aitken-Neville: row c from row c - 1
-        double e = 0.0;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-          double cur = est[i];
-#pragma unroll
-          for (int j = 1; j <= c; ++j) {
-            const double old = R[j - 1][i];
-            R[j - 1][i] = cur;
-            const double ratio = (double)seq[c] / (double)seq[c - j];
-            cur = cur + (cur - old) / (ratio * ratio - 1.0);
-          }
-          R[c][i] = cur;
-          if (c >= 2) e = fmax(e, fabs(R[c][i] - R[c - 1][i]) / (i < 3 ? sx : sv));
-        }
-        if (c >= 2 && wave_max_d(act ? e : 0.0) <= tol) accepted = c;
-      }
-    }
+    for (int c = 2; c < 8; ++c)
+      if (accepted < 0 && __ballot(act && !(err[c] <= tol)) == 0) accepted = c;
     if (accepted < 0) {
+      buf ^= 1;
       H = H / 2.0;
       if (++halvings > 60) { status = 1; break; }
       continue;
     }
     halvings = 0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if (c == accepted)
+    for (int i = 0; i < 6; ++i) {
+      double e[8], dummy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < 6; ++i) y[i] = R[c][i];
+      for (int c = 0; c < 8; ++c) e[c] = est_s[buf][c][i][slot];
+      y[i] = ce_tableau(e, 1.0, accepted, dummy);
+    }
+    buf ^= 1;
     if (t + H == t) break;   // the remaining interval is below the resolution of t
     t = t + H;
-    if (accepted <= 4) H = H * 2.0;
+    if (accepted <= 3) H = H * 4.0;
+    else if (accepted == 4) H = H * 2.0;
   }
-  if (act) {
+  if (wv == 0 && rep == 0 && act) {
     xm[b] = make_double4(y[0], y[1], y[2], p0.w);
     v[b] = make_double4(y[3], y[4], y[5], u0.w);
   }
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     atomicAdd(stats + 0, 1ull);
     atomicMax(stats + 1, (unsigned long long)k);
     atomicAdd(stats + 2, (unsigned long long)k);
@@ -287,7 +362,8 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
                            const int *ngroups, int max_groups, double G, double m0, double f_in,
                            double h, double tol, unsigned long long *stats, hipStream_t st) {
   if (max_groups > 0)
-    hipLaunchKernelGGL(k_ce_drift, dim3(max_groups), dim3(64), 0, st, xm, v, thr, gmem, gstart, gsize,
+    hipLaunchKernelGGL(k_ce_drift, dim3(max_groups), dim3(64 * kCeWaves), 0, st, xm, v, thr, gmem,
+                       gstart, gsize,
                        groot, ngroups, G, m0, f_in, h, tol, stats);
   return hipGetLastError();
 }
