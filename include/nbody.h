@@ -144,8 +144,9 @@ int nbody_encounter_groups(nbody_ctx *ctx, int64_t n, const int32_t *pairs, int6
  *   dx_i/dt = v_i,
  *   dv_i/dt = -G m0 x_i/|x_i|^3 + G sum_{j in group, j != i} m_j ((1 - K)/r^3 + K'(r)/r^2) d_ij,
  * integrated with the Gragg-Bulirsch-Stoer method (binary64, tolerance 1e-14 relative to the
- * group's largest position and velocity), one wave per group; a body alone in its group follows
- * its Kepler orbit (as nbody_drift). thr as from nbody_rcrit (rc_i sets the changeover).
+ * group's largest position and velocity), one workgroup of four waves per group (the waves run
+ * the extrapolation's midpoint sweeps side by side); a body alone in its group follows its Kepler
+ * orbit (as nbody_drift). thr as from nbody_rcrit (rc_i sets the changeover).
  * stats (device int64 [6]) receives: [0] groups integrated, [1] largest group, [2] bodies in
  * groups, [3] groups of more than 64 bodies (moved on Kepler orbits only: the result is then not
  * the H_A flow), [4] groups whose integration did not finish, [5] (nbody_step_hybrid only)
