@@ -99,11 +99,12 @@ __global__ __launch_bounds__(kBlock) void k_gfill(const int *__restrict__ label,
 // every wave then forms the same extrapolation tableau, takes the same decision and updates the
 // same state, so the waves stay in step without further exchange.
 //
-// Within a wave, body slot s (0 <= s < k) sits on the lanes s + kp r, r = 0 .. 64/kp - 1, with kp
-// the power of two at or above k: replica r sums the pair terms of every (64/kp)-th member, and the
-// replicas' partial sums meet in a butterfly over lane distances kp, 2 kp, ... (commutative
-// additions, so every replica ends with the same bits). Small groups thus spread their pair sums
-// over the whole wave.
+// Within a wave, body slot s (0 <= s < k) sits on the P lanes s P + r, r = 0 .. P - 1, with
+// P = min(64/kp, 16) and kp the power of two at or above k: replica r sums the pair terms of every
+// P-th member, and the replicas' partial sums meet in a butterfly inside a 16-lane row made of DPP
+// moves (lane exchanges xor 1 and xor 2, then the half-row and row mirrors), each stage an addition
+// of two equal-sized partial sums in either order, so every replica ends with the same bits. Small
+// groups thus spread their pair sums over the whole wave.
 constexpr int kCeWaves = 4;
 constexpr int kMaxMacroSteps = 20000;
 
@@ -113,54 +114,119 @@ __device__ __forceinline__ double wave_max_d(double x) {
   return x;
 }
 
+// r^-1 to a few ulp: the hardware reciprocal square root (relative error about 2^-24) refined by
+// the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3), e = 1 - r2 y^2.
+__device__ __forceinline__ double ce_rinv(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2, y * y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// 1/d for d in [1/2, 1] (the changeover's denominator): the hardware reciprocal refined by two
+// Newton steps x <- x + x (1 - d x), each of which squares the relative error.
+__device__ __forceinline__ double ce_recip(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  x = fma(x, fma(-d, x, 1.0), x);
+  x = fma(x, fma(-d, x, 1.0), x);
+  return x;
+}
+
 // Per-member constants in ascending body order: G m, rc, 1/((1 - f_in) rc).
 struct CeMember {
   double Gm, rc, ispan, pad;
 };
 
-// f = (v, a) of this lane's body at the state z. The pair coefficient is
-// G m_j ((1 - K)/r^3 + K'(r)/r^2) for r < rc_ij and zero beyond; with y the changeover variable and
-// D = 2y^2 - 2y + 1, K = y^2/D, 1 - K = (1 - y)^2/D and K'(r) = 2y(1 - y)/(D^2 (1 - f_in) rc_ij).
-__device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, int iters, int P, int rep,
-                                       int slot, const int *owner, const CeMember *mem,
-                                       double rc, double ispan, double Gm0, double f_in,
-                                       int kp, double (&f)[6]) {
+// A lane's partners: for iteration it the member q = rep + it P (in ascending body order), the lane
+// src of its first replica, and whether the term counts (a member, and not the lane's own body).
+struct CePartner {
+  int src;
+  bool use;
+  CeMember m;
+};
+
+__device__ __forceinline__ CePartner ce_partner(int q, int k, bool act, int slot, int P,
+                                                const int *owner, const CeMember *mem) {
+  const bool valid = q < k;
+  const int qq = valid ? q : 0;
+  CePartner p;
+  p.src = owner[qq] * P;
+  p.use = act && valid && owner[qq] != slot;
+  p.m = mem[qq];
+  return p;
+}
+
+// Pair term of one partner, added to a. The coefficient is G m_j ((1 - K)/r^3 + K'(r)/r^2); with y
+// the changeover variable clamped to [0, 1] and D = 2y^2 - 2y + 1, 1 - K = (1 - y)^2/D and
+// K'(r) = 2y(1 - y)/(D^2 (1 - f_in) rc_ij), which gives 1/r^3 inside f_in rc_ij and 0 beyond rc_ij
+// with no branch. No division or square root: r^-1 and 1/D come from refined hardware estimates.
+__device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p, double rc,
+                                        double ispan, double f_in, double &a0, double &a1,
+                                        double &a2) {
+  const double dx = __shfl(z[0], p.src, 64) - z[0];
+  const double dy = __shfl(z[1], p.src, 64) - z[1];
+  const double dz = __shfl(z[2], p.src, 64) - z[2];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir = ce_rinv(r2);
+  const double r = r2 * ir;
+  const bool mine = rc > p.m.rc;
+  const double rcij = mine ? rc : p.m.rc;
+  const double isp = mine ? ispan : p.m.ispan;
+  const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
+  const double omy = 1.0 - y;
+  const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
+  const double c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
+  const double cm = p.use ? c * p.m.Gm : 0.0;
+  a0 = fma(cm, dx, a0);
+  a1 = fma(cm, dy, a1);
+  a2 = fma(cm, dz, a2);
+}
+
+// x from the lane that DPP control CTRL names (within a 16-lane row), in two 32-bit moves.
+template <int CTRL>
+__device__ __forceinline__ double ce_dpp(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void ce_row_add(double &a0, double &a1, double &a2) {
+  a0 += ce_dpp<CTRL>(a0);
+  a1 += ce_dpp<CTRL>(a1);
+  a2 += ce_dpp<CTRL>(a2);
+}
+
+// Partners of a lane kept in registers; members beyond them are read from LDS.
+constexpr int kCeRegPartners = 4;
+
+// f = (v, a) of this lane's body at the state z.
+__device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, bool act, int iters, int P,
+                                       int rep, int slot, const int *owner, const CeMember *mem,
+                                       const CePartner (&pr)[kCeRegPartners], double rc,
+                                       double ispan, double Gm0, double f_in, double (&f)[6]) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int it = 0; it < iters; ++it) {
-    const int q = rep + it * P;
-    const bool valid = q < k;
-    const int qq = valid ? q : 0;
-    const int src = owner[qq];
-    const double xj = __shfl(z[0], src, 64), yj = __shfl(z[1], src, 64),
-                 zj = __shfl(z[2], src, 64);
-    const CeMember mj = mem[qq];
-    const double dx = xj - z[0], dy = yj - z[1], dz = zj - z[2];
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double rcij = rc > mj.rc ? rc : mj.rc;
-    if (valid && src != slot && r2 < rcij * rcij) {
-      const double r = sqrt(r2);
-      const double ir = 1.0 / r;
-      const double isp = rc > mj.rc ? ispan : mj.ispan;
-      const double y = (r - f_in * rcij) * isp;
-      double c = ir * ir * ir;
-      if (y > 0.0) {
-        const double iD = 1.0 / (2.0 * y * y - 2.0 * y + 1.0);
-        const double omy = 1.0 - y;
-        c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
+  if (iters == 1) {
+    ce_pair(z, pr[0], rc, ispan, f_in, a0, a1, a2);
+  } else {
+    // independent terms side by side (masked beyond the members)
+#pragma unroll
+    for (int u = 0; u < kCeRegPartners; ++u) ce_pair(z, pr[u], rc, ispan, f_in, a0, a1, a2);
+    for (int it = kCeRegPartners; it < iters; it += kCeRegPartners) {
+#pragma unroll
+      for (int u = 0; u < kCeRegPartners; ++u) {
+        const CePartner p = ce_partner(rep + (it + u) * P, k, act, slot, P, owner, mem);
+        ce_pair(z, p, rc, ispan, f_in, a0, a1, a2);
       }
-      c *= mj.Gm;
-      a0 += c * dx;
-      a1 += c * dy;
-      a2 += c * dz;
     }
   }
-  for (int o = kp; o < 64; o <<= 1) {
-    a0 += __shfl_xor(a0, o, 64);
-    a1 += __shfl_xor(a1, o, 64);
-    a2 += __shfl_xor(a2, o, 64);
-  }
+  if (P >= 2) ce_row_add<0xB1>(a0, a1, a2);    // quad_perm [1, 0, 3, 2]: lane xor 1
+  if (P >= 4) ce_row_add<0x4E>(a0, a1, a2);    // quad_perm [2, 3, 0, 1]: lane xor 2
+  if (P >= 8) ce_row_add<0x141>(a0, a1, a2);   // half-row mirror: lane i <-> 7 - i
+  if (P >= 16) ce_row_add<0x140>(a0, a1, a2);  // row mirror: lane i <-> 15 - i
   const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
-  const double s = -Gm0 / (r2 * sqrt(r2));
+  const double ir = ce_rinv(r2);
+  const double s = -Gm0 * (ir * ir * ir);
   f[0] = z[3]; f[1] = z[4]; f[2] = z[5];
   f[3] = s * z[0] + a0;
   f[4] = s * z[1] + a1;
@@ -168,20 +234,21 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, int iters, i
 }
 
 // Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
-__device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, int k, int iters,
-                                         int P, int rep, int slot, const int *owner,
-                                         const CeMember *mem, double rc, double ispan, double Gm0,
-                                         double f_in, int kp, double (&est)[6]) {
+__device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, int k, bool act,
+                                         int iters, int P, int rep, int slot, const int *owner,
+                                         const CeMember *mem, const CePartner (&pr)[kCeRegPartners],
+                                         double rc, double ispan, double Gm0, double f_in,
+                                         double (&est)[6]) {
   const double hs = H / ns;
   double zm[6], zc[6], f[6];
-  ce_rhs(y, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, f);
+  ce_rhs(y, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
     zc[i] = y[i] + hs * f[i];
   }
   for (int s = 1; s < ns; ++s) {
-    ce_rhs(zc, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, f);
+    ce_rhs(zc, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const double zn = zm[i] + 2.0 * hs * f[i];
@@ -189,7 +256,7 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
       zc[i] = zn;
     }
   }
-  ce_rhs(zc, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, f);
+  ce_rhs(zc, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zc[i] + zm[i] + hs * f[i]);
 }
@@ -254,8 +321,8 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
   const int lane = threadIdx.x & 63;
   int kp = 1;
   while (kp < k) kp <<= 1;
-  const int P = 64 / kp;
-  const int slot = lane & (kp - 1), rep = lane / kp;
+  const int P = min(64 / kp, 16);
+  const int slot = lane / P, rep = lane & (P - 1);
   const int iters = (k + P - 1) / P;
   const bool act = slot < k;
   const int b = gmem[base + (act ? slot : 0)];
@@ -269,6 +336,10 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     mem[rank] = CeMember{G * p0.w, rc, ispan, 0.0};
   }
   __syncthreads();
+  CePartner pr[kCeRegPartners];
+#pragma unroll
+  for (int u = 0; u < kCeRegPartners; ++u)
+    pr[u] = ce_partner(rep + u * P, k, act, slot, P, owner, mem);
   double y[6] = {p0.x, p0.y, p0.z, u0.x, u0.y, u0.z};
   double t = 0.0, H = h;
   int halvings = 0, macro = 0, status = 0, buf = 0;
@@ -282,7 +353,8 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     for (int cc = 0; cc < 2; ++cc) {
       const int c = cc == 0 ? wv : 7 - wv;
       double est[6];
-      ce_sweep(y, H, 2 * c + 2, k, iters, P, rep, slot, owner, mem, rc, ispan, Gm0, f_in, kp, est);
+      ce_sweep(y, H, 2 * c + 2, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in,
+               est);
       if (rep == 0)
 #pragma unroll
         for (int i = 0; i < 6; ++i) est_s[buf][c][i][slot] = est[i];
