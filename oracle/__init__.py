@@ -50,6 +50,8 @@ def _lib():
         "or_ce_drift_group": (ctypes.c_int, [P, ctypes.c_int, P, P, P, P, P, D, D]),
         "or_step_hybrid": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P]),
         "or_drift_groups": (ctypes.c_int, [I, P, P, P, P, P, P, D, D, P]),
+        "or_drift_groups_merge": (ctypes.c_int, [I, P, P, P, P, P, P, D, D, P, P, D, ctypes.c_int, P, P, I, P]),
+        "or_step_merge": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P, P, D, P, P, I, P]),
         "or_jump": (None, [I, P, P, P, P, D]),
         "or_drift": (ctypes.c_int, [I, P, P, P, D, P]),
         "or_drift_q": (ctypes.c_int, [I, P, P, P, D]),
@@ -185,6 +187,42 @@ def step_hybrid(x, v, m, p, nsteps, thr=None, tol=1e-18):
     st = _lib().or_step_hybrid(len(m), _p(x), _p(v), _p(m), _p(_prm(p)), int(nsteps), _p(rc), _p(H), _p(V),
                                float(tol), _p(stats))
     return x, v, st, tuple(int(s) for s in stats)
+
+
+def _merge_log(merges, mtime, cnt):
+    k = min(int(cnt), merges.shape[0])
+    return merges[:k].copy(), mtime[:k].copy()
+
+
+def drift_groups_merge(x, v, m, rc, R, f, labels, p, h, tol=1e-18, step=0, cap=4096):
+    """drift_groups with collisions as perfect mergers: two bodies of a group merge when their
+    distance falls below f (R_i + R_j), at the first contact time. Returns x, v, m, R, status,
+    stats, merges {step, survivor, removed} and their times within the drift."""
+    x = _f64(x).copy(); v = _f64(v).copy(); m = _f64(m).copy(); R = _f64(R).copy()
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    stats = np.zeros(3, dtype=np.int64)
+    merges = np.zeros((cap, 3), dtype=np.int32); mtime = np.zeros(cap)
+    cnt = ctypes.c_int64(0)
+    st = _lib().or_drift_groups_merge(len(lab), _p(x), _p(v), _p(m), _p(_f64(rc)), _p(lab), _p(_prm(p)),
+                                      float(h), float(tol), _p(stats), _p(R), float(f), int(step),
+                                      _p(merges), _p(mtime), cap, ctypes.byref(cnt))
+    mg, mt = _merge_log(merges, mtime, cnt.value)
+    return x, v, m, R, st, tuple(int(s) for s in stats), mg, mt
+
+
+def step_merge(x, v, m, R, f, p, nsteps, thr=None, tol=1e-18, cap=4096):
+    """nsteps hybrid steps with collisions as perfect mergers (radius factor f). Returns x, v, m, R,
+    status, stats, merges {step, survivor, removed} and their times within the step's drift."""
+    x = _f64(x).copy(); v = _f64(v).copy(); m = _f64(m).copy(); R = _f64(R).copy()
+    rc, H, V = (None, None, None) if thr is None else (_f64(t) for t in thr)
+    stats = np.zeros(3, dtype=np.int64)
+    merges = np.zeros((cap, 3), dtype=np.int32); mtime = np.zeros(cap)
+    cnt = ctypes.c_int64(0)
+    st = _lib().or_step_merge(len(m), _p(x), _p(v), _p(m), _p(_prm(p)), int(nsteps), _p(rc), _p(H), _p(V),
+                              float(tol), _p(stats), _p(R), float(f), _p(merges), _p(mtime), cap,
+                              ctypes.byref(cnt))
+    mg, mt = _merge_log(merges, mtime, cnt.value)
+    return x, v, m, R, st, tuple(int(s) for s in stats), mg, mt
 
 
 def jump(x, v, m, p, h):

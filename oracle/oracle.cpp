@@ -407,9 +407,14 @@ static int64_t groups_bfs(int64_t n, const int32_t *pairs, int64_t npairs, int32
 // potential, the complement of the kick's weight, and vanishes for r >= rc_ij. Bodies in no group
 // keep the Kepler drift.
 template <class T>
-static void ce_rhs(int k, const T *y, const double *m, const double *rc, const Params &p, T *f) {
+static void ce_rhs(int k, const T *y, const double *m, const double *rc, const bool *alive, const Params &p,
+                   T *f) {
   const T *x = y, *v = y + 3 * k;
   for (int i = 0; i < k; i++) {
+    if (!alive[i]) {           // a body merged away is held fixed
+      for (int l = 0; l < 3; l++) f[3 * i + l] = f[3 * k + 3 * i + l] = T(0);
+      continue;
+    }
     T r2 = x[3 * i] * x[3 * i] + x[3 * i + 1] * x[3 * i + 1] + x[3 * i + 2] * x[3 * i + 2];
     T r = msqrt(r2);
     T s = T(0) - T(p.G * p.m0) / (r2 * r);
@@ -435,86 +440,209 @@ static void ce_rhs(int k, const T *y, const double *m, const double *rc, const P
   }
 }
 
-// Gragg-Bulirsch-Stoer integration of one group over time h: a macro step H is covered by
-// modified-midpoint sweeps with n = 2, 4, ..., 16 substeps, and the sweeps are extrapolated to
-// zero substep length as a polynomial in (H/n)^2 (Aitken-Neville). A step is accepted when the
-// last two extrapolants agree to tol, relative to the group's largest position and velocity;
-// otherwise H is halved. y = [x (3k), v (3k)] in and out. Returns 0, or 1 if H had to be halved
-// more than 60 times in a row.
+// Collisions as perfect mergers (the paper's outcomes of collisions, with the radius factor f of
+// its section on the acceleration factor). Two bodies of a group are in contact when their
+// distance is below f (R_i + R_j); the merger keeps the lower body index with the summed mass, the
+// summed volume (R^3 = R_i^3 + R_j^3) and the centre-of-mass position and velocity, and parks the
+// other as a massless body of zero radius on a circular orbit of radius 1e6 about the central mass
+// at the angle 2 pi j/n, far from everything.
+struct MergeCtx {
+  double f;                  // radius factor
+  int64_t n;                 // bodies in the system (parking angle)
+  int step;                  // step index written to the log
+  std::vector<int64_t> *log; // {step, survivor, removed} per merger
+  std::vector<long double> *time;   // time within the drift of each merger
+};
+
+constexpr double kParkRadius = 1e6;
+constexpr int kMaxBisections = 80;   // contact-time bisection: at most 80 halvings of the step
+
 template <class T>
-static int ce_drift_group(int k, T *y, const double *m, const double *rc, const Params &p, double h,
-                          double tol) {
+static int contact_pair(int k, const T *y, const double *R, const bool *alive, double f) {
+  for (int a = 0; a < k; a++)
+    for (int b = a + 1; b < k; b++) {
+      if (!alive[a] || !alive[b]) continue;
+      T d2 = T(0);
+      for (int l = 0; l < 3; l++) {
+        const T d = y[3 * b + l] - y[3 * a + l];
+        d2 = d2 + d * d;
+      }
+      const T lim = T(f * (R[a] + R[b]));
+      if (val(d2) < val(lim * lim)) return a * k + b;
+    }
+  return -1;
+}
+
+// One Gragg-Bulirsch-Stoer attempt over H from y: modified-midpoint sweeps with n = 2, 4, ..., 16
+// substeps, extrapolated to zero substep length as a polynomial in (H/n)^2 (Aitken-Neville). The
+// attempt is accepted at the first column c >= 2 whose last two extrapolants agree to tol (relative
+// to the group's largest position and velocity of the bodies still present); y1 receives that
+// extrapolant. Returns the column, or -1.
+template <class T>
+static int gbs_attempt(int k, const T *y, const double *m, const double *rc, const bool *alive,
+                       const Params &p, T H, double tol, T *y1) {
   const int seq[8] = {2, 4, 6, 8, 10, 12, 14, 16};
   const int D = 6 * k;
   std::vector<T> R(8 * (size_t)D), zm(D), zc(D), zn(D), f(D), est(D);
-  T t = T(0), H = T(h);
-  const T hT = T(h);
-  int halvings = 0;
-  while (val(mabs(hT - t)) > 0) {
-    if (val(mabs(H)) > val(mabs(hT - t))) H = hT - t;
-    T sx = T(0), sv = T(0);
-    for (int i = 0; i < 3 * k; i++) {
-      sx = mmax(sx, mabs(y[i]));
-      sv = mmax(sv, mabs(y[3 * k + i]));
-    }
-    int accepted = -1;
-    for (int c = 0; c < 8 && accepted < 0; c++) {
-      const int ns = seq[c];
-      const T hs = H / T(ns);
-      // modified midpoint: z1 = z0 + hs f(z0); z_{s+1} = z_{s-1} + 2 hs f(z_s); end value
-      // (z_n + z_{n-1} + hs f(z_n)) / 2
-      for (int i = 0; i < D; i++) zm[i] = y[i];
-      ce_rhs<T>(k, zm.data(), m, rc, p, f.data());
-      for (int i = 0; i < D; i++) zc[i] = zm[i] + hs * f[i];
-      for (int s = 1; s < ns; s++) {
-        ce_rhs<T>(k, zc.data(), m, rc, p, f.data());
-        for (int i = 0; i < D; i++) {
-          zn[i] = zm[i] + T(2) * hs * f[i];
-          zm[i] = zc[i];
-          zc[i] = zn[i];
-        }
+  T sx = T(0), sv = T(0);
+  for (int a = 0; a < k; a++)
+    for (int l = 0; l < 3; l++)
+      if (alive[a]) {
+        sx = mmax(sx, mabs(y[3 * a + l]));
+        sv = mmax(sv, mabs(y[3 * k + 3 * a + l]));
       }
-      ce_rhs<T>(k, zc.data(), m, rc, p, f.data());
-      for (int i = 0; i < D; i++) est[i] = (zc[i] + zm[i] + hs * f[i]) / T(2);
-      // Aitken-Neville in (H/n)^2: row c from row c - 1
+  for (int c = 0; c < 8; c++) {
+    const int ns = seq[c];
+    const T hs = H / T(ns);
+    // modified midpoint: z1 = z0 + hs f(z0); z_{s+1} = z_{s-1} + 2 hs f(z_s); end value
+    // (z_n + z_{n-1} + hs f(z_n)) / 2
+    for (int i = 0; i < D; i++) zm[i] = y[i];
+    ce_rhs<T>(k, zm.data(), m, rc, alive, p, f.data());
+    for (int i = 0; i < D; i++) zc[i] = zm[i] + hs * f[i];
+    for (int s = 1; s < ns; s++) {
+      ce_rhs<T>(k, zc.data(), m, rc, alive, p, f.data());
       for (int i = 0; i < D; i++) {
-        T cur = est[i];
-        for (int j = 1; j <= c; j++) {
-          const T old = R[(size_t)(j - 1) * D + i];
-          R[(size_t)(j - 1) * D + i] = cur;
-          const T ratio = T(seq[c]) / T(seq[c - j]);
-          cur = cur + (cur - old) / (ratio * ratio - T(1));
-        }
-        R[(size_t)c * D + i] = cur;
-      }
-      if (c >= 2) {
-        double err = 0;
-        for (int i = 0; i < D; i++) {
-          const T sc = i < 3 * k ? sx : sv;
-          err = std::max(err, val(mabs(R[(size_t)c * D + i] - R[(size_t)(c - 1) * D + i]) / sc));
-        }
-        if (err <= tol) accepted = c;
+        zn[i] = zm[i] + T(2) * hs * f[i];
+        zm[i] = zc[i];
+        zc[i] = zn[i];
       }
     }
-    if (accepted < 0) {
+    ce_rhs<T>(k, zc.data(), m, rc, alive, p, f.data());
+    for (int i = 0; i < D; i++) est[i] = (zc[i] + zm[i] + hs * f[i]) / T(2);
+    // Aitken-Neville in (H/n)^2: row c from row c - 1
+    for (int i = 0; i < D; i++) {
+      T cur = est[i];
+      for (int j = 1; j <= c; j++) {
+        const T old = R[(size_t)(j - 1) * D + i];
+        R[(size_t)(j - 1) * D + i] = cur;
+        const T ratio = T(seq[c]) / T(seq[c - j]);
+        cur = cur + (cur - old) / (ratio * ratio - T(1));
+      }
+      R[(size_t)c * D + i] = cur;
+    }
+    if (c >= 2) {
+      double err = 0;
+      for (int i = 0; i < D; i++) {
+        const int body = (i % (3 * k)) / 3;
+        if (!alive[body]) continue;
+        const T sc = i < 3 * k ? sx : sv;
+        err = std::max(err, val(mabs(R[(size_t)c * D + i] - R[(size_t)(c - 1) * D + i]) / sc));
+      }
+      if (err <= tol) {
+        for (int i = 0; i < D; i++) y1[i] = R[(size_t)c * D + i];
+        return c;
+      }
+    }
+  }
+  return -1;
+}
+
+// Integration of y over time L: macro steps from H = L, halved when rejected and doubled after
+// acceptance at column c <= 4. With radii given, every accepted step is followed by a contact test,
+// and the integration stops at the first step that ends in contact: y then still holds the state at
+// that step's start, *done the time covered before it and *Hc its length. Returns 0 (L covered),
+// 1 (contact) or 2 (H halved more than 60 times in a row).
+template <class T>
+static int gbs_advance(int k, T *y, const double *m, const double *rc, const bool *alive, const double *R,
+                       const Params &p, T L, double tol, double f, T *done, T *Hc) {
+  const int D = 6 * k;
+  std::vector<T> y1(D);
+  T t = T(0), H = L;
+  int halvings = 0;
+  while (val(mabs(L - t)) > 0) {
+    if (val(mabs(H)) > val(mabs(L - t))) H = L - t;
+    const int c = gbs_attempt<T>(k, y, m, rc, alive, p, H, tol, y1.data());
+    if (c < 0) {
       H = H / T(2);
-      if (++halvings > 60) return 1;
+      if (++halvings > 60) return 2;
       continue;
     }
     halvings = 0;
-    for (int i = 0; i < D; i++) y[i] = R[(size_t)accepted * D + i];
+    if (R && contact_pair<T>(k, y1.data(), R, alive, f) >= 0) {
+      *done = t;
+      *Hc = H;
+      return 1;
+    }
+    for (int i = 0; i < D; i++) y[i] = y1[i];
     if (t + H == t) break;            // the remaining interval is below the resolution of t
     t = t + H;
-    if (accepted <= 4) H = H * T(2);
+    if (c <= 4) H = H * T(2);
+  }
+  return 0;
+}
+
+// Close-encounter drift of one group over time h (y = [x (3k), v (3k)] in and out). Without
+// collisions (mc null) one adaptive integration. With collisions: integrate until a step ends in
+// contact; find the first contact time in that step by bisection on the step length (each trial an
+// adaptive integration from the step's start, halving until the interval cannot be split, at most
+// 80 times); merge
+// the contact pair of lowest member ranks at that time; continue with the merged body. m and R
+// (member masses and radii) are updated; ids are the members' body indices (ascending).
+template <class T>
+static int ce_drift_group(int k, T *y, double *m, const double *rc, const Params &p, double h, double tol,
+                          double *R = nullptr, const int64_t *ids = nullptr, MergeCtx *mc = nullptr) {
+  const int D = 6 * k;
+  std::vector<char> alive_c(k, 1);
+  bool *alive = reinterpret_cast<bool *>(alive_c.data());
+  const double *Rc = mc ? R : nullptr;
+  T t = T(0);
+  const T hT = T(h);
+  std::vector<T> y0(D), ym(D);
+  while (true) {
+    T done = T(0), Hc = T(0);
+    const int st = gbs_advance<T>(k, y, m, rc, alive, Rc, p, hT - t, tol, mc ? mc->f : 0.0, &done, &Hc);
+    if (st == 2) return 1;
+    if (st == 0) break;
+    t = t + done;
+    for (int i = 0; i < D; i++) y0[i] = y[i];
+    T lo = T(0), hi = Hc;
+    for (int it = 0; it < kMaxBisections; it++) {
+      const T mid = (lo + hi) / T(2);
+      if (!(val(mid) > val(lo) && val(mid) < val(hi))) break;
+      for (int i = 0; i < D; i++) ym[i] = y0[i];
+      T d2, h2;
+      if (gbs_advance<T>(k, ym.data(), m, rc, alive, nullptr, p, mid, tol, 0.0, &d2, &h2) == 2) return 1;
+      if (contact_pair<T>(k, ym.data(), R, alive, mc->f) >= 0) hi = mid; else lo = mid;
+    }
+    T d2, h2;
+    if (gbs_advance<T>(k, y, m, rc, alive, nullptr, p, hi, tol, 0.0, &d2, &h2) == 2) return 1;
+    t = t + hi;
+    const int pr = contact_pair<T>(k, y, R, alive, mc->f);
+    if (pr >= 0) {
+      const int a = pr / k, b = pr % k;
+      const double M = m[a] + m[b];
+      for (int l = 0; l < 3; l++) {
+        y[3 * a + l] = (T(m[a]) * y[3 * a + l] + T(m[b]) * y[3 * b + l]) / T(M);
+        y[3 * k + 3 * a + l] = (T(m[a]) * y[3 * k + 3 * a + l] + T(m[b]) * y[3 * k + 3 * b + l]) / T(M);
+      }
+      const double th = 2.0 * M_PI * (double)ids[b] / (double)mc->n;
+      const double vc = std::sqrt(p.G * p.m0 / kParkRadius);
+      y[3 * b] = T(kParkRadius * std::cos(th));
+      y[3 * b + 1] = T(kParkRadius * std::sin(th));
+      y[3 * b + 2] = T(0);
+      y[3 * k + 3 * b] = T(-vc * std::sin(th));
+      y[3 * k + 3 * b + 1] = T(vc * std::cos(th));
+      y[3 * k + 3 * b + 2] = T(0);
+      R[a] = std::cbrt(R[a] * R[a] * R[a] + R[b] * R[b] * R[b]);
+      R[b] = 0.0;
+      m[a] = M;
+      m[b] = 0.0;
+      alive[b] = false;
+      mc->log->insert(mc->log->end(), {(int64_t)mc->step, ids[a], ids[b]});
+      mc->time->push_back(t);
+    }
+    if (val(mabs(hT - t)) <= 0) break;
   }
   return 0;
 }
 
 // Drift of every body over h with the close-encounter groups given by labels (smallest index of
-// each body's group; a body alone in its group keeps the Kepler drift).
+// each body's group; a body alone in its group keeps the Kepler drift). With mc, bodies of a group
+// that come into contact merge (m and R updated).
 template <class T>
-static int drift_groups(int64_t n, T *x, T *v, const T *m, const double *rc, const int32_t *label,
-                        const Params &p, double h, double tol, int64_t *stats) {
+static int drift_groups(int64_t n, T *x, T *v, double *m, const double *rc, const int32_t *label,
+                        const Params &p, double h, double tol, int64_t *stats, double *R = nullptr,
+                        MergeCtx *mc = nullptr) {
   std::vector<std::vector<int64_t>> members((size_t)n);
   for (int64_t i = 0; i < n; i++) members[(size_t)label[i]].push_back(i);
   int worst = 0;
@@ -528,22 +656,28 @@ static int drift_groups(int64_t n, T *x, T *v, const T *m, const double *rc, con
     }
     const int k = (int)g.size();
     std::vector<T> y(6 * (size_t)k);
-    std::vector<double> mg(k), rcg(k);
+    std::vector<double> mg(k), rcg(k), Rg(k, 0.0);
     for (int a = 0; a < k; a++) {
       for (int l = 0; l < 3; l++) {
         y[3 * a + l] = x[3 * g[a] + l];
         y[3 * k + 3 * a + l] = v[3 * g[a] + l];
       }
-      mg[a] = val(m[g[a]]);
+      mg[a] = m[g[a]];
       rcg[a] = rc[g[a]];
+      if (R) Rg[a] = R[g[a]];
     }
-    const int st = ce_drift_group<T>(k, y.data(), mg.data(), rcg.data(), p, h, tol);
+    const int st = ce_drift_group<T>(k, y.data(), mg.data(), rcg.data(), p, h, tol, Rg.data(), g.data(), mc);
     worst = std::max(worst, st);
-    for (int a = 0; a < k; a++)
+    for (int a = 0; a < k; a++) {
       for (int l = 0; l < 3; l++) {
         x[3 * g[a] + l] = y[3 * a + l];
         v[3 * g[a] + l] = y[3 * k + 3 * a + l];
       }
+      if (mc) {
+        m[g[a]] = mg[a];
+        R[g[a]] = Rg[a];
+      }
+    }
     if (stats) {
       stats[0] += 1;
       stats[1] = std::max<int64_t>(stats[1], k);
@@ -554,9 +688,11 @@ static int drift_groups(int64_t n, T *x, T *v, const T *m, const double *rc, con
 }
 
 // nsteps hybrid steps: as steps() but the drift integrates H_A in full, every close-encounter
-// group (from the close pairs at the positions of the step's first kick) with ce_drift_group.
-static int steps_hybrid(int64_t n, double *x, double *v, const double *m, const Params &p, int nsteps,
-                        const double *rc, const double *H, const double *V, double tol, int64_t *stats) {
+// group (from the close pairs at the positions of the step's first kick) with ce_drift_group;
+// with mc, contacts within a group merge (m and R updated, mergers logged with their step).
+static int steps_hybrid(int64_t n, double *x, double *v, double *m, const Params &p, int nsteps,
+                        const double *rc, const double *H, const double *V, double tol, int64_t *stats,
+                        double *R = nullptr, MergeCtx *mc = nullptr) {
   std::vector<double> acc(3 * n);
   std::vector<int32_t> label(n);
   const double h = 0.5 * p.dt;
@@ -569,9 +705,10 @@ static int steps_hybrid(int64_t n, double *x, double *v, const double *m, const 
     encounters(n, x, H, V, np, pairs.data());
     groups_bfs(n, pairs.data(), np, label.data(), nullptr);
     jump<double>(n, x, v, m, p, h);
-    std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n), ml(m, m + n);
-    worst = std::max(worst, drift_groups<long double>(n, xl.data(), vl.data(), ml.data(), rc, label.data(),
-                                                      p, p.dt, tol, stats));
+    std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n);
+    if (mc) mc->step = s;
+    worst = std::max(worst, drift_groups<long double>(n, xl.data(), vl.data(), m, rc, label.data(), p, p.dt,
+                                                      tol, stats, R, mc));
     for (int64_t i = 0; i < 3 * n; i++) { x[i] = (double)xl[i]; v[i] = (double)vl[i]; }
     jump<double>(n, x, v, m, p, h);
     kick_acc<double>(n, x, m, rc, H, V, p, acc.data(), nullptr, nullptr);
@@ -709,10 +846,41 @@ int or_ce_drift_group(const int64_t *idx, int k, double *x, double *v, const dou
 int or_drift_groups(int64_t n, double *x, double *v, const double *m, const double *rc, const int32_t *label,
                     const double *prm, double h, double tol, int64_t *stats) {
   Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
-  std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n), ml(m, m + n);
+  std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n);
+  std::vector<double> mm(m, m + n);
   if (stats) stats[0] = stats[1] = stats[2] = 0;
-  const int st = drift_groups<long double>(n, xl.data(), vl.data(), ml.data(), rc, label, p, h, tol, stats);
+  const int st = drift_groups<long double>(n, xl.data(), vl.data(), mm.data(), rc, label, p, h, tol, stats);
   for (int64_t i = 0; i < 3 * n; i++) { x[i] = (double)xl[i]; v[i] = (double)vl[i]; }
+  return st;
+}
+
+// Copies a merger log out: up to cap entries of {step, survivor, removed} and their times; returns
+// the number of mergers.
+static int64_t put_log(const std::vector<int64_t> &log, const std::vector<long double> &time, int64_t cap,
+                       int32_t *merges, double *mtime) {
+  const int64_t cnt = (int64_t)time.size();
+  for (int64_t e = 0; e < std::min(cnt, cap); e++) {
+    for (int l = 0; l < 3; l++) merges[3 * e + l] = (int32_t)log[3 * e + l];
+    mtime[e] = (double)time[e];
+  }
+  return cnt;
+}
+
+// As or_drift_groups, with collisions: bodies of a group whose distance falls below
+// f (R_i + R_j) merge (m and R in/out; mergers logged as {step, survivor, removed} with the time
+// within the drift). Returns the integrator status; *count receives the number of mergers.
+int or_drift_groups_merge(int64_t n, double *x, double *v, double *m, const double *rc, const int32_t *label,
+                          const double *prm, double h, double tol, int64_t *stats, double *R, double f,
+                          int step, int32_t *merges, double *mtime, int64_t cap, int64_t *count) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n);
+  std::vector<int64_t> log;
+  std::vector<long double> time;
+  MergeCtx mc{f, n, step, &log, &time};
+  if (stats) stats[0] = stats[1] = stats[2] = 0;
+  const int st = drift_groups<long double>(n, xl.data(), vl.data(), m, rc, label, p, h, tol, stats, R, &mc);
+  for (int64_t i = 0; i < 3 * n; i++) { x[i] = (double)xl[i]; v[i] = (double)vl[i]; }
+  *count = put_log(log, time, cap, merges, mtime);
   return st;
 }
 
@@ -729,7 +897,30 @@ int or_step_hybrid(int64_t n, double *x, double *v, const double *m, const doubl
     thresholds(n, x, v, m, p, rc.data(), H.data(), V.data());
   }
   if (stats) stats[0] = stats[1] = stats[2] = 0;
-  return steps_hybrid(n, x, v, m, p, nsteps, rc.data(), H.data(), V.data(), tol, stats);
+  std::vector<double> mm(m, m + n);
+  return steps_hybrid(n, x, v, mm.data(), p, nsteps, rc.data(), H.data(), V.data(), tol, stats);
+}
+
+// nsteps hybrid steps with collisions (perfect mergers at contact, radius factor f): m and R in/out,
+// mergers logged as {step, survivor, removed} with the time within the step's drift.
+int or_step_merge(int64_t n, double *x, double *v, double *m, const double *prm, int nsteps,
+                  const double *rc_in, const double *H_in, const double *V_in, double tol, int64_t *stats,
+                  double *R, double f, int32_t *merges, double *mtime, int64_t cap, int64_t *count) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  std::vector<double> rc(n), H(n), V(n);
+  if (rc_in && H_in && V_in) {
+    std::copy(rc_in, rc_in + n, rc.begin()); std::copy(H_in, H_in + n, H.begin());
+    std::copy(V_in, V_in + n, V.begin());
+  } else {
+    thresholds(n, x, v, m, p, rc.data(), H.data(), V.data());
+  }
+  if (stats) stats[0] = stats[1] = stats[2] = 0;
+  std::vector<int64_t> log;
+  std::vector<long double> time;
+  MergeCtx mc{f, n, 0, &log, &time};
+  const int st = steps_hybrid(n, x, v, m, p, nsteps, rc.data(), H.data(), V.data(), tol, stats, R, &mc);
+  *count = put_log(log, time, cap, merges, mtime);
+  return st;
 }
 
 void or_jump(int64_t n, double *x, const double *v, const double *m, const double *prm, double h) {

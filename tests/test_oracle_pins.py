@@ -549,3 +549,75 @@ def test_hybrid_step_conserves_full_energy(params, disk2048_groups):
     if a[3][0] == 0:
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------ collisions as perfect mergers
+def test_merge_radial_infall_contact_time_closed_form(params):
+    """Two bodies released at rest with a negligible central mass fall radially onto each other: the
+    relative orbit is the degenerate Kepler ellipse of mu = G (m1 + m2), so the separation reaches
+    f (R1 + R2) at t = sqrt(r0^3 / (8 mu)) (pi - E + sin E), cos E = 1 - 2 f (R1 + R2)/r0 (closed
+    form). The merged body has the summed mass and volume and moves with the centre of mass; the
+    removed body is parked far away, massless."""
+    p = dict(params, m0=1e-30)
+    m = np.array([3e-6, 1e-6]); R = np.array([6e-5, 4e-5]); f = 1.5
+    r0 = 2e-3
+    x = np.array([[1.0, 0.0, 0.0], [1.0 + r0, 0.0, 0.0]])
+    v = np.array([[0.01, 0.02, 0.0], [0.01, 0.02, 0.0]])
+    rc = np.array([5e-2, 5e-2])                  # r0 < f_in rc: full Newtonian pull
+    h = 0.1
+    X, V, M, RR, st, stats, mg, mt = oracle.drift_groups_merge(x, v, m, rc, R, f, np.array([0, 0]), p, h)
+    assert st == 0
+    np.testing.assert_array_equal(mg, [[0, 0, 1]])
+    mu = p["G"] * m.sum()
+    E = math.acos(1 - 2 * f * R.sum() / r0)
+    tc = math.sqrt(r0 ** 3 / (8 * mu)) * (math.pi - E + math.sin(E))
+    assert abs(mt[0] - tc) < 1e-14 * tc
+    assert M[0] == m[0] + m[1] and M[1] == 0.0
+    assert abs(RR[0] ** 3 - (R ** 3).sum()) < 1e-15 * (R ** 3).sum() and RR[1] == 0.0
+    xcm = (m[:, None] * x).sum(0) / m.sum(); vcm = (m[:, None] * v).sum(0) / m.sum()
+    np.testing.assert_allclose(X[0], xcm + vcm * h, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(V[0], vcm, rtol=0, atol=1e-17)
+    assert abs(np.linalg.norm(X[1]) - 1e6) < 1e-6
+
+
+def test_merge_conserves_mass_momentum_volume_in_a_cluster(params):
+    """Six bodies on crossing paths with a negligible central mass: every merger conserves mass,
+    momentum and volume, so over the whole drift the totals stay fixed, the centre of mass moves
+    uniformly, and the log names each removed body once, always a higher index than its
+    survivor."""
+    p = dict(params, m0=1e-30)
+    rng = np.random.default_rng(7)
+    k = 6
+    x = 1.0 + 2e-3 * rng.standard_normal((k, 3))
+    v = 0.02 * rng.standard_normal((k, 3))
+    v -= v.mean(0)
+    v += x.mean(0) - x                           # converging flow: several contacts
+    m = rng.uniform(1e-6, 4e-6, k)
+    R = rng.uniform(2e-4, 4e-4, k)
+    rc = np.full(k, 0.2)
+    h = 0.05
+    X, V, M, RR, st, stats, mg, mt = oracle.drift_groups_merge(x, v, m, rc, R, 1.0, np.zeros(k), p, h)
+    assert st == 0 and len(mg) >= 2
+    assert (mg[:, 1] < mg[:, 2]).all() and len(set(mg[:, 2])) == len(mg)
+    assert (np.diff(mt) >= 0).all() and mt[-1] <= h
+    alive = M > 0
+    assert alive.sum() == k - len(mg)
+    assert abs(M.sum() - m.sum()) < 1e-15 * m.sum()
+    assert abs((RR ** 3).sum() - (R ** 3).sum()) < 1e-14 * (R ** 3).sum()
+    P0 = (m[:, None] * v).sum(0); P1 = (M[:, None] * V).sum(0)
+    np.testing.assert_allclose(P1, P0, rtol=0, atol=1e-15 * np.abs(m[:, None] * v).sum())
+    xcm0 = (m[:, None] * x).sum(0) / m.sum(); xcm1 = (M[alive, None] * X[alive]).sum(0) / M.sum()
+    np.testing.assert_allclose(xcm1, xcm0 + P0 / m.sum() * h, rtol=0, atol=1e-14)
+    assert np.all(np.abs(np.linalg.norm(X[~alive], axis=1) - 1e6) < 1e-6)
+
+
+def test_merge_step_without_contacts_equals_hybrid_step(params, disk2048_groups):
+    """With f = 0 nothing can touch: the merging step is the hybrid step bit for bit."""
+    d, thr, _ = disk2048_groups
+    R = d["radius"]
+    a = oracle.step_merge(d["x"], d["v"], d["m"], R, 0.0, params, 3, thr=thr)
+    b = oracle.step_hybrid(d["x"], d["v"], d["m"], params, 3, thr=thr)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], d["m"])
+    assert len(a[6]) == 0
