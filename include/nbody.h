@@ -138,6 +138,35 @@ int nbody_encounter_groups(nbody_ctx *ctx, int64_t n, const int32_t *pairs, int6
                            const int64_t *count, int32_t *labels, int64_t *out, void *stream);
 
 /*
+ * Collisions as perfect mergers (the outcomes of collisions, in the paper's section on further
+ * physics, with the radius factor f of its section on the acceleration factor), applied inside the
+ * close-encounter drift. Two bodies of a group are in contact when their distance falls below
+ * f (R_i + R_j). The drift finds the first contact time (the first integrator step that ends in
+ * contact, then bisection on that step's length) and merges the pair there: the lower body index
+ * keeps the summed mass, the summed volume (R^3 = R_i^3 + R_j^3) and the centre-of-mass position
+ * and velocity; the other body becomes massless with zero radius and is parked on a circular
+ * orbit of radius 1e6 about the central mass at the angle 2 pi j/n, where it meets nothing (callers
+ * may drop such bodies between calls). Contacts are looked for only within groups: with rc far above
+ * f R a colliding pair is a close pair at the start of the step.
+ *   radius  device double [n]: physical radii, in/out (merged bodies updated, removed ones 0).
+ *   f       radius factor, finite and >= 0 (0: no contact is possible).
+ *   merges  device int32 [cap][3]: {step within the call, survivor, removed} per merger, in no
+ *           particular order; time: device double [cap], the time of each merger within its step's
+ *           drift. Both may be NULL when cap is 0.
+ *   count   device int64: number of mergers in the call (set to 0 first; may exceed cap, in which
+ *           case only cap are logged).
+ * Ownership stays with the caller; all pointers are device pointers.
+ */
+typedef struct nbody_collisions {
+  double *radius;
+  double f;
+  int32_t *merges;
+  double *time;
+  int64_t cap;
+  int64_t *count;
+} nbody_collisions;
+
+/*
  * Close-encounter drift: H_A in full (eq. Ha, both lines) over time h. The bodies of every
  * close-encounter group (labels as written by nbody_encounter_groups: the smallest index of each
  * body's group) move under the equations of motion of H_A restricted to their group,
@@ -147,23 +176,28 @@ int nbody_encounter_groups(nbody_ctx *ctx, int64_t n, const int32_t *pairs, int6
  * group's largest position and velocity), one workgroup of four waves per group (the waves run
  * the extrapolation's midpoint sweeps side by side); a body alone in its group follows its Kepler
  * orbit (as nbody_drift). thr as from nbody_rcrit (rc_i sets the changeover).
+ * col (may be NULL): collisions as perfect mergers within the groups (see nbody_collisions).
  * stats (device int64 [6]) receives: [0] groups integrated, [1] largest group, [2] bodies in
  * groups, [3] groups of more than 64 bodies (moved on Kepler orbits only: the result is then not
- * the H_A flow), [4] groups whose integration did not finish, [5] (nbody_step_hybrid only)
- * encounter lists that exceeded the internal capacity of max(16 n, 65536) pairs.
+ * the H_A flow, and no contacts are found in them), [4] groups whose integration did not finish,
+ * [5] (nbody_step_hybrid only) encounter lists that exceeded the internal capacity of
+ * max(16 n, 65536) pairs.
  */
 int nbody_drift_groups(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr,
-                       const int32_t *labels, double h, int64_t *stats, void *stream);
+                       const int32_t *labels, double h, const nbody_collisions *col, int64_t *stats,
+                       void *stream);
 
 /*
  * Hybrid step: as nbody_step (B(dt/2) C(dt/2) A(dt) C(dt/2) B(dt/2), thresholds fixed for the
  * call, merged half kicks), but the drift A integrates H_A in full: the close pairs found by each
  * kick's pair loop form the close-encounter groups of the drift that follows, integrated as in
  * nbody_drift_groups. The step then conserves the full energy E instead of the K-weighted E'.
- * stats as for nbody_drift_groups, summed over the steps (stats[1] the maximum). Binary64 only.
+ * col (may be NULL): collisions as perfect mergers in every step's drift (merged masses take part
+ * in the kicks that follow; rc stays fixed for the call). stats as for nbody_drift_groups, summed
+ * over the steps (stats[1] the maximum). Binary64 only.
  */
 int nbody_step_hybrid(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr,
-                      int32_t nsteps, int64_t *stats, void *stream);
+                      int32_t nsteps, const nbody_collisions *col, int64_t *stats, void *stream);
 
 /*
  * Input check before integrating a state. The method has no softening, so a body at the central

@@ -32,6 +32,12 @@ class _Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Collisions(ctypes.Structure):
+    """nbody_collisions: collisions as perfect mergers in the close-encounter drift."""
+    _fields_ = [("radius", ctypes.c_void_p), ("f", ctypes.c_double), ("merges", ctypes.c_void_p),
+                ("time", ctypes.c_void_p), ("cap", ctypes.c_int64), ("count", ctypes.c_void_p)]
+
+
 @dataclasses.dataclass
 class Params:
     G: float = 1.0
@@ -61,8 +67,8 @@ EXPORTS = {
     "nbody_step": [_I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P],
     "nbody_validate": [_I64, _P, _P, _P, _P],
     "nbody_encounter_groups": [_I64, _P, _I64, _P, _P, _P, _P],
-    "nbody_drift_groups": [_I64, _P, _P, _P, _P, _D, _P, _P],
-    "nbody_step_hybrid": [_I64, _P, _P, _P, _I32, _P, _P],
+    "nbody_drift_groups": [_I64, _P, _P, _P, _P, _D, _P, _P, _P],
+    "nbody_step_hybrid": [_I64, _P, _P, _P, _I32, _P, _P, _P],
     "nbody_energy": [_I64, _P, _P, _P, _P, _P],
     "nbody_bench_pairs": [_I64, _P, _P, _I32, _P, _P],
     "nbody_kick_vjp": [_I64, _P, _P, _D, _P, _P, _P],
@@ -241,24 +247,54 @@ class Context:
 
     _CE_STATS = ("groups", "largest", "bodies", "too_large", "unfinished", "list_overflows")
 
-    def drift_groups(self, xm, v, thr, labels, h):
-        """Close-encounter drift (H_A in full) over h with the given group labels; returns the
-        statistics as a dict."""
-        _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
-        stats = torch.zeros(6, dtype=torch.int64, device=xm.device)
-        self._check(lib().nbody_drift_groups(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr),
-                                             _ptr(labels.contiguous()), float(h), _ptr(stats), _stream()),
-                    "nbody_drift_groups")
-        return dict(zip(self._CE_STATS, stats.cpu().tolist()))
+    @staticmethod
+    def _collisions(radius, f, cap, device):
+        """The nbody_collisions block for radius (or None) and its log buffers."""
+        if radius is None:
+            return None, None
+        if radius.dtype != torch.float64 or not radius.is_contiguous():
+            raise NBodyError("radius must be a contiguous float64 tensor")
+        log = {"merges": torch.zeros((max(cap, 1), 3), dtype=torch.int32, device=device),
+               "time": torch.zeros(max(cap, 1), dtype=torch.float64, device=device),
+               "count": torch.zeros(1, dtype=torch.int64, device=device)}
+        col = Collisions(_ptr(radius), float(f), _ptr(log["merges"]), _ptr(log["time"]), int(cap),
+                         _ptr(log["count"]))
+        return col, log
 
-    def step_hybrid(self, xm, v, nsteps, thr=None):
-        """nsteps hybrid steps in place (close-encounter groups integrated in the drift); returns
-        the statistics as a dict."""
+    def _ce_result(self, stats, log):
+        out = dict(zip(self._CE_STATS, stats.cpu().tolist()))
+        if log is not None:
+            cnt = int(log["count"].item())
+            k = min(cnt, log["merges"].shape[0])
+            out["mergers"] = cnt
+            out["merges"] = log["merges"][:k].cpu().numpy()
+            out["merge_times"] = log["time"][:k].cpu().numpy()
+        return out
+
+    def drift_groups(self, xm, v, thr, labels, h, radius=None, f=1.0, cap=4096):
+        """Close-encounter drift (H_A in full) over h with the given group labels; with radius
+        (float64 [n], in/out), bodies of a group closer than f (R_i + R_j) merge. Returns the
+        statistics as a dict (with the merger log when colliding)."""
         _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
         stats = torch.zeros(6, dtype=torch.int64, device=xm.device)
+        col, log = self._collisions(radius, f, cap, xm.device)
+        self._check(lib().nbody_drift_groups(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr),
+                                             _ptr(labels.contiguous()), float(h),
+                                             ctypes.byref(col) if col else None, _ptr(stats), _stream()),
+                    "nbody_drift_groups")
+        return self._ce_result(stats, log)
+
+    def step_hybrid(self, xm, v, nsteps, thr=None, radius=None, f=1.0, cap=4096):
+        """nsteps hybrid steps in place (close-encounter groups integrated in the drift); with
+        radius (float64 [n], in/out), collisions merge bodies. Returns the statistics as a dict
+        (with the merger log when colliding)."""
+        _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
+        stats = torch.zeros(6, dtype=torch.int64, device=xm.device)
+        col, log = self._collisions(radius, f, cap, xm.device)
         self._check(lib().nbody_step_hybrid(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr), int(nsteps),
-                                            _ptr(stats), _stream()), "nbody_step_hybrid")
-        return dict(zip(self._CE_STATS, stats.cpu().tolist()))
+                                            ctypes.byref(col) if col else None, _ptr(stats), _stream()),
+                    "nbody_step_hybrid")
+        return self._ce_result(stats, log)
 
     def validate(self, xm, v):
         """(index, reason) of the first invalid body, or (-1, 0); reasons: 1 non-finite value,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -12,6 +13,7 @@
 #include <vector>
 
 #include "../../include/nbody.h"
+
 #include "internal.hpp"
 
 using namespace nbk;
@@ -306,15 +308,36 @@ int group_bufs(nbody_ctx *c, int n, GroupBufs &g) {
   return NBODY_OK;
 }
 
+// Checks the collision arguments and fills the kernel's view of them (radius null: no collisions).
+int collide_args(nbody_ctx *c, int n, const nbody_collisions *col, CeCollide &cc) {
+  cc = CeCollide{nullptr, 0.0, nullptr, nullptr, 0, nullptr, 0, n};
+  if (!col) return NBODY_OK;
+  TRY(check_dev(c, col->radius, "col->radius", true));
+  TRY(check_dev(c, col->count, "col->count", true));
+  if (!(col->f >= 0.0) || !std::isfinite(col->f)) return fail(c, NBODY_E_INVAL, "col->f must be finite and >= 0");
+  if (col->cap < 0) return fail(c, NBODY_E_INVAL, "col->cap < 0");
+  if (col->cap > 0) {
+    TRY(check_dev(c, col->merges, "col->merges", true));
+    TRY(check_dev(c, col->time, "col->time", true));
+  }
+  cc.radius = col->radius;
+  cc.f = col->f;
+  cc.merges = col->merges;
+  cc.mtime = col->time;
+  cc.cap = col->cap;
+  cc.count = (unsigned long long *)col->count;
+  return NBODY_OK;
+}
+
 // Member lists of the groups given by labels; then the close-encounter integration of every group
 // over h (the other bodies are not touched here).
 int ce_drift(nbody_ctx *c, int n, double4 *xm, double4 *v, const double4 *thr, const int *labels,
-             const GroupBufs &g, double h, unsigned long long *stats, hipStream_t st) {
+             const GroupBufs &g, double h, unsigned long long *stats, const CeCollide &col, hipStream_t st) {
   HIPCHK(c, launch_group_lists(labels, n, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
                                g.counter, st), "group lists");
   const nbody_params &p = c->p;
   HIPCHK(c, launch_ce_drift(xm, v, thr, g.gmem, g.gstart, g.gsize, g.groot, g.counter, n / 2 + 1, p.G, p.m0,
-                            p.f_in, h, kCeTol, stats, st), "close-encounter drift");
+                            p.f_in, h, kCeTol, stats, col, st), "close-encounter drift");
   return NBODY_OK;
 }
 
@@ -521,26 +544,29 @@ int nbody_encounter_groups(nbody_ctx *c, int64_t n, const int32_t *pairs, int64_
 }
 
 int nbody_drift_groups(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr, const int32_t *labels,
-                       double h, int64_t *stats, void *stream) {
+                       double h, const nbody_collisions *col, int64_t *stats, void *stream) {
   TRY(check_n(c, n));
   TRY(check_dev(c, xm, "xm", true));
   TRY(check_dev(c, v, "v", true));
   TRY(check_dev(c, thr, "thr", true));
   TRY(check_dev(c, labels, "labels", true));
   TRY(check_dev(c, stats, "stats", true));
+  CeCollide cc;
+  TRY(collide_args(c, (int)n, col, cc));
   hipStream_t st = (hipStream_t)stream;
   GroupBufs g;
   TRY(group_bufs(c, (int)n, g));
   HIPCHK(c, hipMemsetAsync(stats, 0, 6 * sizeof(int64_t), st), "memset");
+  if (cc.count) HIPCHK(c, hipMemsetAsync(cc.count, 0, sizeof(int64_t), st), "memset");
   TRY(ce_drift(c, (int)n, (double4 *)xm, (double4 *)v, (const double4 *)thr, labels, g, h,
-               (unsigned long long *)stats, st));
+               (unsigned long long *)stats, cc, st));
   // bodies in no group: Kepler orbits (g.in marks the group members)
   HIPCHK(c, launch_drift((double4 *)xm, (double4 *)v, (int)n, h, c->p.G * c->p.m0, nullptr, st, g.in), "drift");
   return NBODY_OK;
 }
 
 int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr, int32_t nsteps,
-                      int64_t *stats, void *stream) {
+                      const nbody_collisions *col, int64_t *stats, void *stream) {
   TRY(check_n(c, n));
   TRY(check_dev(c, xm, "xm", true));
   TRY(check_dev(c, v, "v", true));
@@ -548,8 +574,11 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   TRY(check_dev(c, stats, "stats", true));
   if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
   if (c->p.precision != NBODY_PREC_F64) return fail(c, NBODY_E_INVAL, "the hybrid step runs in binary64");
+  CeCollide cc;
+  TRY(collide_args(c, (int)n, col, cc));
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(c, hipMemsetAsync(stats, 0, 6 * sizeof(int64_t), st), "memset");
+  if (cc.count) HIPCHK(c, hipMemsetAsync(cc.count, 0, sizeof(int64_t), st), "memset");
   if (nsteps == 0) return NBODY_OK;
   const nbody_params &p = c->p;
   const int N = (int)n;
@@ -600,8 +629,11 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     // first jump for all; Kepler drift for the bodies in no group
     HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
                                 g.in), "jump+drift");
+    cc.step = s - 1;
     HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
-                              p.f_in, p.dt, kCeTol, S, st), "close-encounter drift");
+                              p.f_in, p.dt, kCeTol, S, cc, st), "close-encounter drift");
+    // mergers change masses: the equal-mass flag of the pair kernel is taken again
+    if (cc.radius) TRY(mass_check(c, N, X, st, &a.uni));
     HIPCHK(c, launch_momentum(X, Vv, N, momB, st), "momentum");
     HIPCHK(c, launch_jump(X, momB, nbf, N, h, p.m0, st), "jump");
     if (a.perm && s % c->locality_every == 0) TRY(locality(c, N, X, st, &a.perm));

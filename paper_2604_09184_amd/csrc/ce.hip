@@ -107,6 +107,8 @@ __global__ __launch_bounds__(kBlock) void k_gfill(const int *__restrict__ label,
 // groups thus spread their pair sums over the whole wave.
 constexpr int kCeWaves = 4;
 constexpr int kMaxMacroSteps = 20000;
+constexpr int kMaxBisections = 80;       // contact-time bisection: at most 80 halvings of a step
+constexpr double kParkRadius = 1e6;      // orbit radius of bodies merged away
 
 __device__ __forceinline__ double wave_max_d(double x) {
 #pragma unroll
@@ -131,15 +133,16 @@ __device__ __forceinline__ double ce_recip(double d) {
   return x;
 }
 
-// Per-member constants in ascending body order: G m, rc, 1/((1 - f_in) rc).
+// Per-member values in ascending body order: G m, rc, 1/((1 - f_in) rc) and the contact radius
+// f R (G m and f R change when members merge).
 struct CeMember {
-  double Gm, rc, ispan, pad;
+  double Gm, rc, ispan, fR;
 };
 
 // A lane's partners: for iteration it the member q = rep + it P (in ascending body order), the lane
 // src of its first replica, and whether the term counts (a member, and not the lane's own body).
 struct CePartner {
-  int src;
+  int src, q;
   bool use;
   CeMember m;
 };
@@ -149,6 +152,7 @@ __device__ __forceinline__ CePartner ce_partner(int q, int k, bool act, int slot
   const bool valid = q < k;
   const int qq = valid ? q : 0;
   CePartner p;
+  p.q = q;
   p.src = owner[qq] * P;
   p.use = act && valid && owner[qq] != slot;
   p.m = mem[qq];
@@ -201,7 +205,8 @@ __device__ __forceinline__ void ce_row_add(double &a0, double &a1, double &a2) {
 constexpr int kCeRegPartners = 4;
 
 // f = (v, a) of this lane's body at the state z.
-__device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, bool act, int iters, int P,
+__device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, bool act, bool alive, int iters,
+                                       int P,
                                        int rep, int slot, const int *owner, const CeMember *mem,
                                        const CePartner (&pr)[kCeRegPartners], double rc,
                                        double ispan, double Gm0, double f_in, double (&f)[6]) {
@@ -227,28 +232,31 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, bool act, in
   const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
   const double ir = ce_rinv(r2);
   const double s = -Gm0 * (ir * ir * ir);
-  f[0] = z[3]; f[1] = z[4]; f[2] = z[5];
-  f[3] = s * z[0] + a0;
-  f[4] = s * z[1] + a1;
-  f[5] = s * z[2] + a2;
+  // a body merged away is held fixed
+  f[0] = alive ? z[3] : 0.0;
+  f[1] = alive ? z[4] : 0.0;
+  f[2] = alive ? z[5] : 0.0;
+  f[3] = alive ? s * z[0] + a0 : 0.0;
+  f[4] = alive ? s * z[1] + a1 : 0.0;
+  f[5] = alive ? s * z[2] + a2 : 0.0;
 }
 
 // Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
 __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, int k, bool act,
-                                         int iters, int P, int rep, int slot, const int *owner,
+                                         bool alive, int iters, int P, int rep, int slot, const int *owner,
                                          const CeMember *mem, const CePartner (&pr)[kCeRegPartners],
                                          double rc, double ispan, double Gm0, double f_in,
                                          double (&est)[6]) {
   const double hs = H / ns;
   double zm[6], zc[6], f[6];
-  ce_rhs(y, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
+  ce_rhs(y, k, act, alive, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
     zc[i] = y[i] + hs * f[i];
   }
   for (int s = 1; s < ns; ++s) {
-    ce_rhs(zc, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
+    ce_rhs(zc, k, act, alive, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const double zn = zm[i] + 2.0 * hs * f[i];
@@ -256,7 +264,7 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
       zc[i] = zn;
     }
   }
-  ce_rhs(zc, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
+  ce_rhs(zc, k, act, alive, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zc[i] + zm[i] + hs * f[i]);
 }
@@ -283,22 +291,153 @@ __device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale
   return out;
 }
 
+// Shared state of one group's integration (LDS): the tableau's end values (double buffered), the
+// slot of each member rank, the member values, and masses, radii and body indices by rank.
+struct CeShared {
+  double est[2][8][6][64];
+  CeMember mem[64];
+  double mass[64], rad[64];
+  int owner[64], body[64];
+};
+
+// Per-lane constants of one group's integration.
+struct CeLane {
+  int k, iters, P, rep, slot, wv, rank;
+  bool act;
+  double rc, ispan, Gm0, f_in, tol;
+};
+
+// One macro-step attempt over H from y (all four waves together): returns the accepted column
+// (identical in every wave) or -1; y1 receives the accepted extrapolant.
+__device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool alive, const CeLane &L,
+                                          CeShared &sh, const CePartner (&pr)[kCeRegPartners],
+                                          int &buf, double (&y1)[6]) {
+  const bool live = L.act && alive;
+  const double sx = wave_max_d(live ? fmax(fabs(y[0]), fmax(fabs(y[1]), fabs(y[2]))) : 0.0);
+  const double sv = wave_max_d(live ? fmax(fabs(y[3]), fmax(fabs(y[4]), fabs(y[5]))) : 0.0);
+  const double isx = 1.0 / sx, isv = 1.0 / sv;
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc) {
+    const int c = cc == 0 ? L.wv : 7 - L.wv;
+    double est[6];
+    ce_sweep(y, H, 2 * c + 2, L.k, L.act, alive, L.iters, L.P, L.rep, L.slot, sh.owner, sh.mem, pr, L.rc,
+             L.ispan, L.Gm0, L.f_in, est);
+    if (L.rep == 0)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) sh.est[buf][c][i][L.slot] = est[i];
+  }
+  __syncthreads();
+  // tableau of every component; the first pass finds the accepted column
+  double err[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double e[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) e[c] = sh.est[buf][c][i][L.slot];
+    (void)ce_tableau(e, i < 3 ? isx : isv, -1, err);
+  }
+  int accepted = -1;
+#pragma unroll
+  for (int c = 2; c < 8; ++c)
+    if (accepted < 0 && __ballot(live && !(err[c] <= L.tol)) == 0) accepted = c;
+  if (accepted >= 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double e[8], dummy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int c = 0; c < 8; ++c) e[c] = sh.est[buf][c][i][L.slot];
+      y1[i] = ce_tableau(e, 1.0, accepted, dummy);
+    }
+  }
+  buf ^= 1;
+  return accepted;
+}
+
+// Lowest (rank_lo, rank_hi) pair of live members closer than f (R_lo + R_hi) at the state y, as
+// rank_lo * 64 + rank_hi, or -1; identical in every lane and wave.
+__device__ __forceinline__ void ce_contact_test(const double (&y)[6], double fR, const CeLane &L,
+                                                const CePartner &p, int &key) {
+  const double dx = __shfl(y[0], p.src, 64) - y[0];
+  const double dy = __shfl(y[1], p.src, 64) - y[1];
+  const double dz = __shfl(y[2], p.src, 64) - y[2];
+  const double lim = fR + p.m.fR;
+  if (p.use && fR > 0.0 && p.m.fR > 0.0 && dx * dx + dy * dy + dz * dz < lim * lim) {
+    const int lo = min(L.rank, p.q), hi = max(L.rank, p.q);
+    key = min(key, lo * 64 + hi);
+  }
+}
+
+__device__ __forceinline__ int ce_contact(const double (&y)[6], double fR, const CeLane &L,
+                                          const CeShared &sh, const CePartner (&pr)[kCeRegPartners]) {
+  int key = 0x7fffffff;
+#pragma unroll
+  for (int u = 0; u < kCeRegPartners; ++u)
+    if (u < L.iters) ce_contact_test(y, fR, L, pr[u], key);
+  for (int it = kCeRegPartners; it < L.iters; ++it)
+    ce_contact_test(y, fR, L,
+                    ce_partner(L.rep + it * L.P, L.k, L.act, L.slot, L.P, sh.owner, sh.mem), key);
+  if (__ballot(key != 0x7fffffff) == 0) return -1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) key = min(key, __shfl_xor(key, o, 64));
+  return key;
+}
+
+// Adaptive integration of y over the time Ltot (macro steps from H = Ltot; halved when rejected,
+// 4 H after acceptance at column <= 3, 2 H at column 4). With check, every accepted step is
+// followed by a contact test and the integration stops at the first step that ends in contact: y
+// then holds that step's start, done the time covered before it and Hc its length. Returns 0
+// (covered), 1 (contact) or 2 (H halved 60 times in a row, or too many macro steps).
+__device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool check, bool alive,
+                                          double fR, const CeLane &L, CeShared &sh,
+                                          const CePartner (&pr)[kCeRegPartners], int &buf,
+                                          double &done, double &Hc) {
+  double t = 0.0, H = Ltot;
+  int halvings = 0, macro = 0;
+  while (fabs(Ltot - t) > 0.0) {
+    if (++macro > kMaxMacroSteps) return 2;
+    if (fabs(H) > fabs(Ltot - t)) H = Ltot - t;
+    double y1[6];
+    const int c = ce_attempt(y, H, alive, L, sh, pr, buf, y1);
+    if (c < 0) {
+      H = H / 2.0;
+      if (++halvings > 60) return 2;
+      continue;
+    }
+    halvings = 0;
+    if (check && ce_contact(y1, fR, L, sh, pr) >= 0) {
+      done = t;
+      Hc = H;
+      return 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) y[i] = y1[i];
+    if (t + H == t) break;   // the remaining interval is below the resolution of t
+    t = t + H;
+    if (c <= 3) H = H * 4.0;
+    else if (c == 4) H = H * 2.0;
+  }
+  return 0;
+}
+
 // stats (device uint64 [6]): [0] groups integrated, [1] largest group, [2] bodies in groups, [3]
 // groups above 64 bodies (drifted on Kepler orbits only), [4] groups whose integration did not
 // finish (step halved 60 times in a row, or too many macro steps).
 //
-// Step control: a macro step is accepted at the first column c >= 2 whose last two extrapolants
-// agree to tol (|T[c][c] - T[c][c-1]|, relative to the group's largest |x| and |v|); after
-// acceptance at c <= 3 the next H is 4 H, at c = 4 it is 2 H, otherwise H; a rejected step is
-// halved.
+// Collisions (col.radius not null): two live members are in contact when their distance is below
+// f (R_i + R_j). The integration stops at the first accepted step that ends in contact, the first
+// contact time inside that step is found by bisection on the step length (each trial integrating
+// from the step's start; at most kMaxBisections halvings, fewer when the interval can no longer be
+// split), and the contact pair of lowest member ranks merges there: the lower body index keeps
+// the summed mass, the summed volume and the centre-of-mass position and velocity; the other
+// becomes massless, of zero radius, parked on a circular orbit of radius kParkRadius about the
+// central mass at the angle 2 pi j/n, and is held fixed for the rest of the drift. Each merger is
+// logged as {step, survivor, removed} with its time within the drift.
 __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
     const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
     const int *__restrict__ groot, const int *__restrict__ ngroups, double G, double m0,
-    double f_in, double h, double tol, unsigned long long *__restrict__ stats) {
-  __shared__ double est_s[2][8][6][64];
-  __shared__ int owner[64];
-  __shared__ CeMember mem[64];
+    double f_in, double h, double tol, unsigned long long *__restrict__ stats, CeCollide col) {
+  __shared__ CeShared sh;
   const int w = blockIdx.x;
   if (w >= *ngroups) return;
   const int r = groot[w];
@@ -317,85 +456,138 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     if (threadIdx.x == 0) atomicAdd(stats + 3, 1ull);
     return;
   }
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  CeLane L;
+  L.k = k;
+  L.wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   int kp = 1;
   while (kp < k) kp <<= 1;
-  const int P = min(64 / kp, 16);
-  const int slot = lane / P, rep = lane & (P - 1);
-  const int iters = (k + P - 1) / P;
-  const bool act = slot < k;
-  const int b = gmem[base + (act ? slot : 0)];
+  L.P = min(64 / kp, 16);
+  L.slot = lane / L.P;
+  L.rep = lane & (L.P - 1);
+  L.iters = (k + L.P - 1) / L.P;
+  L.act = L.slot < k;
+  L.Gm0 = Gm0;
+  L.f_in = f_in;
+  L.tol = tol;
+  const int b = gmem[base + (L.act ? L.slot : 0)];
   const double4 p0 = xm[b], u0 = v[b];
-  const double rc = thr[b].x;
-  const double ispan = 1.0 / ((1.0 - f_in) * rc);
-  if (wv == 0 && rep == 0 && act) {
-    int rank = 0;
-    for (int q = 0; q < k; ++q) rank += gmem[base + q] < b;
-    owner[rank] = slot;
-    mem[rank] = CeMember{G * p0.w, rc, ispan, 0.0};
+  L.rc = thr[b].x;
+  L.ispan = 1.0 / ((1.0 - f_in) * L.rc);
+  L.rank = 0;
+  for (int q = 0; q < k; ++q) L.rank += gmem[base + q] < b;
+  const bool collide = col.radius != nullptr;
+  const double R0 = collide ? col.radius[b] : 0.0;
+  if (L.wv == 0 && L.rep == 0 && L.act) {
+    sh.owner[L.rank] = L.slot;
+    sh.body[L.rank] = b;
+    sh.mass[L.rank] = p0.w;
+    sh.rad[L.rank] = R0;
+    sh.mem[L.rank] = CeMember{G * p0.w, L.rc, L.ispan, col.f * R0};
   }
   __syncthreads();
   CePartner pr[kCeRegPartners];
 #pragma unroll
   for (int u = 0; u < kCeRegPartners; ++u)
-    pr[u] = ce_partner(rep + u * P, k, act, slot, P, owner, mem);
+    pr[u] = ce_partner(L.rep + u * L.P, k, L.act, L.slot, L.P, sh.owner, sh.mem);
+  bool alive = true;
+  double fR = col.f * R0;
   double y[6] = {p0.x, p0.y, p0.z, u0.x, u0.y, u0.z};
-  double t = 0.0, H = h;
-  int halvings = 0, macro = 0, status = 0, buf = 0;
-  while (fabs(h - t) > 0.0) {
-    if (++macro > kMaxMacroSteps) { status = 1; break; }
-    if (fabs(H) > fabs(h - t)) H = h - t;
-    const double sx = wave_max_d(act ? fmax(fabs(y[0]), fmax(fabs(y[1]), fabs(y[2]))) : 0.0);
-    const double sv = wave_max_d(act ? fmax(fabs(y[3]), fmax(fabs(y[4]), fabs(y[5]))) : 0.0);
-    const double isx = 1.0 / sx, isv = 1.0 / sv;
+  double y0[6] = {0, 0, 0, 0, 0, 0};
+  int status = 0, buf = 0, phase = 0, bis = 0;
+  double t = 0.0, lo = 0.0, hi = 0.0, mid = 0.0;
+  // phase 0: integrate the rest of the drift (with contact tests when colliding); phase 1: a
+  // bisection trial from y0 over mid; phase 2: from y0 to the contact time hi, then merge
+  while (true) {
+    double L_int = h - t;
+    if (phase != 0) {
 #pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-      const int c = cc == 0 ? wv : 7 - wv;
-      double est[6];
-      ce_sweep(y, H, 2 * c + 2, k, act, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in,
-               est);
-      if (rep == 0)
-#pragma unroll
-        for (int i = 0; i < 6; ++i) est_s[buf][c][i][slot] = est[i];
+      for (int i = 0; i < 6; ++i) y[i] = y0[i];
+      L_int = phase == 1 ? mid : hi;
     }
-    __syncthreads();
-    // tableau of every component; the first pass finds the accepted column
-    double err[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double done = 0.0, Hc = 0.0;
+    const int st = ce_advance(y, L_int, collide && phase == 0, alive, fR, L, sh, pr, buf, done, Hc);
+    if (st == 2) { status = 1; break; }
+    if (phase == 0) {
+      if (st == 0) break;
+      t = t + done;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      double e[8];
+      for (int i = 0; i < 6; ++i) y0[i] = y[i];
+      lo = 0.0;
+      hi = Hc;
+      bis = 0;
+    } else if (phase == 1) {
+      if (ce_contact(y, fR, L, sh, pr) >= 0) hi = mid; else lo = mid;
+      ++bis;
+    } else {
+      t = t + hi;
+      const int key = ce_contact(y, fR, L, sh, pr);
+      if (key >= 0) {
+        const int ra = key >> 6, rb = key & 63;
+        const int sa = sh.owner[ra] * L.P, sb = sh.owner[rb] * L.P;
+        const double ma = sh.mass[ra], mb = sh.mass[rb];
+        const double M = ma + mb;
+        double ya[6], yb[6];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) e[c] = est_s[buf][c][i][slot];
-      (void)ce_tableau(e, i < 3 ? isx : isv, -1, err);
-    }
-    int accepted = -1;
+        for (int i = 0; i < 6; ++i) {
+          ya[i] = __shfl(y[i], sa, 64);
+          yb[i] = __shfl(y[i], sb, 64);
+        }
+        const double Ra = sh.rad[ra], Rb = sh.rad[rb];
+        const double Rm = cbrt(Ra * Ra * Ra + Rb * Rb * Rb);
+        const int ba = sh.body[ra], bb = sh.body[rb];
+        if (L.rank == ra && L.act) {
 #pragma unroll
-    for (int c = 2; c < 8; ++c)
-      if (accepted < 0 && __ballot(act && !(err[c] <= tol)) == 0) accepted = c;
-    if (accepted < 0) {
-      buf ^= 1;
-      H = H / 2.0;
-      if (++halvings > 60) { status = 1; break; }
+          for (int i = 0; i < 6; ++i) y[i] = (ma * ya[i] + mb * yb[i]) / M;
+          fR = col.f * Rm;
+        }
+        if (L.rank == rb && L.act) {
+          const double th = 2.0 * M_PI * (double)bb / (double)col.n;
+          const double vc = sqrt(Gm0 / kParkRadius);
+          y[0] = kParkRadius * cos(th);
+          y[1] = kParkRadius * sin(th);
+          y[2] = 0.0;
+          y[3] = -vc * sin(th);
+          y[4] = vc * cos(th);
+          y[5] = 0.0;
+          alive = false;
+          fR = 0.0;
+        }
+        __syncthreads();   // every wave is past its last read of the member values
+        if (threadIdx.x == 0) {
+          sh.mass[ra] = M;
+          sh.mass[rb] = 0.0;
+          sh.rad[ra] = Rm;
+          sh.rad[rb] = 0.0;
+          sh.mem[ra].Gm = G * M;
+          sh.mem[ra].fR = col.f * Rm;
+          sh.mem[rb].Gm = 0.0;
+          sh.mem[rb].fR = 0.0;
+          const unsigned long long e = atomicAdd(col.count, 1ull);
+          if (e < (unsigned long long)col.cap) {
+            col.merges[3 * e] = col.step;
+            col.merges[3 * e + 1] = ba;
+            col.merges[3 * e + 2] = bb;
+            col.mtime[e] = t;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kCeRegPartners; ++u)
+          pr[u] = ce_partner(L.rep + u * L.P, k, L.act, L.slot, L.P, sh.owner, sh.mem);
+      }
+      phase = 0;
+      if (!(fabs(h - t) > 0.0)) break;
       continue;
     }
-    halvings = 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      double e[8], dummy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int c = 0; c < 8; ++c) e[c] = est_s[buf][c][i][slot];
-      y[i] = ce_tableau(e, 1.0, accepted, dummy);
-    }
-    buf ^= 1;
-    if (t + H == t) break;   // the remaining interval is below the resolution of t
-    t = t + H;
-    if (accepted <= 3) H = H * 4.0;
-    else if (accepted == 4) H = H * 2.0;
+    // next bisection trial, or the final advance to the contact time
+    mid = 0.5 * (lo + hi);
+    phase = (bis < kMaxBisections && mid > lo && mid < hi) ? 1 : 2;
   }
-  if (wv == 0 && rep == 0 && act) {
-    xm[b] = make_double4(y[0], y[1], y[2], p0.w);
+  if (L.wv == 0 && L.rep == 0 && L.act) {
+    xm[b] = make_double4(y[0], y[1], y[2], sh.mass[L.rank]);
     v[b] = make_double4(y[3], y[4], y[5], u0.w);
+    if (collide) col.radius[b] = sh.rad[L.rank];
   }
   if (threadIdx.x == 0) {
     atomicAdd(stats + 0, 1ull);
@@ -432,11 +624,12 @@ hipError_t launch_group_lists(const int *label, int n, int *mark, int *in, int *
 hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
                            const int *gstart, const int *gsize, const int *groot,
                            const int *ngroups, int max_groups, double G, double m0, double f_in,
-                           double h, double tol, unsigned long long *stats, hipStream_t st) {
+                           double h, double tol, unsigned long long *stats, const CeCollide &col,
+                           hipStream_t st) {
   if (max_groups > 0)
     hipLaunchKernelGGL(k_ce_drift, dim3(max_groups), dim3(64 * kCeWaves), 0, st, xm, v, thr, gmem,
                        gstart, gsize,
-                       groot, ngroups, G, m0, f_in, h, tol, stats);
+                       groot, ngroups, G, m0, f_in, h, tol, stats, col);
   return hipGetLastError();
 }
 

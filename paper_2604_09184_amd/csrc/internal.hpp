@@ -60,10 +60,25 @@ hipError_t launch_group_lists(const int *label, int n, int *mark, int *in, int *
                               int *gfill, int *gmem, int *groot, int *counter, hipStream_t st);
 hipError_t launch_list_overflow(const int64_t *count, int64_t cap, unsigned long long *stats,
                                 hipStream_t st);
+// Collisions inside the close-encounter drift: radius null = none. Mergers are appended to
+// merges [cap][3] = {step, survivor, removed} and mtime [cap] (time within the drift); count is
+// incremented once per merger, also beyond cap.
+struct CeCollide {
+  double *radius;
+  double f;
+  int32_t *merges;
+  double *mtime;
+  int64_t cap;
+  unsigned long long *count;
+  int step;
+  int n;
+};
+
 hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
                            const int *gstart, const int *gsize, const int *groot,
                            const int *ngroups, int max_groups, double G, double m0, double f_in,
-                           double h, double tol, unsigned long long *stats, hipStream_t st);
+                           double h, double tol, unsigned long long *stats, const CeCollide &col,
+                           hipStream_t st);
 
 // adjoint.hip
 hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double2 *uni,
