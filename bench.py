@@ -169,7 +169,8 @@ def variant_adjoint(nb, p):
 
 def variant_hybrid(nb, p):
     """Hybrid step (close-encounter groups integrated in full in the drift) against the plain step on
-    the 2048-body disk, 100 steps each: time and the drift of the full energy E and of E'."""
+    the 2048-body disk, 100 steps each: time and the drift of the full energy E and of E'; then the
+    hybrid step with collisions as perfect mergers (f = 300)."""
     import torch
 
     import diskgen
@@ -193,6 +194,15 @@ def variant_hybrid(nb, p):
                      "Eprime_rel_drift": float(abs(e1["Eprime"] - e0["Eprime"]) / abs(e0["Eprime"]))}
         if name == "hybrid":
             out[name]["groups"] = stats
+    # the same 100 hybrid steps with collisions as perfect mergers at f = 300 (radii from the
+    # bodies' density): time per step and the number of mergers
+    X = torch.tensor(xm, device="cuda:0")
+    V = torch.tensor(v4, device="cuda:0")
+    R = torch.tensor(d["radius"], device="cuda:0")
+    thr = ctx.rcrit(X, V)
+    sec, stats = timed(lambda: ctx.step_hybrid(X, V, 100, thr=thr, radius=R, f=300.0))
+    out["hybrid_merge_f300"] = {"seconds": round(sec, 4), "ms_per_step": round(sec * 10, 4),
+                                "mergers": stats["mergers"], "bodies_left": int((X[:, 3] > 0).sum().item())}
     return out
 
 
