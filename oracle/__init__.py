@@ -52,6 +52,10 @@ def _lib():
         "or_drift_groups": (ctypes.c_int, [I, P, P, P, P, P, P, D, D, P]),
         "or_drift_groups_merge": (ctypes.c_int, [I, P, P, P, P, P, P, D, D, P, P, D, ctypes.c_int, P, P, I, P]),
         "or_step_merge": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P, P, D, P, P, I, P]),
+        "or_level_kick_acc": (None, [I, P, P, P, I, P, ctypes.c_int, P, P]),
+        "or_ce_drift_group_levels": (ctypes.c_int, [P, ctypes.c_int, P, P, P, P, ctypes.c_int, P, D, D]),
+        "or_step_levels": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P, ctypes.c_int, ctypes.c_int,
+                                          P, D, P, P, I, P]),
         "or_jump": (None, [I, P, P, P, P, D]),
         "or_drift": (ctypes.c_int, [I, P, P, P, D, P]),
         "or_drift_q": (ctypes.c_int, [I, P, P, P, D]),
@@ -221,6 +225,46 @@ def step_merge(x, v, m, R, f, p, nsteps, thr=None, tol=1e-18, cap=4096):
     st = _lib().or_step_merge(len(m), _p(x), _p(v), _p(m), _p(_prm(p)), int(nsteps), _p(rc), _p(H), _p(V),
                               float(tol), _p(stats), _p(R), float(f), _p(merges), _p(mtime), cap,
                               ctypes.byref(cnt))
+    mg, mt = _merge_log(merges, mtime, cnt.value)
+    return x, v, m, R, st, tuple(int(s) for s in stats), mg, mt
+
+
+def level_kick_acc(x, m, pairs, rc_levels, level, p):
+    """Acceleration of the level-`level` kick over the listed pairs (rc_levels: [level + 1][n])."""
+    x = _f64(x); m = _f64(m)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    rcl = np.ascontiguousarray(rc_levels, dtype=np.float64)
+    acc = np.empty((len(m), 3))
+    _lib().or_level_kick_acc(len(m), _p(x), _p(m), _p(pr), pr.shape[0], _p(rcl), int(level), _p(_prm(p)), _p(acc))
+    return acc
+
+
+def ce_drift_group_levels(x, v, m, rc_levels, p, idx, h, tol=1e-18):
+    """Close-encounter drift of the group idx with the pair term weighted by prod_l [1 - K_l]
+    (rc_levels: [nl][n]); returns new copies of x, v and the status."""
+    x = _f64(x).copy(); v = _f64(v).copy()
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    rcl = np.ascontiguousarray(np.asarray(rc_levels, dtype=np.float64)[:, idx])
+    st = _lib().or_ce_drift_group_levels(_p(idx), len(idx), _p(x), _p(v), _p(_f64(m)), _p(rcl), rcl.shape[0],
+                                         _p(_prm(p)), float(h), float(tol))
+    return x, v, st
+
+
+def step_levels(x, v, m, p, nsteps, levels, substeps, thr=None, tol=1e-18, R=None, f=0.0, cap=4096):
+    """nsteps hybrid steps whose close-encounter drift runs through `levels` intermediate changeover
+    levels (time steps dt / substeps^l); with R, collisions merge bodies. Returns x, v, m, R,
+    status, stats, merges and their times."""
+    x = _f64(x).copy(); v = _f64(v).copy(); m = _f64(m).copy()
+    R = None if R is None else _f64(R).copy()
+    rc, H, V = (None, None, None) if thr is None else (_f64(t) for t in thr)
+    stats = np.zeros(3, dtype=np.int64)
+    merges = np.zeros((cap, 3), dtype=np.int32); mtime = np.zeros(cap)
+    cnt = ctypes.c_int64(0)
+    st = _lib().or_step_levels(len(m), _p(x), _p(v), _p(m), _p(_prm(p)), int(nsteps), _p(rc), _p(H), _p(V),
+                               float(tol), _p(stats), int(levels), int(substeps), _p(R), float(f), _p(merges),
+                               _p(mtime), cap, ctypes.byref(cnt))
+    if st < 0:
+        raise ValueError("levels must be 0..4 and substeps >= 1")
     mg, mt = _merge_log(merges, mtime, cnt.value)
     return x, v, m, R, st, tuple(int(s) for s in stats), mg, mt
 

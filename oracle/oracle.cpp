@@ -131,7 +131,9 @@ template <> struct Acc<double> {
 };
 
 // ---------------------------------------------------------------- parameters
-struct Params { double G, m0, dt, n1, n2, f_in; };
+// nl: number of changeover levels whose [1 - K_l] factors weight the close-encounter pair term
+// (1 without intermediate levels).
+struct Params { double G, m0, dt, n1, n2, f_in; int nl = 1; };
 
 // ---------------------------------------------------------------- critical radius (eq. rcrit)
 // Per body: rc_i (used by the changeover), and the exact-predicate thresholds H_i, V_i.
@@ -406,10 +408,32 @@ static int64_t groups_bfs(int64_t n, const int32_t *pairs, int64_t npairs, int32
 // with d_ij = x_j - x_i: the pair term is minus the gradient of the [1 - K] part of the pair
 // potential, the complement of the kick's weight, and vanishes for r >= rc_ij. Bodies in no group
 // keep the Kepler drift.
+// Product of the changeover complements of the levels 0..nl-1 for a pair at distance q,
+// W = prod_l (1 - K_l(q)), and dW/dq; rcs[l] = rc_l,ij of level l.
+template <class T>
+static void level_weight(T q, const double *rcs, int nl, const Params &p, T *W, T *dW) {
+  T w = T(1), dw = T(0);
+  for (int l = 0; l < nl; l++) {
+    const T span = T((1.0 - p.f_in) * rcs[l]);
+    T K, dKdy;
+    changeover((q - T(p.f_in * rcs[l])) / span, &K, &dKdy);
+    const T dK = dKdy / span;
+    dw = dw * (T(1) - K) - w * dK;
+    w = w * (T(1) - K);
+  }
+  *W = w;
+  *dW = dw;
+}
+
+// The equations of motion of a group under H_A: Kepler about the central mass plus the pair term
+// of the potential -G m_i m_j W(r)/r, W = prod over the levels of [1 - K_l] (one level without
+// intermediate levels: the [1 - K] part). rc holds the members' critical radii level by level
+// ([nl][k]).
 template <class T>
 static void ce_rhs(int k, const T *y, const double *m, const double *rc, const bool *alive, const Params &p,
                    T *f) {
   const T *x = y, *v = y + 3 * k;
+  double rcs[8];
   for (int i = 0; i < k; i++) {
     if (!alive[i]) {           // a body merged away is held fixed
       for (int l = 0; l < 3; l++) f[3 * i + l] = f[3 * k + 3 * i + l] = T(0);
@@ -424,13 +448,12 @@ static void ce_rhs(int k, const T *y, const double *m, const double *rc, const b
       T d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
       T q2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       T q = msqrt(q2);
-      double rcij = std::max(rc[i], rc[j]);
-      T yc = (q - T(p.f_in * rcij)) / T((1.0 - p.f_in) * rcij);
-      if (val(yc) >= 1) continue;
-      T K, dKdy;
-      changeover(yc, &K, &dKdy);
-      T dKdr = dKdy / T((1.0 - p.f_in) * rcij);
-      T c = T(p.G * m[j]) * ((T(1) - K) / (q2 * q) + dKdr / q2);
+      if (val(q) >= std::max(rc[i], rc[j])) continue;     // beyond rc_0: W = 0
+      for (int l = 0; l < p.nl; l++) rcs[l] = std::max(rc[l * k + i], rc[l * k + j]);
+      T W, dW;
+      level_weight(q, rcs, p.nl, p, &W, &dW);
+      // minus the gradient of -G m_i m_j W/r with respect to x_i, divided by m_i
+      T c = T(p.G * m[j]) * (W / (q2 * q) - dW / q2);
       for (int l = 0; l < 3; l++) a[l] = a[l] + c * d[l];
     }
     for (int l = 0; l < 3; l++) {
@@ -638,13 +661,15 @@ static int ce_drift_group(int k, T *y, double *m, const double *rc, const Params
 
 // Drift of every body over h with the close-encounter groups given by labels (smallest index of
 // each body's group; a body alone in its group keeps the Kepler drift). With mc, bodies of a group
-// that come into contact merge (m and R updated).
+// that come into contact merge (m and R updated). rc holds the critical radii level by level
+// ([p.nl][n]); with a mask only the bodies it marks move.
 template <class T>
 static int drift_groups(int64_t n, T *x, T *v, double *m, const double *rc, const int32_t *label,
                         const Params &p, double h, double tol, int64_t *stats, double *R = nullptr,
-                        MergeCtx *mc = nullptr) {
+                        MergeCtx *mc = nullptr, const char *mask = nullptr) {
   std::vector<std::vector<int64_t>> members((size_t)n);
-  for (int64_t i = 0; i < n; i++) members[(size_t)label[i]].push_back(i);
+  for (int64_t i = 0; i < n; i++)
+    if (!mask || mask[i]) members[(size_t)label[i]].push_back(i);
   int worst = 0;
   for (int64_t r = 0; r < n; r++) {
     const auto &g = members[(size_t)r];
@@ -656,14 +681,14 @@ static int drift_groups(int64_t n, T *x, T *v, double *m, const double *rc, cons
     }
     const int k = (int)g.size();
     std::vector<T> y(6 * (size_t)k);
-    std::vector<double> mg(k), rcg(k), Rg(k, 0.0);
+    std::vector<double> mg(k), rcg((size_t)p.nl * k), Rg(k, 0.0);
     for (int a = 0; a < k; a++) {
       for (int l = 0; l < 3; l++) {
         y[3 * a + l] = x[3 * g[a] + l];
         y[3 * k + 3 * a + l] = v[3 * g[a] + l];
       }
       mg[a] = m[g[a]];
-      rcg[a] = rc[g[a]];
+      for (int l = 0; l < p.nl; l++) rcg[(size_t)l * k + a] = rc[(size_t)l * n + g[a]];
       if (R) Rg[a] = R[g[a]];
     }
     const int st = ce_drift_group<T>(k, y.data(), mg.data(), rcg.data(), p, h, tol, Rg.data(), g.data(), mc);
@@ -687,12 +712,93 @@ static int drift_groups(int64_t n, T *x, T *v, double *m, const double *rc, cons
   return worst;
 }
 
+// ---------------------------------------------------------------- multi-level changeover
+// Intermediate levels between the symplectic step and the direct integrator (the paper's
+// multi-level changeover). Level l has the time step dt_l = dt / s^l and critical radii from
+// eq. rcrit at that step, rc_l = max(n1 R_Hill, n2 dt_l v) with the exact-predicate thresholds
+// H, V_l. The drift of the bodies in close pairs (the step's level-0 list P0) integrates
+// H_A = Kepler + W_0 U, U = -G m_i m_j / r over P0 and W_l = prod_{i <= l} [1 - K_i]. Above the
+// deepest level L, a level-l drift over tau is split into s substeps of
+//   kick(tau/2s) drift_{l+1}(tau/s) kick(tau/2s),
+// where the kick acts on the pairs of P0 with the potential W_l K_{l+1} U and drift_{l+1}
+// integrates Kepler + W_{l+1} U. At level L the pairs of P0 closer than rc_L (exact predicate at
+// the current positions) form groups integrated with the Gragg-Bulirsch-Stoer method on
+// Kepler + W_L U; the other bodies of P0 follow Kepler orbits. Without intermediate levels (L = 0)
+// this is the drift of the hybrid step.
+struct Levels {
+  int L, s;
+  int64_t n;
+  std::vector<double> rc, H, V;   // [L + 1][n], level-major
+};
+
+// Kick over the pairs of P0 with the level-l potential W_{l-1} K_l U (l >= 1), in pair order.
+template <class T>
+static void level_kick(int64_t n, const T *x, T *v, const double *m, const int32_t *P0, int64_t np,
+                       const Levels &lv, int l, const Params &p, T h) {
+  std::vector<T> a(3 * (size_t)n, T(0));
+  double rcs[8];
+  for (int64_t e = 0; e < np; e++) {
+    const int64_t i = P0[2 * e], j = P0[2 * e + 1];
+    T d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+    T q2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    T q = msqrt(q2);
+    for (int k = 0; k <= l; k++) rcs[k] = std::max(lv.rc[(size_t)k * n + i], lv.rc[(size_t)k * n + j]);
+    T W, dW, K, dKdy;
+    level_weight(q, rcs, l, p, &W, &dW);
+    const T span = T((1.0 - p.f_in) * rcs[l]);
+    changeover((q - T(p.f_in * rcs[l])) / span, &K, &dKdy);
+    const T dK = dKdy / span;
+    const T Vw = W * K, dV = dW * K + W * dK;
+    const T c = T(p.G) * (Vw / (q2 * q) - dV / q2);
+    for (int k = 0; k < 3; k++) {
+      a[3 * i + k] = a[3 * i + k] + c * T(m[j]) * d[k];
+      a[3 * j + k] = a[3 * j + k] - c * T(m[i]) * d[k];
+    }
+  }
+  for (int64_t i = 0; i < 3 * n; i++) v[i] = v[i] + h * a[i];
+}
+
+template <class T>
+static int drift_levels(int64_t n, T *x, T *v, double *m, const int32_t *P0, int64_t np,
+                        const std::vector<char> &inP0, const Levels &lv, const Params &p, int l, double tau,
+                        double tol, int64_t *stats, double *R, MergeCtx *mc) {
+  if (l == lv.L) {
+    // groups of the level-L close pairs at the current positions
+    std::vector<int32_t> PL;
+    for (int64_t e = 0; e < np; e++) {
+      const int64_t i = P0[2 * e], j = P0[2 * e + 1];
+      const double xi[3] = {(double)val(x[3 * i]), (double)val(x[3 * i + 1]), (double)val(x[3 * i + 2])};
+      const double xj[3] = {(double)val(x[3 * j]), (double)val(x[3 * j + 1]), (double)val(x[3 * j + 2])};
+      double r2;
+      const size_t o = (size_t)l * n;
+      if (l == 0 || close_pair(xi, xj, lv.H[o + i], lv.H[o + j], lv.V[o + i], lv.V[o + j], &r2)) {
+        PL.push_back((int32_t)i);
+        PL.push_back((int32_t)j);
+      }
+    }
+    std::vector<int32_t> label(n);
+    groups_bfs(n, PL.data(), (int64_t)PL.size() / 2, label.data(), nullptr);
+    Params pl = p;
+    pl.nl = l + 1;
+    return drift_groups<T>(n, x, v, m, lv.rc.data(), label.data(), pl, tau, tol, stats, R, mc, inP0.data());
+  }
+  const double ts = tau / lv.s;
+  int worst = 0;
+  for (int k = 0; k < lv.s; k++) {
+    level_kick<T>(n, x, v, m, P0, np, lv, l + 1, p, T(0.5 * ts));
+    worst = std::max(worst, drift_levels<T>(n, x, v, m, P0, np, inP0, lv, p, l + 1, ts, tol, stats, R, mc));
+    level_kick<T>(n, x, v, m, P0, np, lv, l + 1, p, T(0.5 * ts));
+  }
+  return worst;
+}
+
 // nsteps hybrid steps: as steps() but the drift integrates H_A in full, every close-encounter
 // group (from the close pairs at the positions of the step's first kick) with ce_drift_group;
 // with mc, contacts within a group merge (m and R updated, mergers logged with their step).
+// With lv (L > 0), the drift of the bodies in close pairs runs through the intermediate levels.
 static int steps_hybrid(int64_t n, double *x, double *v, double *m, const Params &p, int nsteps,
                         const double *rc, const double *H, const double *V, double tol, int64_t *stats,
-                        double *R = nullptr, MergeCtx *mc = nullptr) {
+                        double *R = nullptr, MergeCtx *mc = nullptr, const Levels *lv = nullptr) {
   std::vector<double> acc(3 * n);
   std::vector<int32_t> label(n);
   const double h = 0.5 * p.dt;
@@ -707,8 +813,17 @@ static int steps_hybrid(int64_t n, double *x, double *v, double *m, const Params
     jump<double>(n, x, v, m, p, h);
     std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n);
     if (mc) mc->step = s;
-    worst = std::max(worst, drift_groups<long double>(n, xl.data(), vl.data(), m, rc, label.data(), p, p.dt,
-                                                      tol, stats, R, mc));
+    if (lv && lv->L > 0) {
+      std::vector<char> inP0(n, 0);
+      for (int64_t e = 0; e < np; e++) inP0[pairs[2 * e]] = inP0[pairs[2 * e + 1]] = 1;
+      for (int64_t i = 0; i < n; i++)
+        if (!inP0[i]) worst = std::max(worst, kepler<long double>(&xl[3 * i], &vl[3 * i], p.G * p.m0, p.dt));
+      worst = std::max(worst, drift_levels<long double>(n, xl.data(), vl.data(), m, pairs.data(), np, inP0, *lv,
+                                                        p, 0, p.dt, tol, stats, R, mc));
+    } else {
+      worst = std::max(worst, drift_groups<long double>(n, xl.data(), vl.data(), m, rc, label.data(), p, p.dt,
+                                                        tol, stats, R, mc));
+    }
     for (int64_t i = 0; i < 3 * n; i++) { x[i] = (double)xl[i]; v[i] = (double)vl[i]; }
     jump<double>(n, x, v, m, p, h);
     kick_acc<double>(n, x, m, rc, H, V, p, acc.data(), nullptr, nullptr);
@@ -899,6 +1014,74 @@ int or_step_hybrid(int64_t n, double *x, double *v, const double *m, const doubl
   if (stats) stats[0] = stats[1] = stats[2] = 0;
   std::vector<double> mm(m, m + n);
   return steps_hybrid(n, x, v, mm.data(), p, nsteps, rc.data(), H.data(), V.data(), tol, stats);
+}
+
+// Acceleration of the level-l kick (l >= 1) over the listed pairs: acc = G sum m_j (V/r^3 - V'/r^2) d
+// with V = W_{l-1} K_l; rc holds the critical radii of the levels 0..l ([l + 1][n]).
+void or_level_kick_acc(int64_t n, const double *x, const double *m, const int32_t *pairs, int64_t np,
+                       const double *rc, int l, const double *prm, double *acc) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  Levels lv{l, 1, n, std::vector<double>(rc, rc + (size_t)(l + 1) * n), {}, {}};
+  std::vector<double> v(3 * (size_t)n, 0.0);
+  level_kick<double>(n, x, v.data(), m, pairs, np, lv, l, p, 1.0);
+  std::copy(v.begin(), v.end(), acc);
+}
+
+// Close-encounter drift of one group with the pair term weighted by the levels 0..nl-1
+// (rc [nl][k] of the members), long double; returns the integrator status.
+int or_ce_drift_group_levels(const int64_t *idx, int k, double *x, double *v, const double *m, const double *rc,
+                             int nl, const double *prm, double h, double tol) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  p.nl = nl;
+  std::vector<long double> y(6 * (size_t)k);
+  std::vector<double> mg(k);
+  for (int a = 0; a < k; a++) {
+    for (int l = 0; l < 3; l++) {
+      y[3 * a + l] = x[3 * idx[a] + l];
+      y[3 * k + 3 * a + l] = v[3 * idx[a] + l];
+    }
+    mg[a] = m[idx[a]];
+  }
+  const int st = ce_drift_group<long double>(k, y.data(), mg.data(), rc, p, h, tol);
+  for (int a = 0; a < k; a++)
+    for (int l = 0; l < 3; l++) {
+      x[3 * idx[a] + l] = (double)y[3 * a + l];
+      v[3 * idx[a] + l] = (double)y[3 * k + 3 * a + l];
+    }
+  return st;
+}
+
+// nsteps hybrid steps with L intermediate changeover levels (time steps dt / s^l) and, when R is
+// given, collisions as perfect mergers (radius factor f; m and R in/out, mergers logged).
+int or_step_levels(int64_t n, double *x, double *v, double *m, const double *prm, int nsteps,
+                   const double *rc_in, const double *H_in, const double *V_in, double tol, int64_t *stats,
+                   int L, int sub, double *R, double f, int32_t *merges, double *mtime, int64_t cap,
+                   int64_t *count) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  if (L < 0 || L > 4 || sub < 1) return -1;
+  Levels lv{L, sub, n, std::vector<double>((size_t)(L + 1) * n), std::vector<double>((size_t)(L + 1) * n),
+            std::vector<double>((size_t)(L + 1) * n)};
+  double dtl = p.dt;
+  for (int l = 0; l <= L; l++) {
+    Params pl = p;
+    pl.dt = dtl;
+    const size_t o = (size_t)l * n;
+    if (l == 0 && rc_in && H_in && V_in) {
+      std::copy(rc_in, rc_in + n, lv.rc.begin()); std::copy(H_in, H_in + n, lv.H.begin());
+      std::copy(V_in, V_in + n, lv.V.begin());
+    } else {
+      thresholds(n, x, v, m, pl, lv.rc.data() + o, lv.H.data() + o, lv.V.data() + o);
+    }
+    dtl = dtl / sub;
+  }
+  if (stats) stats[0] = stats[1] = stats[2] = 0;
+  std::vector<int64_t> log;
+  std::vector<long double> time;
+  MergeCtx mc{f, n, 0, &log, &time};
+  const int st = steps_hybrid(n, x, v, m, p, nsteps, lv.rc.data(), lv.H.data(), lv.V.data(), tol, stats,
+                              R, R ? &mc : nullptr, &lv);
+  *count = put_log(log, time, cap, merges, mtime);
+  return st;
 }
 
 // nsteps hybrid steps with collisions (perfect mergers at contact, radius factor f): m and R in/out,
