@@ -188,16 +188,36 @@ int nbody_drift_groups(nbody_ctx *ctx, int64_t n, double *xm, double *v, const d
                        void *stream);
 
 /*
+ * Multi-level changeover (the paper's intermediate levels between the symplectic step and the
+ * direct close-encounter integrator, section "The hybrid symplectic integrator"). Level l has the
+ * time step dt / substeps^l and critical radii from eq. rcrit at that step (thresholds taken at
+ * the call's start). The drift of the bodies with close partners integrates
+ * H_A = Kepler + W_0 U over the step's close pairs (U = -G m_i m_j / r, W_l = prod_{i<=l} [1 - K_i]);
+ * above the deepest level L a level-l drift over tau is substeps substeps of
+ * kick(tau/2s) drift_{l+1}(tau/s) kick(tau/2s), the kick acting on the close pairs with the
+ * potential W_l K_{l+1} U; at level L the close pairs still within rc_L form the groups that the
+ * direct integrator takes (pair term weighted by W_L), and the other bodies follow Kepler orbits.
+ * levels = 0 is the plain hybrid step; at most 4 levels.
+ */
+typedef struct nbody_levels {
+  int32_t levels;
+  int32_t substeps;
+} nbody_levels;
+
+/*
  * Hybrid step: as nbody_step (B(dt/2) C(dt/2) A(dt) C(dt/2) B(dt/2), thresholds fixed for the
  * call, merged half kicks), but the drift A integrates H_A in full: the close pairs found by each
  * kick's pair loop form the close-encounter groups of the drift that follows, integrated as in
  * nbody_drift_groups. The step then conserves the full energy E instead of the K-weighted E'.
- * col (may be NULL): collisions as perfect mergers in every step's drift (merged masses take part
- * in the kicks that follow; rc stays fixed for the call). stats as for nbody_drift_groups, summed
+ * lv (may be NULL: no intermediate levels): multi-level changeover (see nbody_levels); contacts
+ * are then looked for by the direct integrator at the deepest level and merger times are within
+ * that level's substep. col (may be NULL): collisions as perfect mergers in every step's drift
+ * (merged masses take part in the kicks that follow; rc stays fixed for the call). stats as for nbody_drift_groups, summed
  * over the steps (stats[1] the maximum). Binary64 only.
  */
 int nbody_step_hybrid(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr,
-                      int32_t nsteps, const nbody_collisions *col, int64_t *stats, void *stream);
+                      int32_t nsteps, const nbody_levels *lv, const nbody_collisions *col,
+                      int64_t *stats, void *stream);
 
 /*
  * Input check before integrating a state. The method has no softening, so a body at the central

@@ -38,6 +38,11 @@ class Collisions(ctypes.Structure):
                 ("time", ctypes.c_void_p), ("cap", ctypes.c_int64), ("count", ctypes.c_void_p)]
 
 
+class Levels(ctypes.Structure):
+    """nbody_levels: intermediate changeover levels of the hybrid step."""
+    _fields_ = [("levels", ctypes.c_int32), ("substeps", ctypes.c_int32)]
+
+
 @dataclasses.dataclass
 class Params:
     G: float = 1.0
@@ -68,7 +73,7 @@ EXPORTS = {
     "nbody_validate": [_I64, _P, _P, _P, _P],
     "nbody_encounter_groups": [_I64, _P, _I64, _P, _P, _P, _P],
     "nbody_drift_groups": [_I64, _P, _P, _P, _P, _D, _P, _P, _P],
-    "nbody_step_hybrid": [_I64, _P, _P, _P, _I32, _P, _P, _P],
+    "nbody_step_hybrid": [_I64, _P, _P, _P, _I32, _P, _P, _P, _P],
     "nbody_energy": [_I64, _P, _P, _P, _P, _P],
     "nbody_bench_pairs": [_I64, _P, _P, _I32, _P, _P],
     "nbody_kick_vjp": [_I64, _P, _P, _D, _P, _P, _P],
@@ -284,16 +289,19 @@ class Context:
                     "nbody_drift_groups")
         return self._ce_result(stats, log)
 
-    def step_hybrid(self, xm, v, nsteps, thr=None, radius=None, f=1.0, cap=4096):
+    def step_hybrid(self, xm, v, nsteps, thr=None, radius=None, f=1.0, cap=4096, levels=0, substeps=8):
         """nsteps hybrid steps in place (close-encounter groups integrated in the drift); with
-        radius (float64 [n], in/out), collisions merge bodies. Returns the statistics as a dict
-        (with the merger log when colliding)."""
+        levels > 0, the drift of the bodies with close partners runs through that many
+        intermediate changeover levels (time steps dt / substeps^l); with radius (float64 [n],
+        in/out), collisions merge bodies. Returns the statistics as a dict (with the merger log
+        when colliding)."""
         _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
         stats = torch.zeros(6, dtype=torch.int64, device=xm.device)
         col, log = self._collisions(radius, f, cap, xm.device)
+        lv = Levels(int(levels), int(substeps))
         self._check(lib().nbody_step_hybrid(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr), int(nsteps),
-                                            ctypes.byref(col) if col else None, _ptr(stats), _stream()),
-                    "nbody_step_hybrid")
+                                            ctypes.byref(lv), ctypes.byref(col) if col else None, _ptr(stats),
+                                            _stream()), "nbody_step_hybrid")
         return self._ce_result(stats, log)
 
     def validate(self, xm, v):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnbody.so")
-SOURCES = ["capi.hip", "pairs.hip", "kick.hip", "kepler.hip", "adjoint.hip", "batched.hip", "groups.hip", "ce.hip"]
+SOURCES = ["capi.hip", "pairs.hip", "kick.hip", "kepler.hip", "adjoint.hip", "batched.hip", "groups.hip", "ce.hip", "levels.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

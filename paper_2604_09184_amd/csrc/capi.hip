@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -29,7 +30,8 @@ enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MO
              B_ADJ_STATES, B_XA, B_VA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GMARK, B_GIN, B_GSIZE,
-             B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_HGOUT, B_NUM };
+             B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_HGOUT, B_LTHR, B_ADEG, B_AOFF,
+             B_AFILL, B_ADJ, B_LSKIP, B_NUM };
 
 }  // namespace
 
@@ -336,8 +338,11 @@ int ce_drift(nbody_ctx *c, int n, double4 *xm, double4 *v, const double4 *thr, c
   HIPCHK(c, launch_group_lists(labels, n, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
                                g.counter, st), "group lists");
   const nbody_params &p = c->p;
+  LevelThr lt{};
+  lt.thr[0] = thr;
+  lt.nl = 1;
   HIPCHK(c, launch_ce_drift(xm, v, thr, g.gmem, g.gstart, g.gsize, g.groot, g.counter, n / 2 + 1, p.G, p.m0,
-                            p.f_in, h, kCeTol, stats, col, st), "close-encounter drift");
+                            p.f_in, h, kCeTol, stats, col, lt, st), "close-encounter drift");
   return NBODY_OK;
 }
 
@@ -566,7 +571,7 @@ int nbody_drift_groups(nbody_ctx *c, int64_t n, double *xm, double *v, const dou
 }
 
 int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr, int32_t nsteps,
-                      const nbody_collisions *col, int64_t *stats, void *stream) {
+                      const nbody_levels *lv, const nbody_collisions *col, int64_t *stats, void *stream) {
   TRY(check_n(c, n));
   TRY(check_dev(c, xm, "xm", true));
   TRY(check_dev(c, v, "v", true));
@@ -574,6 +579,10 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   TRY(check_dev(c, stats, "stats", true));
   if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
   if (c->p.precision != NBODY_PREC_F64) return fail(c, NBODY_E_INVAL, "the hybrid step runs in binary64");
+  const int L = lv ? lv->levels : 0;
+  const int sub = lv ? lv->substeps : 1;
+  if (L < 0 || L >= kMaxLevels) return fail(c, NBODY_E_INVAL, "levels must be 0..%d", kMaxLevels - 1);
+  if (L > 0 && sub < 1) return fail(c, NBODY_E_INVAL, "substeps must be >= 1");
   CeCollide cc;
   TRY(collide_args(c, (int)n, col, cc));
   hipStream_t st = (hipStream_t)stream;
@@ -612,11 +621,63 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   TRY(locality(c, N, X, st, &a.perm));
   TRY(mass_check(c, N, X, st, &a.uni));
   const int ublocks = (int)std::min<int64_t>(4096, (cap + kBlock - 1) / kBlock);
-  // groups of the list at the current kick positions
+  // intermediate changeover levels: thresholds at dt / sub^l (fixed for the call), the symmetric
+  // adjacency of each step's close pairs, and a drift mask
+  LevelThr lt{};
+  lt.thr[0] = T;
+  lt.nl = L + 1;
+  int *deg = nullptr, *off = nullptr, *fill = nullptr, *adj = nullptr, *lskip = nullptr;
+  if (L > 0) {
+    double4 *lthr = (double4 *)ensure(c, B_LTHR, (size_t)L * n * sizeof(double4));
+    deg = (int *)ensure(c, B_ADEG, (size_t)n * sizeof(int));
+    off = (int *)ensure(c, B_AOFF, (size_t)n * sizeof(int));
+    fill = (int *)ensure(c, B_AFILL, (size_t)n * sizeof(int));
+    adj = (int *)ensure(c, B_ADJ, (size_t)cap * 2 * sizeof(int));
+    lskip = (int *)ensure(c, B_LSKIP, (size_t)n * sizeof(int));
+    if (!lthr || !deg || !off || !fill || !adj || !lskip)
+      return fail(c, NBODY_E_NOMEM, "workspace allocation failed (changeover levels)");
+    const double cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
+    double dtl = p.dt;
+    for (int l = 1; l <= L; ++l) {
+      dtl = dtl / sub;
+      const double t = p.n2 * dtl;
+      HIPCHK(c, launch_rcrit(X, Vv, lthr + (size_t)(l - 1) * n, N, p.m0, cH, t * t, p.n1, t, st), "level rcrit");
+      lt.thr[l] = lthr + (size_t)(l - 1) * n;
+    }
+  }
+  // groups of the list at the current kick positions (and, with levels, its adjacency)
   auto groups_now = [&]() -> int {
     TRY(emit_list(c, a, lpairs, cap, lcount, st));
     HIPCHK(c, launch_list_overflow(lcount, cap, S, st), "list check");
-    HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.mark, gout, ublocks, st), "groups");
+    if (L == 0)
+      HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.mark, gout, ublocks, st), "groups");
+    else
+      HIPCHK(c, launch_adjacency(lpairs, cap, lcount, N, deg, off, fill, adj, st), "adjacency");
+    return NBODY_OK;
+  };
+  int step = 0;
+  // level-l drift over tau of the bodies with close partners: at the deepest level the groups of
+  // the level-L close pairs go through the close-encounter integrator and the others follow Kepler
+  // orbits; above it, sub substeps of kick / drift_{l+1} / kick
+  std::function<int(int, double)> drift_levels = [&](int l, double tau) -> int {
+    if (l == L) {
+      HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.mark, gout, ublocks, st, X, lt.thr[L]),
+             "level groups");
+      HIPCHK(c, launch_group_lists(labels, N, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
+                                   g.counter, st), "group lists");
+      cc.step = step;
+      HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
+                                p.f_in, tau, kCeTol, S, cc, lt, st), "close-encounter drift");
+      HIPCHK(c, launch_level_mask(deg, g.in, N, lskip, st), "level mask");
+      HIPCHK(c, launch_drift(X, Vv, N, tau, mu, nullptr, st, lskip), "level drift");
+      return NBODY_OK;
+    }
+    const double ts = tau / sub;
+    for (int k = 0; k < sub; ++k) {
+      HIPCHK(c, launch_level_kick(X, Vv, off, deg, adj, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
+      TRY(drift_levels(l + 1, ts));
+      HIPCHK(c, launch_level_kick(X, Vv, off, deg, adj, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
+    }
     return NBODY_OK;
   };
   HIPCHK(c, launch_pairs(a, true, true, false, false, st), "hybrid pairs");
@@ -624,14 +685,24 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
          "hybrid finalize");
   TRY(groups_now());
   for (int s = 1; s <= nsteps; ++s) {
-    HIPCHK(c, launch_group_lists(labels, N, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
-                                 g.counter, st), "group lists");
-    // first jump for all; Kepler drift for the bodies in no group
-    HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
-                                g.in), "jump+drift");
-    cc.step = s - 1;
-    HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
-                              p.f_in, p.dt, kCeTol, S, cc, st), "close-encounter drift");
+    step = s - 1;
+    if (L == 0) {
+      HIPCHK(c, launch_group_lists(labels, N, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
+                                   g.counter, st), "group lists");
+      // first jump for all; Kepler drift for the bodies in no group
+      HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
+                                  g.in), "jump+drift");
+      cc.step = step;
+      HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
+                                p.f_in, p.dt, kCeTol, S, cc, lt, st), "close-encounter drift");
+    } else {
+      // first jump for all; Kepler drift for the bodies without close partners; the others
+      // through the levels
+      HIPCHK(c, launch_level_mask(deg, nullptr, N, lskip, st), "level mask");
+      HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
+                                  lskip), "jump+drift");
+      TRY(drift_levels(0, p.dt));
+    }
     // mergers change masses: the equal-mass flag of the pair kernel is taken again
     if (cc.radius) TRY(mass_check(c, N, X, st, &a.uni));
     HIPCHK(c, launch_momentum(X, Vv, N, momB, st), "momentum");

@@ -139,6 +139,24 @@ struct CeMember {
   double Gm, rc, ispan, fR;
 };
 
+// Shared state of one group's integration (LDS): the tableau's end values (double buffered), the
+// slot of each member rank, the member values, masses, radii and body indices by rank, and the
+// critical radii rc_l and 1/((1 - f_in) rc_l) of the changeover levels by rank.
+struct CeShared {
+  double est[2][8][6][64];
+  CeMember mem[64];
+  double mass[64], rad[64];
+  double lrc[kMaxLevels][64], lisp[kMaxLevels][64];
+  int owner[64], body[64];
+};
+
+// Per-lane constants of one group's integration (nl: changeover levels weighting the pair term).
+struct CeLane {
+  int k, iters, P, rep, slot, wv, rank, nl;
+  bool act;
+  double rc, ispan, Gm0, f_in, tol;
+};
+
 // A lane's partners: for iteration it the member q = rep + it P (in ascending body order), the lane
 // src of its first replica, and whether the term counts (a member, and not the lane's own body).
 struct CePartner {
@@ -147,15 +165,14 @@ struct CePartner {
   CeMember m;
 };
 
-__device__ __forceinline__ CePartner ce_partner(int q, int k, bool act, int slot, int P,
-                                                const int *owner, const CeMember *mem) {
-  const bool valid = q < k;
+__device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const CeShared &sh) {
+  const bool valid = q < L.k;
   const int qq = valid ? q : 0;
   CePartner p;
-  p.q = q;
-  p.src = owner[qq] * P;
-  p.use = act && valid && owner[qq] != slot;
-  p.m = mem[qq];
+  p.q = qq;
+  p.src = sh.owner[qq] * L.P;
+  p.use = L.act && valid && sh.owner[qq] != L.slot;
+  p.m = sh.mem[qq];
   return p;
 }
 
@@ -163,22 +180,43 @@ __device__ __forceinline__ CePartner ce_partner(int q, int k, bool act, int slot
 // the changeover variable clamped to [0, 1] and D = 2y^2 - 2y + 1, 1 - K = (1 - y)^2/D and
 // K'(r) = 2y(1 - y)/(D^2 (1 - f_in) rc_ij), which gives 1/r^3 inside f_in rc_ij and 0 beyond rc_ij
 // with no branch. No division or square root: r^-1 and 1/D come from refined hardware estimates.
-__device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p, double rc,
-                                        double ispan, double f_in, double &a0, double &a1,
-                                        double &a2) {
+//
+// With intermediate changeover levels the pair potential is weighted by W = prod_l [1 - K_l] (one
+// factor per level, each with its own rc_l), and the coefficient is G m_j (W/r^3 - W'(r)/r^2).
+__device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p, const CeLane &L,
+                                        const CeShared &sh, double &a0, double &a1, double &a2) {
   const double dx = __shfl(z[0], p.src, 64) - z[0];
   const double dy = __shfl(z[1], p.src, 64) - z[1];
   const double dz = __shfl(z[2], p.src, 64) - z[2];
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double ir = ce_rinv(r2);
   const double r = r2 * ir;
-  const bool mine = rc > p.m.rc;
-  const double rcij = mine ? rc : p.m.rc;
-  const double isp = mine ? ispan : p.m.ispan;
-  const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
-  const double omy = 1.0 - y;
-  const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
-  const double c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
+  const double f_in = L.f_in;
+  double c;
+  if (L.nl == 1) {
+    const bool mine = L.rc > p.m.rc;
+    const double rcij = mine ? L.rc : p.m.rc;
+    const double isp = mine ? L.ispan : p.m.ispan;
+    const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
+    const double omy = 1.0 - y;
+    const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
+    c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
+  } else {
+    double W = 1.0, dW = 0.0;
+    for (int l = 0; l < L.nl; ++l) {
+      const double rci = sh.lrc[l][L.rank], rcj = sh.lrc[l][p.q];
+      const bool mine = rci > rcj;
+      const double rcij = mine ? rci : rcj;
+      const double isp = mine ? sh.lisp[l][L.rank] : sh.lisp[l][p.q];
+      const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
+      const double omy = 1.0 - y;
+      const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
+      const double omK = omy * omy * iD, dK = 2.0 * y * omy * iD * iD * isp;
+      dW = dW * omK - W * dK;
+      W = W * omK;
+    }
+    c = ir * ir * (W * ir - dW);
+  }
   const double cm = p.use ? c * p.m.Gm : 0.0;
   a0 = fma(cm, dx, a0);
   a1 = fma(cm, dy, a1);
@@ -205,23 +243,22 @@ __device__ __forceinline__ void ce_row_add(double &a0, double &a1, double &a2) {
 constexpr int kCeRegPartners = 4;
 
 // f = (v, a) of this lane's body at the state z.
-__device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, bool act, bool alive, int iters,
-                                       int P,
-                                       int rep, int slot, const int *owner, const CeMember *mem,
-                                       const CePartner (&pr)[kCeRegPartners], double rc,
-                                       double ispan, double Gm0, double f_in, double (&f)[6]) {
+__device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, const CeShared &sh,
+                                       const CePartner (&pr)[kCeRegPartners], bool alive,
+                                       double (&f)[6]) {
+  const int P = L.P;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  if (iters == 1) {
-    ce_pair(z, pr[0], rc, ispan, f_in, a0, a1, a2);
+  if (L.iters == 1) {
+    ce_pair(z, pr[0], L, sh, a0, a1, a2);
   } else {
     // independent terms side by side (masked beyond the members)
 #pragma unroll
-    for (int u = 0; u < kCeRegPartners; ++u) ce_pair(z, pr[u], rc, ispan, f_in, a0, a1, a2);
-    for (int it = kCeRegPartners; it < iters; it += kCeRegPartners) {
+    for (int u = 0; u < kCeRegPartners; ++u) ce_pair(z, pr[u], L, sh, a0, a1, a2);
+    for (int it = kCeRegPartners; it < L.iters; it += kCeRegPartners) {
 #pragma unroll
       for (int u = 0; u < kCeRegPartners; ++u) {
-        const CePartner p = ce_partner(rep + (it + u) * P, k, act, slot, P, owner, mem);
-        ce_pair(z, p, rc, ispan, f_in, a0, a1, a2);
+        const CePartner p = ce_partner(L.rep + (it + u) * P, L, sh);
+        ce_pair(z, p, L, sh, a0, a1, a2);
       }
     }
   }
@@ -231,7 +268,7 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, bool act, bo
   if (P >= 16) ce_row_add<0x140>(a0, a1, a2);  // row mirror: lane i <-> 15 - i
   const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
   const double ir = ce_rinv(r2);
-  const double s = -Gm0 * (ir * ir * ir);
+  const double s = -L.Gm0 * (ir * ir * ir);
   // a body merged away is held fixed
   f[0] = alive ? z[3] : 0.0;
   f[1] = alive ? z[4] : 0.0;
@@ -242,21 +279,19 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], int k, bool act, bo
 }
 
 // Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
-__device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, int k, bool act,
-                                         bool alive, int iters, int P, int rep, int slot, const int *owner,
-                                         const CeMember *mem, const CePartner (&pr)[kCeRegPartners],
-                                         double rc, double ispan, double Gm0, double f_in,
-                                         double (&est)[6]) {
+__device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, const CeLane &L,
+                                         const CeShared &sh, const CePartner (&pr)[kCeRegPartners],
+                                         bool alive, double (&est)[6]) {
   const double hs = H / ns;
   double zm[6], zc[6], f[6];
-  ce_rhs(y, k, act, alive, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
+  ce_rhs(y, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
     zc[i] = y[i] + hs * f[i];
   }
   for (int s = 1; s < ns; ++s) {
-    ce_rhs(zc, k, act, alive, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
+    ce_rhs(zc, L, sh, pr, alive, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const double zn = zm[i] + 2.0 * hs * f[i];
@@ -264,7 +299,7 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
       zc[i] = zn;
     }
   }
-  ce_rhs(zc, k, act, alive, iters, P, rep, slot, owner, mem, pr, rc, ispan, Gm0, f_in, f);
+  ce_rhs(zc, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zc[i] + zm[i] + hs * f[i]);
 }
@@ -291,22 +326,6 @@ __device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale
   return out;
 }
 
-// Shared state of one group's integration (LDS): the tableau's end values (double buffered), the
-// slot of each member rank, the member values, and masses, radii and body indices by rank.
-struct CeShared {
-  double est[2][8][6][64];
-  CeMember mem[64];
-  double mass[64], rad[64];
-  int owner[64], body[64];
-};
-
-// Per-lane constants of one group's integration.
-struct CeLane {
-  int k, iters, P, rep, slot, wv, rank;
-  bool act;
-  double rc, ispan, Gm0, f_in, tol;
-};
-
 // One macro-step attempt over H from y (all four waves together): returns the accepted column
 // (identical in every wave) or -1; y1 receives the accepted extrapolant.
 __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool alive, const CeLane &L,
@@ -320,8 +339,7 @@ __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool a
   for (int cc = 0; cc < 2; ++cc) {
     const int c = cc == 0 ? L.wv : 7 - L.wv;
     double est[6];
-    ce_sweep(y, H, 2 * c + 2, L.k, L.act, alive, L.iters, L.P, L.rep, L.slot, sh.owner, sh.mem, pr, L.rc,
-             L.ispan, L.Gm0, L.f_in, est);
+    ce_sweep(y, H, 2 * c + 2, L, sh, pr, alive, est);
     if (L.rep == 0)
 #pragma unroll
       for (int i = 0; i < 6; ++i) sh.est[buf][c][i][L.slot] = est[i];
@@ -374,8 +392,7 @@ __device__ __forceinline__ int ce_contact(const double (&y)[6], double fR, const
   for (int u = 0; u < kCeRegPartners; ++u)
     if (u < L.iters) ce_contact_test(y, fR, L, pr[u], key);
   for (int it = kCeRegPartners; it < L.iters; ++it)
-    ce_contact_test(y, fR, L,
-                    ce_partner(L.rep + it * L.P, L.k, L.act, L.slot, L.P, sh.owner, sh.mem), key);
+    ce_contact_test(y, fR, L, ce_partner(L.rep + it * L.P, L, sh), key);
   if (__ballot(key != 0x7fffffff) == 0) return -1;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) key = min(key, __shfl_xor(key, o, 64));
@@ -436,7 +453,8 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
     const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
     const int *__restrict__ groot, const int *__restrict__ ngroups, double G, double m0,
-    double f_in, double h, double tol, unsigned long long *__restrict__ stats, CeCollide col) {
+    double f_in, double h, double tol, unsigned long long *__restrict__ stats, CeCollide col,
+    LevelThr lt) {
   __shared__ CeShared sh;
   const int w = blockIdx.x;
   if (w >= *ngroups) return;
@@ -470,6 +488,7 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
   L.Gm0 = Gm0;
   L.f_in = f_in;
   L.tol = tol;
+  L.nl = lt.nl;
   const int b = gmem[base + (L.act ? L.slot : 0)];
   const double4 p0 = xm[b], u0 = v[b];
   L.rc = thr[b].x;
@@ -484,12 +503,17 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     sh.mass[L.rank] = p0.w;
     sh.rad[L.rank] = R0;
     sh.mem[L.rank] = CeMember{G * p0.w, L.rc, L.ispan, col.f * R0};
+    for (int l = 0; l < lt.nl; ++l) {
+      const double rcl = l == 0 ? L.rc : lt.thr[l][b].x;
+      sh.lrc[l][L.rank] = rcl;
+      sh.lisp[l][L.rank] = 1.0 / ((1.0 - f_in) * rcl);
+    }
   }
   __syncthreads();
   CePartner pr[kCeRegPartners];
 #pragma unroll
   for (int u = 0; u < kCeRegPartners; ++u)
-    pr[u] = ce_partner(L.rep + u * L.P, k, L.act, L.slot, L.P, sh.owner, sh.mem);
+    pr[u] = ce_partner(L.rep + u * L.P, L, sh);
   bool alive = true;
   double fR = col.f * R0;
   double y[6] = {p0.x, p0.y, p0.z, u0.x, u0.y, u0.z};
@@ -574,7 +598,7 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kCeRegPartners; ++u)
-          pr[u] = ce_partner(L.rep + u * L.P, k, L.act, L.slot, L.P, sh.owner, sh.mem);
+          pr[u] = ce_partner(L.rep + u * L.P, L, sh);
       }
       phase = 0;
       if (!(fabs(h - t) > 0.0)) break;
@@ -625,11 +649,11 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
                            const int *gstart, const int *gsize, const int *groot,
                            const int *ngroups, int max_groups, double G, double m0, double f_in,
                            double h, double tol, unsigned long long *stats, const CeCollide &col,
-                           hipStream_t st) {
+                           const LevelThr &lt, hipStream_t st) {
   if (max_groups > 0)
     hipLaunchKernelGGL(k_ce_drift, dim3(max_groups), dim3(64 * kCeWaves), 0, st, xm, v, thr, gmem,
                        gstart, gsize,
-                       groot, ngroups, G, m0, f_in, h, tol, stats, col);
+                       groot, ngroups, G, m0, f_in, h, tol, stats, col, lt);
   return hipGetLastError();
 }
 

@@ -43,11 +43,15 @@ __global__ __launch_bounds__(kBlock) void k_groups_init(int *__restrict__ parent
   if (i < 2) out[i] = 0;
 }
 
+// With xm and thr given, a listed pair is an edge only while it is close under thr's exact
+// predicate at the positions xm (a deeper changeover level's thresholds).
 __global__ __launch_bounds__(kBlock) void k_groups_union(const int32_t *__restrict__ pairs,
                                                          int64_t cap,
                                                          const int64_t *__restrict__ count, int n,
                                                          int *parent,
-                                                         unsigned long long *__restrict__ out) {
+                                                         unsigned long long *__restrict__ out,
+                                                         const double4 *__restrict__ xm,
+                                                         const double4 *__restrict__ thr) {
   const int64_t np = min(*count, cap);
   unsigned long long bad = 0;
   for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < np;
@@ -56,6 +60,12 @@ __global__ __launch_bounds__(kBlock) void k_groups_union(const int32_t *__restri
     if (i < 0 || j < 0 || i >= n || j >= n || i == j) {
       ++bad;
       continue;
+    }
+    if (xm) {
+      const double4 a = xm[i], b = xm[j], ta = thr[i], tb = thr[j];
+      const double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+      if (!nbd::close_exact(r2, ta.y, tb.y, ta.z, tb.z)) continue;
     }
     int ri = find_root(parent, i), rj = find_root(parent, j);
     while (ri != rj) {
@@ -92,13 +102,13 @@ __global__ __launch_bounds__(kBlock) void k_groups_count(const int *__restrict__
 
 hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
                          int32_t *labels, int *mark, int64_t *out, int union_blocks,
-                         hipStream_t st) {
+                         hipStream_t st, const double4 *xm, const double4 *thr) {
   unsigned long long *o = (unsigned long long *)out;
   hipLaunchKernelGGL(k_groups_init, dim3(nblocks(n > 2 ? n : 2)), dim3(kBlock), 0, st, labels, mark,
                      n, o);
   if (cap > 0)
     hipLaunchKernelGGL(k_groups_union, dim3(union_blocks), dim3(kBlock), 0, st, pairs, cap, count, n,
-                       labels, o);
+                       labels, o, xm, thr);
   hipLaunchKernelGGL(k_groups_flatten, dim3(nblocks(n)), dim3(kBlock), 0, st, labels, mark, n);
   hipLaunchKernelGGL(k_groups_count, dim3(nblocks(n)), dim3(kBlock), 0, st, mark, n, o);
   return hipGetLastError();

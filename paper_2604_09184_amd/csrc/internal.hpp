@@ -74,11 +74,30 @@ struct CeCollide {
   int n;
 };
 
+// Critical radii of the changeover levels 0..nl-1 (level 0 is the step's thr); the pair term of
+// the close-encounter drift is weighted by prod_l [1 - K_l].
+constexpr int kMaxLevels = 5;
+struct LevelThr {
+  const double4 *thr[kMaxLevels];
+  int nl;
+};
+
 hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
                            const int *gstart, const int *gsize, const int *groot,
                            const int *ngroups, int max_groups, double G, double m0, double f_in,
                            double h, double tol, unsigned long long *stats, const CeCollide &col,
-                           hipStream_t st);
+                           const LevelThr &lt, hipStream_t st);
+
+// levels.hip: symmetric adjacency of a pair list (rows sorted by neighbour index), the level kicks
+// over it and the masks of the level drifts.
+hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n, int *deg,
+                            int *off, int *fill, int *adj, hipStream_t st);
+hipError_t launch_level_kick(const double4 *xm, double4 *v, const int *off, const int *deg,
+                             const int *adj, int n, const LevelThr &lt, int level, double G,
+                             double f_in, double h, hipStream_t st);
+// skip[i] = 1 unless body i has a listed partner (deg > 0) and is outside the groups (in == 0);
+// with in null: skip[i] = (deg[i] > 0).
+hipError_t launch_level_mask(const int *deg, const int *in, int n, int *skip, hipStream_t st);
 
 // adjoint.hip
 hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double2 *uni,
@@ -92,7 +111,7 @@ hipError_t launch_drift_vjp(const double4 *xm, const double4 *v, int n, double d
 // groups.hip
 hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
                          int32_t *labels, int *mark, int64_t *out, int union_blocks,
-                         hipStream_t st);
+                         hipStream_t st, const double4 *xm = nullptr, const double4 *thr = nullptr);
 
 // batched.hip
 constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048

@@ -1,0 +1,103 @@
+"""GPU parity of the multi-level changeover (intermediate levels with time steps dt / s^l between
+the symplectic step and the direct close-encounter integrator) against the oracle's long-double
+recursion. Bars: group statistics equal (the deepest-level groups come from the same exact
+predicate); states 1e-10 relative after several steps (as for the hybrid step)."""
+import numpy as np
+import pytest
+
+import diskgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2604_09184_amd as nb
+    nb.lib()
+    return nb
+
+
+@pytest.fixture(scope="module")
+def ctx(nb):
+    return nb.Context(nb.Params(**diskgen.PARAMS))
+
+
+def dev_state(d):
+    xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+    return torch.tensor(xm, device=DEV), torch.tensor(v4, device=DEV)
+
+
+def rel_err(X, V, ox, ov):
+    x = X.cpu().numpy()[:, :3]; v = V.cpu().numpy()[:, :3]
+    ex = (np.abs(x - ox).max(1) / np.linalg.norm(ox, axis=1)).max()
+    ev = (np.abs(v - ov).max(1) / np.linalg.norm(ov, axis=1)).max()
+    return ex, ev
+
+
+@pytest.mark.parametrize("L,s,steps", [(1, 8, 10), (2, 4, 5)])
+def test_levels_match_oracle(ctx, L, s, steps):
+    say(f"levels L={L} s={s} disk2048 x{steps}")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = dev_state(d)
+    thr = ctx.rcrit(X, V)
+    stats = ctx.step_hybrid(X, V, steps, thr=thr, levels=L, substeps=s)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov, om, oR, st, ostats, _, _ = oracle.step_levels(d["x"], d["v"], d["m"], p, steps, L, s, thr=othr)
+    ex, ev = rel_err(X, V, ox, ov)
+    say(f"  {stats}; oracle {ostats}; state rel err x {ex:.2e} v {ev:.2e}")
+    assert st == 0 and stats["unfinished"] == 0 and stats["too_large"] == 0
+    assert (stats["groups"], stats["largest"], stats["bodies"]) == ostats
+    assert ex < 1e-10 and ev < 1e-10
+
+
+def test_zero_levels_is_the_hybrid_step(ctx):
+    say("levels L=0 vs hybrid")
+    d = diskgen.workload("disk2048")
+    X1, V1 = dev_state(d)
+    X2, V2 = X1.clone(), V1.clone()
+    thr = ctx.rcrit(X1, V1)
+    ctx.step_hybrid(X1, V1, 3, thr=thr, levels=0)
+    ctx.step_hybrid(X2, V2, 3, thr=thr)
+    assert torch.equal(X1, X2) and torch.equal(V1, V2)
+
+
+def test_levels_split_the_percolating_group(ctx):
+    """The 32768-body disk: its close pairs form one group of 9470 bodies, too large for the direct
+    integrator; one intermediate level (s = 8) hands it only small groups. 2 steps against the
+    oracle's recursion."""
+    say("levels L=1 s=8 disk32768 x2")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk32768")
+    X, V = dev_state(d)
+    thr = ctx.rcrit(X, V)
+    plain = ctx.step_hybrid(X.clone(), V.clone(), 1, thr=thr)
+    assert plain["too_large"] >= 1          # groups above 64 bodies (only Kepler orbits)
+    stats = ctx.step_hybrid(X, V, 2, thr=thr, levels=1, substeps=8)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov, om, oR, st, ostats, _, _ = oracle.step_levels(d["x"], d["v"], d["m"], p, 2, 1, 8, thr=othr)
+    ex, ev = rel_err(X, V, ox, ov)
+    say(f"  plain {plain}; levels {stats}; oracle {ostats}; state rel err x {ex:.2e} v {ev:.2e}")
+    assert stats["too_large"] == 0 and stats["unfinished"] == 0 and stats["largest"] <= 64
+    assert (stats["groups"], stats["largest"], stats["bodies"]) == ostats
+    assert ex < 1e-10 and ev < 1e-10
+
+
+def test_levels_arguments_checked(nb, ctx):
+    say("levels argument checks")
+    d = diskgen.workload("disk2048", n=64)
+    X, V = dev_state(d)
+    with pytest.raises(nb.NBodyError):
+        ctx.step_hybrid(X, V, 1, levels=5)
+    with pytest.raises(nb.NBodyError):
+        ctx.step_hybrid(X, V, 1, levels=1, substeps=0)
