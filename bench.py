@@ -203,6 +203,27 @@ def variant_hybrid(nb, p):
     sec, stats = timed(lambda: ctx.step_hybrid(X, V, 100, thr=thr, radius=R, f=300.0))
     out["hybrid_merge_f300"] = {"seconds": round(sec, 4), "ms_per_step": round(sec * 10, 4),
                                 "mergers": stats["mergers"], "bodies_left": int((X[:, 3] > 0).sum().item())}
+    # the 32768-body disk, whose close pairs percolate into groups too large for the direct
+    # integrator: 10 steps plain, hybrid, and hybrid with one intermediate level (s = 8)
+    d = diskgen.workload("disk32768")
+    xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+    big = {}
+    for name, kw in (("plain", None), ("hybrid", {}), ("levels1_s8", {"levels": 1, "substeps": 8})):
+        X = torch.tensor(xm, device="cuda:0")
+        V = torch.tensor(v4, device="cuda:0")
+        thr = ctx.rcrit(X, V)
+        e0 = ctx.energy(X, V, thr)
+        if kw is None:
+            sec, st = timed(lambda: ctx.step(X, V, 10, thr=thr))
+            st = None
+        else:
+            sec, st = timed(lambda: ctx.step_hybrid(X, V, 10, thr=thr, **kw))
+        e1 = ctx.energy(X, V, thr)
+        big[name] = {"ms_per_step": round(sec * 100, 4),
+                     "E_rel_drift": float(abs(e1["E"] - e0["E"]) / abs(e0["E"]))}
+        if st is not None:
+            big[name]["groups"] = {k: st[k] for k in ("groups", "largest", "bodies", "too_large")}
+    out["disk32768_10_steps"] = big
     return out
 
 

@@ -54,6 +54,7 @@ def _lib():
         "or_step_merge": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P, P, D, P, P, I, P]),
         "or_level_kick_acc": (None, [I, P, P, P, I, P, ctypes.c_int, P, P]),
         "or_ce_drift_group_levels": (ctypes.c_int, [P, ctypes.c_int, P, P, P, P, ctypes.c_int, P, D, D]),
+        "or_drift_levels": (ctypes.c_int, [I, P, P, P, P, I, P, P, P, ctypes.c_int, ctypes.c_int, P, D, D]),
         "or_step_levels": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P, ctypes.c_int, ctypes.c_int,
                                           P, D, P, P, I, P]),
         "or_jump": (None, [I, P, P, P, P, D]),
@@ -247,6 +248,17 @@ def ce_drift_group_levels(x, v, m, rc_levels, p, idx, h, tol=1e-18):
     rcl = np.ascontiguousarray(np.asarray(rc_levels, dtype=np.float64)[:, idx])
     st = _lib().or_ce_drift_group_levels(_p(idx), len(idx), _p(x), _p(v), _p(_f64(m)), _p(rcl), rcl.shape[0],
                                          _p(_prm(p)), float(h), float(tol))
+    return x, v, st
+
+
+def drift_levels(x, v, m, pairs, thr_levels, p, levels, substeps, h, tol=1e-18):
+    """The drift A(h) alone through `levels` intermediate levels; thr_levels = (rc, H, V), each
+    [levels + 1][n]; pairs: the step's close pairs. Returns x, v, status."""
+    x = _f64(x).copy(); v = _f64(v).copy()
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    rc, H, V = (np.ascontiguousarray(t, dtype=np.float64) for t in thr_levels)
+    st = _lib().or_drift_levels(len(m), _p(x), _p(v), _p(_f64(m)), _p(pr), pr.shape[0], _p(rc), _p(H), _p(V),
+                                int(levels), int(substeps), _p(_prm(p)), float(h), float(tol))
     return x, v, st
 
 

@@ -1051,6 +1051,28 @@ int or_ce_drift_group_levels(const int64_t *idx, int k, double *x, double *v, co
   return st;
 }
 
+// The drift A(h) alone with L intermediate levels (substep factor sub), long double: the bodies
+// without listed pairs follow Kepler orbits, the others go through the levels with the pairs as
+// the step's close pairs. rc, H, V: [L + 1][n] level thresholds. Returns the integrator status.
+int or_drift_levels(int64_t n, double *x, double *v, const double *m, const int32_t *pairs, int64_t np,
+                    const double *rc, const double *H, const double *V, int L, int sub, const double *prm,
+                    double h, double tol) {
+  Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
+  Levels lv{L, sub, n, std::vector<double>(rc, rc + (size_t)(L + 1) * n),
+            std::vector<double>(H, H + (size_t)(L + 1) * n), std::vector<double>(V, V + (size_t)(L + 1) * n)};
+  std::vector<long double> xl(x, x + 3 * n), vl(v, v + 3 * n);
+  std::vector<double> mm(m, m + n);
+  std::vector<char> inP0(n, 0);
+  for (int64_t e = 0; e < np; e++) inP0[pairs[2 * e]] = inP0[pairs[2 * e + 1]] = 1;
+  int worst = 0;
+  for (int64_t i = 0; i < n; i++)
+    if (!inP0[i]) worst = std::max(worst, kepler<long double>(&xl[3 * i], &vl[3 * i], p.G * p.m0, h));
+  worst = std::max(worst, drift_levels<long double>(n, xl.data(), vl.data(), mm.data(), pairs, np, inP0, lv, p, 0,
+                                                    h, tol, nullptr, nullptr, nullptr));
+  for (int64_t i = 0; i < 3 * n; i++) { x[i] = (double)xl[i]; v[i] = (double)vl[i]; }
+  return worst;
+}
+
 // nsteps hybrid steps with L intermediate changeover levels (time steps dt / s^l) and, when R is
 // given, collisions as perfect mergers (radius factor f; m and R in/out, mergers logged).
 int or_step_levels(int64_t n, double *x, double *v, double *m, const double *prm, int nsteps,
