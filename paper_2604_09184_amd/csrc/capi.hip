@@ -31,7 +31,7 @@ enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MO
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GMARK, B_GIN, B_GSIZE,
              B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_HGOUT, B_LTHR, B_ADEG, B_AOFF,
-             B_AFILL, B_ADJ, B_LSKIP, B_NUM };
+             B_AFILL, B_ADJ, B_LSKIP, B_AOWN, B_ATERM, B_ATOT, B_NUM };
 
 }  // namespace
 
@@ -304,7 +304,7 @@ int group_bufs(nbody_ctx *c, int n, GroupBufs &g) {
   g.gfill = (int *)ensure(c, B_GFILL, b);
   g.gmem = (int *)ensure(c, B_GMEM, b);
   g.groot = (int *)ensure(c, B_GROOT, b);
-  g.counter = (int *)ensure(c, B_GCNT, sizeof(int));
+  g.counter = (int *)ensure(c, B_GCNT, 2 * sizeof(int));
   if (!g.mark || !g.in || !g.gsize || !g.gstart || !g.gfill || !g.gmem || !g.groot || !g.counter)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
   return NBODY_OK;
@@ -626,15 +626,19 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   LevelThr lt{};
   lt.thr[0] = T;
   lt.nl = L + 1;
-  int *deg = nullptr, *off = nullptr, *fill = nullptr, *adj = nullptr, *lskip = nullptr;
+  LevelAdj la{};
+  int *lskip = nullptr;
   if (L > 0) {
     double4 *lthr = (double4 *)ensure(c, B_LTHR, (size_t)L * n * sizeof(double4));
-    deg = (int *)ensure(c, B_ADEG, (size_t)n * sizeof(int));
-    off = (int *)ensure(c, B_AOFF, (size_t)n * sizeof(int));
-    fill = (int *)ensure(c, B_AFILL, (size_t)n * sizeof(int));
-    adj = (int *)ensure(c, B_ADJ, (size_t)cap * 2 * sizeof(int));
+    la.deg = (int *)ensure(c, B_ADEG, (size_t)n * sizeof(int));
+    la.off = (int *)ensure(c, B_AOFF, (size_t)n * sizeof(int));
+    la.fill = (int *)ensure(c, B_AFILL, (size_t)n * sizeof(int));
+    la.adj = (int *)ensure(c, B_ADJ, (size_t)cap * 2 * sizeof(int));
+    la.own = (int *)ensure(c, B_AOWN, (size_t)cap * 2 * sizeof(int));
+    la.term = (double4 *)ensure(c, B_ATERM, (size_t)cap * 2 * sizeof(double4));
+    la.total = (int *)ensure(c, B_ATOT, sizeof(int));
     lskip = (int *)ensure(c, B_LSKIP, (size_t)n * sizeof(int));
-    if (!lthr || !deg || !off || !fill || !adj || !lskip)
+    if (!lthr || !la.deg || !la.off || !la.fill || !la.adj || !la.own || !la.term || !la.total || !lskip)
       return fail(c, NBODY_E_NOMEM, "workspace allocation failed (changeover levels)");
     const double cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
     double dtl = p.dt;
@@ -652,7 +656,7 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     if (L == 0)
       HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.mark, gout, ublocks, st), "groups");
     else
-      HIPCHK(c, launch_adjacency(lpairs, cap, lcount, N, deg, off, fill, adj, st), "adjacency");
+      HIPCHK(c, launch_adjacency(lpairs, cap, lcount, N, la, st), "adjacency");
     return NBODY_OK;
   };
   int step = 0;
@@ -668,15 +672,15 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
       cc.step = step;
       HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
                                 p.f_in, tau, kCeTol, S, cc, lt, st), "close-encounter drift");
-      HIPCHK(c, launch_level_mask(deg, g.in, N, lskip, st), "level mask");
+      HIPCHK(c, launch_level_mask(la.deg, g.in, N, lskip, st), "level mask");
       HIPCHK(c, launch_drift(X, Vv, N, tau, mu, nullptr, st, lskip), "level drift");
       return NBODY_OK;
     }
     const double ts = tau / sub;
     for (int k = 0; k < sub; ++k) {
-      HIPCHK(c, launch_level_kick(X, Vv, off, deg, adj, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
+      HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
       TRY(drift_levels(l + 1, ts));
-      HIPCHK(c, launch_level_kick(X, Vv, off, deg, adj, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
+      HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
     }
     return NBODY_OK;
   };
@@ -698,7 +702,7 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     } else {
       // first jump for all; Kepler drift for the bodies without close partners; the others
       // through the levels
-      HIPCHK(c, launch_level_mask(deg, nullptr, N, lskip, st), "level mask");
+      HIPCHK(c, launch_level_mask(la.deg, nullptr, N, lskip, st), "level mask");
       HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
                                   lskip), "jump+drift");
       TRY(drift_levels(0, p.dt));

@@ -32,7 +32,10 @@ __global__ __launch_bounds__(kBlock) void k_gmark(const int *__restrict__ label,
     gsize[i] = 0;
     gfill[i] = 0;
   }
-  if (i == 0) *counter = 0;
+  if (i == 0) {
+    counter[0] = 0;
+    counter[1] = 0;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_gmark2(const int *__restrict__ label, int n,
@@ -52,28 +55,12 @@ __global__ __launch_bounds__(kBlock) void k_gsize(const int *__restrict__ label,
   if (g) atomicAdd(gsize + r, 1);
 }
 
-// Exclusive prefix sum of gsize over n roots (one workgroup; each thread a contiguous segment).
-__global__ __launch_bounds__(1024) void k_gscan(const int *__restrict__ gsize, int n,
-                                                int *__restrict__ gstart) {
-  __shared__ int lds[1024];
-  const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int b0 = t * per, b1 = min(n, b0 + per);
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += gsize[b];
-  lds[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int add = t >= o ? lds[t - o] : 0;
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
-  }
-  int run = lds[t] - s;
-  for (int b = b0; b < b1; ++b) {
-    gstart[b] = run;
-    run += gsize[b];
-  }
+// Slices of the member array by atomic allocation (counter[1]): where a group's slice sits does
+// not matter, each group is integrated on its own with its members ordered by body index.
+__global__ __launch_bounds__(kBlock) void k_galloc(const int *__restrict__ gsize, int n,
+                                                   int *__restrict__ gstart, int *__restrict__ counter) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && gsize[i] > 0) gstart[i] = atomicAdd(counter + 1, gsize[i]);
 }
 
 // Members into their group's slots (slot order is arbitrary; the integrator orders them by body
@@ -639,7 +626,7 @@ hipError_t launch_group_lists(const int *label, int n, int *mark, int *in, int *
                      counter);
   hipLaunchKernelGGL(k_gmark2, dim3(nblocks(n)), dim3(kBlock), 0, st, label, n, mark);
   hipLaunchKernelGGL(k_gsize, dim3(nblocks(n)), dim3(kBlock), 0, st, label, mark, n, in, gsize);
-  hipLaunchKernelGGL(k_gscan, dim3(1), dim3(1024), 0, st, gsize, n, gstart);
+  hipLaunchKernelGGL(k_galloc, dim3(nblocks(n)), dim3(kBlock), 0, st, gsize, n, gstart, counter);
   hipLaunchKernelGGL(k_gfill, dim3(nblocks(n)), dim3(kBlock), 0, st, label, in, n, gstart, gfill,
                      gmem, groot, counter);
   return hipGetLastError();

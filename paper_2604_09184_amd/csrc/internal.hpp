@@ -90,11 +90,16 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
 
 // levels.hip: symmetric adjacency of a pair list (rows sorted by neighbour index), the level kicks
 // over it and the masks of the level drifts.
-hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n, int *deg,
-                            int *off, int *fill, int *adj, hipStream_t st);
-hipError_t launch_level_kick(const double4 *xm, double4 *v, const int *off, const int *deg,
-                             const int *adj, int n, const LevelThr &lt, int level, double G,
-                             double f_in, double h, hipStream_t st);
+// deg/off/fill [n]; adj/own [2 cap] (neighbour and row body per slot); term [2 cap]; total: slots used.
+struct LevelAdj {
+  int *deg, *off, *fill, *adj, *own, *total;
+  double4 *term;
+};
+hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
+                            const LevelAdj &g, hipStream_t st);
+hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int64_t max_edges, int n,
+                             const LevelThr &lt, int level, double G, double f_in, double h,
+                             hipStream_t st);
 // skip[i] = 1 unless body i has a listed partner (deg > 0) and is outside the groups (in == 0);
 // with in null: skip[i] = (deg[i] > 0).
 hipError_t launch_level_mask(const int *deg, const int *in, int n, int *skip, hipStream_t st);

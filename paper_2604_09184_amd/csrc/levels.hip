@@ -5,20 +5,26 @@
 // acting on the step's close pairs with the potential -G m_i m_j W_l K_{l+1} / r,
 // W_l = prod_{i <= l} [1 - K_i]. This file holds the kick and its bookkeeping; the orchestration
 // is on the host and the deepest level runs the close-encounter integrator.
-#include <algorithm>
-
 #include "internal.hpp"
 
 namespace nbk {
 
 // ------------------------------------------------------------------ adjacency of a pair list
 __global__ __launch_bounds__(kBlock) void k_adj_zero(int *__restrict__ deg, int *__restrict__ fill,
-                                                     int n) {
+                                                     int n, int *__restrict__ total) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) {
     deg[i] = 0;
     fill[i] = 0;
   }
+  if (i == 0) *total = 0;
+}
+
+// Row slots by atomic allocation: where a row sits does not matter (each row is used on its own).
+__global__ __launch_bounds__(kBlock) void k_adj_alloc(const int *__restrict__ deg, int n,
+                                                      int *__restrict__ off, int *__restrict__ total) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && deg[i] > 0) off[i] = atomicAdd(total, deg[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_adj_count(const int32_t *__restrict__ pairs, int64_t cap,
@@ -33,28 +39,44 @@ __global__ __launch_bounds__(kBlock) void k_adj_count(const int32_t *__restrict_
   }
 }
 
+// adj[slot] = neighbour, own[slot] = the row's body.
 __global__ __launch_bounds__(kBlock) void k_adj_fill(const int32_t *__restrict__ pairs, int64_t cap,
                                                      const int64_t *__restrict__ count, int n,
                                                      const int *__restrict__ off,
-                                                     int *__restrict__ fill, int *__restrict__ adj) {
+                                                     int *__restrict__ fill, int *__restrict__ adj,
+                                                     int *__restrict__ own) {
   const int64_t np = min(*count, cap);
   for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < np; e += (int64_t)gridDim.x * kBlock) {
     const int i = pairs[2 * e], j = pairs[2 * e + 1];
     if (i < 0 || j < 0 || i >= n || j >= n || i == j) continue;
-    adj[off[i] + atomicAdd(fill + i, 1)] = j;
-    adj[off[j] + atomicAdd(fill + j, 1)] = i;
+    const int si = off[i] + atomicAdd(fill + i, 1), sj = off[j] + atomicAdd(fill + j, 1);
+    adj[si] = j;
+    own[si] = i;
+    adj[sj] = i;
+    own[sj] = j;
   }
 }
 
-// Each row in ascending neighbour index (insertion sort: rows are short), so that the kicks sum
-// in an order that does not depend on the atomics above.
+// Each row in ascending neighbour index, so that the kicks sum in an order that does not depend on
+// the atomics above: one wave per row; a row of up to 64 entries is placed by rank (the entries
+// are distinct), a longer one by insertion sort in one lane.
 __global__ __launch_bounds__(kBlock) void k_adj_sort(const int *__restrict__ off,
                                                      const int *__restrict__ deg, int n,
                                                      int *__restrict__ adj) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  int *row = adj + off[i];
   const int d = deg[i];
+  if (d < 2) return;
+  int *row = adj + off[i];
+  if (d <= 64) {
+    const int a = lane < d ? row[lane] : 0x7fffffff;
+    int rank = 0;
+    for (int m = 0; m < d; ++m) rank += __shfl(a, m, 64) < a;
+    if (lane < d) row[rank] = a;
+    return;
+  }
+  if (lane != 0) return;
   for (int a = 1; a < d; ++a) {
     const int key = row[a];
     int b = a - 1;
@@ -77,43 +99,52 @@ __device__ __forceinline__ void level_K(double r, double rcij, double f_in, doub
   dK = 2.0 * y * (1.0 - y) / (D * D) / span;
 }
 
-// v_i += h G sum_j m_j (V/r^3 - V'(r)/r^2) d_ij over body i's listed partners (ascending j),
-// V = W_{level-1} K_level.
-__global__ __launch_bounds__(kBlock) void k_level_kick(const double4 *__restrict__ xm,
-                                                       double4 *__restrict__ v,
-                                                       const int *__restrict__ off,
-                                                       const int *__restrict__ deg,
-                                                       const int *__restrict__ adj, int n,
+// Term of one directed edge (row body i, neighbour j): G m_j (V/r^3 - V'(r)/r^2) d_ij with
+// V = W_{level-1} K_level, into term[slot].
+__global__ __launch_bounds__(kBlock) void k_level_edge(const double4 *__restrict__ xm,
+                                                       const int *__restrict__ adj,
+                                                       const int *__restrict__ own,
+                                                       const int *__restrict__ total,
                                                        LevelThr lt, int level, double G,
-                                                       double f_in, double h) {
+                                                       double f_in, double4 *__restrict__ term) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= *total) return;
+  const int i = own[q], j = adj[q];
+  const double4 p = xm[i], pj = xm[j];
+  const double dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r = sqrt(r2);
+  double W = 1.0, dW = 0.0;
+  for (int l = 0; l < level; ++l) {
+    const double rcij = fmax(lt.thr[l][i].x, lt.thr[l][j].x);
+    double K, dK;
+    level_K(r, rcij, f_in, K, dK);
+    dW = dW * (1.0 - K) - W * dK;
+    W = W * (1.0 - K);
+  }
+  double K, dK;
+  level_K(r, fmax(lt.thr[level][i].x, lt.thr[level][j].x), f_in, K, dK);
+  const double V = W * K, dV = dW * K + W * dK;
+  const double c = G * pj.w * (V / (r2 * r) - dV / r2);
+  term[q] = make_double4(c * dx, c * dy, c * dz, 0.0);
+}
+
+// v_i += h sum of the row's terms, in the row's (ascending neighbour) order.
+__global__ __launch_bounds__(kBlock) void k_level_sum(const int *__restrict__ off,
+                                                      const int *__restrict__ deg,
+                                                      const double4 *__restrict__ term, int n,
+                                                      double h, double4 *__restrict__ v) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int d = deg[i];
   if (d == 0) return;
-  const int *row = adj + off[i];
-  const double4 p = xm[i];
+  const double4 *t = term + off[i];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int q = 0; q < d; ++q) {
-    const int j = row[q];
-    const double4 pj = xm[j];
-    const double dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    double W = 1.0, dW = 0.0;
-    for (int l = 0; l < level; ++l) {
-      const double rcij = fmax(lt.thr[l][i].x, lt.thr[l][j].x);
-      double K, dK;
-      level_K(r, rcij, f_in, K, dK);
-      dW = dW * (1.0 - K) - W * dK;
-      W = W * (1.0 - K);
-    }
-    double K, dK;
-    level_K(r, fmax(lt.thr[level][i].x, lt.thr[level][j].x), f_in, K, dK);
-    const double V = W * K, dV = dW * K + W * dK;
-    const double c = G * pj.w * (V / (r2 * r) - dV / r2);
-    a0 += c * dx;
-    a1 += c * dy;
-    a2 += c * dz;
+    const double4 u = t[q];
+    a0 += u.x;
+    a1 += u.y;
+    a2 += u.z;
   }
   double4 u = v[i];
   u.x += h * a0;
@@ -130,48 +161,28 @@ __global__ __launch_bounds__(kBlock) void k_level_mask(const int *__restrict__ d
   skip[i] = in ? !(deg[i] > 0 && !in[i]) : (deg[i] > 0);
 }
 
-// One workgroup's exclusive prefix sum (as for the group slices).
-__global__ __launch_bounds__(1024) void k_adj_scan(const int *__restrict__ deg, int n,
-                                                   int *__restrict__ off) {
-  __shared__ int lds[1024];
-  const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int b0 = t * per, b1 = min(n, b0 + per);
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += deg[b];
-  lds[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int add = t >= o ? lds[t - o] : 0;
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
-  }
-  int run = lds[t] - s;
-  for (int b = b0; b < b1; ++b) {
-    off[b] = run;
-    run += deg[b];
-  }
-}
-
-hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n, int *deg,
-                            int *off, int *fill, int *adj, hipStream_t st) {
+hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
+                            const LevelAdj &g, hipStream_t st) {
   const int blocks = (int)std::min<int64_t>(4096, (cap + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_adj_zero, dim3(nblocks(n)), dim3(kBlock), 0, st, deg, fill, n);
+  hipLaunchKernelGGL(k_adj_zero, dim3(nblocks(n)), dim3(kBlock), 0, st, g.deg, g.fill, n, g.total);
   if (blocks > 0)
-    hipLaunchKernelGGL(k_adj_count, dim3(blocks), dim3(kBlock), 0, st, pairs, cap, count, n, deg);
-  hipLaunchKernelGGL(k_adj_scan, dim3(1), dim3(1024), 0, st, deg, n, off);
+    hipLaunchKernelGGL(k_adj_count, dim3(blocks), dim3(kBlock), 0, st, pairs, cap, count, n, g.deg);
+  hipLaunchKernelGGL(k_adj_alloc, dim3(nblocks(n)), dim3(kBlock), 0, st, g.deg, n, g.off, g.total);
   if (blocks > 0)
-    hipLaunchKernelGGL(k_adj_fill, dim3(blocks), dim3(kBlock), 0, st, pairs, cap, count, n, off, fill, adj);
-  hipLaunchKernelGGL(k_adj_sort, dim3(nblocks(n)), dim3(kBlock), 0, st, off, deg, n, adj);
+    hipLaunchKernelGGL(k_adj_fill, dim3(blocks), dim3(kBlock), 0, st, pairs, cap, count, n, g.off, g.fill,
+                       g.adj, g.own);
+  hipLaunchKernelGGL(k_adj_sort, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st, g.off,
+                     g.deg, n, g.adj);
   return hipGetLastError();
 }
 
-hipError_t launch_level_kick(const double4 *xm, double4 *v, const int *off, const int *deg,
-                             const int *adj, int n, const LevelThr &lt, int level, double G,
-                             double f_in, double h, hipStream_t st) {
-  hipLaunchKernelGGL(k_level_kick, dim3(nblocks(n)), dim3(kBlock), 0, st, xm, v, off, deg, adj, n, lt,
-                     level, G, f_in, h);
+hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int64_t max_edges, int n,
+                             const LevelThr &lt, int level, double G, double f_in, double h,
+                             hipStream_t st) {
+  if (max_edges > 0)
+    hipLaunchKernelGGL(k_level_edge, dim3(nblocks(max_edges)), dim3(kBlock), 0, st, xm, g.adj, g.own,
+                       g.total, lt, level, G, f_in, g.term);
+  hipLaunchKernelGGL(k_level_sum, dim3(nblocks(n)), dim3(kBlock), 0, st, g.off, g.deg, g.term, n, h, v);
   return hipGetLastError();
 }
 
