@@ -58,8 +58,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_fill(const int32_t *__restrict__
 }
 
 // Each row in ascending neighbour index, so that the kicks sum in an order that does not depend on
-// the atomics above: one wave per row; a row of up to 64 entries is placed by rank (the entries
-// are distinct), a longer one by insertion sort in one lane.
+// the atomics above: one wave per row; a row of up to 256 entries is placed by rank (the entries
+// are distinct; lane l holds entries l, l + 64, ...), a longer one by insertion sort in one lane.
+constexpr int kSortChunks = 4;
 __global__ __launch_bounds__(kBlock) void k_adj_sort(const int *__restrict__ off,
                                                      const int *__restrict__ deg, int n,
                                                      int *__restrict__ adj) {
@@ -69,11 +70,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_sort(const int *__restrict__ off
   const int d = deg[i];
   if (d < 2) return;
   int *row = adj + off[i];
-  if (d <= 64) {
-    const int a = lane < d ? row[lane] : 0x7fffffff;
-    int rank = 0;
-    for (int m = 0; m < d; ++m) rank += __shfl(a, m, 64) < a;
-    if (lane < d) row[rank] = a;
+  if (d <= 64 * kSortChunks) {
+    int a[kSortChunks], rank[kSortChunks];
+#pragma unroll
+    for (int c = 0; c < kSortChunks; ++c) {
+      a[c] = c * 64 + lane < d ? row[c * 64 + lane] : 0x7fffffff;
+      rank[c] = 0;
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < kSortChunks; ++c2) {
+      if (c2 * 64 >= d) break;
+      const int lim = min(64, d - c2 * 64);
+      for (int m = 0; m < lim; ++m) {
+        const int x = __shfl(a[c2], m, 64);
+#pragma unroll
+        for (int c = 0; c < kSortChunks; ++c) rank[c] += x < a[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kSortChunks; ++c)
+      if (c * 64 + lane < d) row[rank[c]] = a[c];
     return;
   }
   if (lane != 0) return;
@@ -129,28 +145,38 @@ __global__ __launch_bounds__(kBlock) void k_level_edge(const double4 *__restrict
   term[q] = make_double4(c * dx, c * dy, c * dz, 0.0);
 }
 
-// v_i += h sum of the row's terms, in the row's (ascending neighbour) order.
+// v_i += h sum of the row's terms: one wave per row, lane l adding the terms l, l + 64, ... of the
+// sorted row, then a butterfly of commutative additions (the same bits on every lane).
 __global__ __launch_bounds__(kBlock) void k_level_sum(const int *__restrict__ off,
                                                       const int *__restrict__ deg,
                                                       const double4 *__restrict__ term, int n,
                                                       double h, double4 *__restrict__ v) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
   const int d = deg[i];
   if (d == 0) return;
   const double4 *t = term + off[i];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int q = 0; q < d; ++q) {
+  for (int q = lane; q < d; q += 64) {
     const double4 u = t[q];
     a0 += u.x;
     a1 += u.y;
     a2 += u.z;
   }
-  double4 u = v[i];
-  u.x += h * a0;
-  u.y += h * a1;
-  u.z += h * a2;
-  v[i] = u;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    a0 += __shfl_xor(a0, o, 64);
+    a1 += __shfl_xor(a1, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
+  if (lane == 0) {
+    double4 u = v[i];
+    u.x += h * a0;
+    u.y += h * a1;
+    u.z += h * a2;
+    v[i] = u;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_level_mask(const int *__restrict__ deg,
@@ -182,7 +208,8 @@ hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, i
   if (max_edges > 0)
     hipLaunchKernelGGL(k_level_edge, dim3(nblocks(max_edges)), dim3(kBlock), 0, st, xm, g.adj, g.own,
                        g.total, lt, level, G, f_in, g.term);
-  hipLaunchKernelGGL(k_level_sum, dim3(nblocks(n)), dim3(kBlock), 0, st, g.off, g.deg, g.term, n, h, v);
+  hipLaunchKernelGGL(k_level_sum, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st, g.off,
+                     g.deg, g.term, n, h, v);
   return hipGetLastError();
 }
 
