@@ -227,6 +227,28 @@ def variant_hybrid(nb, p):
     return out
 
 
+def variant_small_n(nb, p):
+    """Small systems: per-step launches (nbody_step) against the self-tuned switch (one persistent
+    launch when that is faster) for disks of 32 ... 2048 bodies, 200 steps each."""
+    import torch
+
+    import diskgen
+    ctx = nb.Context(nb.Params(**p))
+    out = {"steps": 200, "sizes": {}}
+    for n in (32, 64, 128, 256, 2048):
+        d = diskgen.workload("disk2048", n=n)
+        xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
+        X = torch.tensor(xm, device="cuda:0")
+        V = torch.tensor(v4, device="cuda:0")
+        path = ctx.autotune_step(X, V, ntrial=20)
+        ctx.step(X.clone(), V.clone(), 5)
+        t_plain, _ = timed(lambda: ctx.step(X, V, 200))
+        t_auto, _ = timed(lambda: ctx.step_auto(X, V, 200))
+        out["sizes"][str(n)] = {"path": path, "per_step_launches_us": round(t_plain / 200 * 1e6, 2),
+                                "switch_us": round(t_auto / 200 * 1e6, 2)}
+    return out
+
+
 def cpu_baseline(budget_s=25.0):
     """The oracle (plain C++, OpenMP) on the first steps of the same N = 32768 disk."""
     import numpy as np
@@ -260,7 +282,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)   # the clock ramps up over the first ~0.2 s of load
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--only", choices=["split", "batched", "adjoint", "hybrid"],
+    ap.add_argument("--only", choices=["split", "batched", "adjoint", "hybrid", "small_n"],
                     help="run only this variant and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -280,7 +302,7 @@ def main():
     if args.only:
         p = diskgen.PARAMS
         fn = {"split": variant_split, "batched": variant_batched, "adjoint": variant_adjoint,
-              "hybrid": variant_hybrid}[args.only]
+              "hybrid": variant_hybrid, "small_n": variant_small_n}[args.only]
         print(json.dumps({args.only: fn(nb, p)}), flush=True)
         return
     if args.calibrate_copy:
@@ -349,6 +371,8 @@ def main():
         variants["adjoint"] = variant_adjoint(nb, p)
         print("[bench] variant: hybrid step (disk2048)", file=sys.stderr, flush=True)
         variants["hybrid"] = variant_hybrid(nb, p)
+        print("[bench] variant: small-N switch", file=sys.stderr, flush=True)
+        variants["small_n"] = variant_small_n(nb, p)
 
     out = {
         "metric": METRIC,

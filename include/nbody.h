@@ -220,6 +220,27 @@ int nbody_step_hybrid(nbody_ctx *ctx, int64_t n, double *xm, double *v, const do
                       int64_t *stats, void *stream);
 
 /*
+ * Small-N switch. The paper notes that small systems leave a GPU idle, dominated by per-kernel
+ * overhead, and that self-tuning routines pick the fastest integration setup for a problem size
+ * (section "The GENGA code"). Here a single system advances either with nbody_step's per-step
+ * launches (path 0) or in one persistent launch of the ensemble kernel of nbody_step_batched
+ * (paths 1 and 2: its group and wave tiles; binary64, n <= 2048, resp. n <= 256), which removes the
+ * launch latency per step; the two agree to about 1e-12 relative, not bit for bit.
+ * nbody_autotune_step times every admissible path for ntrial steps on scratch copies of (xm, v)
+ * (inputs unchanged), records the fastest for this n in the context, and writes it to *choice
+ * (host int32, may be NULL). It synchronizes the stream.
+ */
+int nbody_autotune_step(nbody_ctx *ctx, int64_t n, const double *xm, const double *v, int32_t ntrial,
+                        int32_t *choice, void *stream);
+
+/*
+ * nsteps steps of one system of n bodies in place with the path recorded for n by
+ * nbody_autotune_step (path 0, identical to nbody_step with thr = NULL, if n was never tuned).
+ * Thresholds are taken at the call's start.
+ */
+int nbody_step_auto(nbody_ctx *ctx, int64_t n, double *xm, double *v, int32_t nsteps, void *stream);
+
+/*
  * Input check before integrating a state. The method has no softening, so a body at the central
  * mass (r_i = 0 in eq. Ha) or two bodies at one position (r_ij = 0 in eq. Hb) are invalid input.
  * result (device int64 [2]) receives {i, reason} for the smallest body index i with a problem

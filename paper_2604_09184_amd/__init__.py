@@ -82,6 +82,8 @@ EXPORTS = {
     "nbody_step_vjp": [_I64, _P, _P, _P, _I32, _P, _P, _P],
     "nbody_step_batched": [_I32, _P, _P, _P, _I32, _P, _P],
     "nbody_autotune_batched": [_I32, _P, _P, _P, _I32, _P],
+    "nbody_autotune_step": [_I64, _P, _P, _I32, _P, _P],
+    "nbody_step_auto": [_I64, _P, _P, _I32, _P],
     "nbody_get_batched_tiles": [_P, _I32],
     "nbody_set_batched_tiles": [_P, _I32],
 }
@@ -380,6 +382,21 @@ class Context:
         self._check(lib().nbody_autotune_batched(self._h, len(o) - 1, op, _ptr(xm), _ptr(v), int(nsteps),
                                                  _stream()), "nbody_autotune_batched")
         return self.batched_tiles()
+
+    def autotune_step(self, xm, v, ntrial=20):
+        """Times nbody_step's per-step launches against one persistent launch for this system size
+        (on copies) and records the faster; returns the path (0 per-step, 1/2 persistent)."""
+        _body(xm, "xm"); _body(v, "v")
+        ch = ctypes.c_int32(-1)
+        self._check(lib().nbody_autotune_step(self._h, xm.shape[0], _ptr(xm), _ptr(v), int(ntrial),
+                                              ctypes.byref(ch), _stream()), "nbody_autotune_step")
+        return ch.value
+
+    def step_auto(self, xm, v, nsteps):
+        """nsteps steps in place with the path recorded by autotune_step for this size."""
+        _body(xm, "xm"); _body(v, "v")
+        self._check(lib().nbody_step_auto(self._h, xm.shape[0], _ptr(xm), _ptr(v), int(nsteps), _stream()),
+                    "nbody_step_auto")
 
     def batched_tiles(self):
         t = (ctypes.c_int32 * 6)()

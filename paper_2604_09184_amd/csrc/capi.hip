@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <functional>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -47,6 +48,7 @@ struct nbody_ctx {
   // 0 = one workgroup per system
   int32_t tiles[nbk::kBuckets] = {0, 0, 0, 0, 0, 0};
   bool tuned = false;
+  std::map<int64_t, int32_t> step_path;   // n -> path chosen by nbody_autotune_step
   std::vector<int64_t> h_offs;   // host staging kept alive across asynchronous copies
   std::vector<int32_t> h_order;
 };
@@ -868,6 +870,78 @@ int nbody_step_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, double *
   c->h_offs.assign(offs, offs + nsys + 1);
   return run_batched(c, nsys, c->tiles, (double4 *)xm, (double4 *)v, nsteps, (unsigned long long *)npairs,
                      (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ small-N switch
+// Paths: 0 = nbody_step's per-step launches; 1 and 2 = one persistent launch of the ensemble kernel
+// for the single system (group tile, wave tile).
+int run_step_path(nbody_ctx *c, int64_t n, double *xm, double *v, int32_t nsteps, int32_t path,
+                  hipStream_t st) {
+  if (path == 0)
+    return nbody_step(c, n, xm, v, nullptr, nsteps, nullptr, 0, nullptr, nullptr, st);
+  int32_t tiles[kBuckets];
+  std::fill(tiles, tiles + kBuckets, path == 2 ? 1 : 0);
+  c->h_offs.assign({0, n});
+  return run_batched(c, 1, tiles, (double4 *)xm, (double4 *)v, nsteps, nullptr, st);
+}
+
+int nbody_autotune_step(nbody_ctx *c, int64_t n, const double *xm, const double *v, int32_t ntrial,
+                        int32_t *choice, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  if (ntrial < 1) return fail(c, NBODY_E_INVAL, "ntrial < 1");
+  hipStream_t st = (hipStream_t)stream;
+  double *txm = (double *)ensure(c, B_T_XM, (size_t)n * sizeof(double4));
+  double *tv = (double *)ensure(c, B_T_V, (size_t)n * sizeof(double4));
+  if (!txm || !tv) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (autotune)");
+  std::vector<int32_t> paths = {0};
+  if (c->p.precision == NBODY_PREC_F64 && n <= (1 << (kBuckets + 5))) paths.push_back(1);
+  if (c->p.precision == NBODY_PREC_F64 && n <= batched_max_wave_n()) paths.push_back(2);
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0), "event");
+  HIPCHK(c, hipEventCreate(&e1), "event");
+  std::vector<float> total(paths.size(), 0.f);
+  int rc = NBODY_OK;
+  // a warm-up run of every path, then the order a, b, c, c, b, a (cancels a linear clock drift)
+  for (int pass = 0; pass < 3 && rc == NBODY_OK; ++pass)
+    for (size_t k = 0; k < paths.size() && rc == NBODY_OK; ++k) {
+      const size_t q = pass == 2 ? paths.size() - 1 - k : k;
+      if ((rc = hipMemcpyAsync(txm, xm, (size_t)n * sizeof(double4), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+          (rc = hipMemcpyAsync(tv, v, (size_t)n * sizeof(double4), hipMemcpyDeviceToDevice, st)) != hipSuccess) {
+        rc = fail(c, NBODY_E_HIP, "copy");
+        break;
+      }
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(c, NBODY_E_HIP, "event"); break; }
+      rc = run_step_path(c, n, txm, tv, ntrial, paths[q], st);
+      if (rc != NBODY_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(c, NBODY_E_HIP, "event");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (pass > 0) total[q] += ms;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != NBODY_OK) return rc;
+  size_t best = 0;
+  for (size_t q = 1; q < paths.size(); ++q)
+    if (total[q] < total[best]) best = q;
+  c->step_path[n] = paths[best];
+  if (choice) *choice = paths[best];
+  return NBODY_OK;
+}
+
+int nbody_step_auto(nbody_ctx *c, int64_t n, double *xm, double *v, int32_t nsteps, void *stream) {
+  TRY(check_n(c, n));
+  TRY(check_dev(c, xm, "xm", true));
+  TRY(check_dev(c, v, "v", true));
+  if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
+  const auto it = c->step_path.find(n);
+  const int32_t path = it == c->step_path.end() ? 0 : it->second;
+  return run_step_path(c, n, xm, v, nsteps, path, (hipStream_t)stream);
 }
 
 int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, const double *xm,

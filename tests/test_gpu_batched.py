@@ -149,3 +149,34 @@ def test_full_ensemble_in_bench_configuration(nb):
         # rounding differences grow by about 1e3 over 100 steps of these disks
         assert ex < 1e-10 and ev < 1e-10
         assert npairs[s] == len(oracle.encounters(ox, othr))
+
+
+# ------------------------------------------------------------------ small-N switch
+def test_small_n_switch_picks_the_persistent_launch_for_small_systems(nb):
+    """At N = 64 one persistent launch beats per-step launches by ~3x and the tuner records it; the
+    auto step then agrees with nbody_step to ~1e-12 (another summation order). At N = 2048 the
+    per-step launches win by more than 30x and the auto step is nbody_step bit for bit; a size never
+    tuned also runs nbody_step."""
+    say("small-N switch")
+    ctx = nb.Context(nb.Params(**diskgen.PARAMS))
+    for n, persistent in ((64, True), (2048, False)):
+        d = diskgen.workload("disk2048", n=n)
+        X, V = to_dev(d["x"], d["v"], d["m"])
+        path = ctx.autotune_step(X, V, ntrial=20)
+        say(f"  n={n}: path {path}")
+        assert (path in (1, 2)) == persistent
+        X1, V1 = X.clone(), V.clone()
+        ctx.step_auto(X1, V1, 10)
+        X2, V2 = X.clone(), V.clone()
+        ctx.step(X2, V2, 10)
+        if persistent:
+            ex = ((X1 - X2)[:, :3].abs().max(1).values / X2[:, :3].norm(dim=1)).max().item()
+            assert ex < 1e-11
+        else:
+            assert torch.equal(X1, X2) and torch.equal(V1, V2)
+    d = diskgen.workload("disk2048", n=100)
+    X, V = to_dev(d["x"], d["v"], d["m"])
+    X1, V1 = X.clone(), V.clone()
+    ctx.step_auto(X1, V1, 5)
+    ctx.step(X, V, 5)
+    assert torch.equal(X1, X) and torch.equal(V1, V)
