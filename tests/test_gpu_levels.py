@@ -101,3 +101,29 @@ def test_levels_arguments_checked(nb, ctx):
         ctx.step_hybrid(X, V, 1, levels=5)
     with pytest.raises(nb.NBodyError):
         ctx.step_hybrid(X, V, 1, levels=1, substeps=0)
+
+
+def test_levels_with_mergers_match_oracle(ctx):
+    """Collisions at the deepest level of the multi-level step (one level, s = 8, f = 300, 10 steps of
+    the 2048 disk): the same mergers as the oracle's recursion, masses bit-exact, states 1e-10."""
+    say("levels L=1 s=8 with mergers f=300 disk2048 x10")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk2048")
+    X, V = dev_state(d)
+    thr = ctx.rcrit(X, V)
+    R = torch.tensor(d["radius"], device=DEV)
+    out = ctx.step_hybrid(X, V, 10, thr=thr, levels=1, substeps=8, radius=R, f=300.0)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov, om, oR, st, ostats, omg, omt = oracle.step_levels(d["x"], d["v"], d["m"], p, 10, 1, 8, thr=othr,
+                                                              R=d["radius"], f=300.0)
+    srt = lambda mg: np.asarray(mg).reshape(-1, 3)[np.lexsort(np.asarray(mg).reshape(-1, 3).T[::-1])]
+    say(f"  gpu {out['mergers']} mergers {srt(out['merges']).tolist()}; oracle {srt(omg).tolist()}")
+    assert st == 0 and out["unfinished"] == 0
+    assert out["mergers"] == len(omg) >= 3
+    np.testing.assert_array_equal(srt(out["merges"]), srt(omg))
+    xm = X.cpu().numpy()
+    np.testing.assert_array_equal(xm[:, 3], om)
+    live = om > 0
+    ex, ev = rel_err(X[torch.tensor(live, device=DEV)], V[torch.tensor(live, device=DEV)], ox[live], ov[live])
+    say(f"  state rel err x {ex:.2e} v {ev:.2e}")
+    assert ex < 1e-10 and ev < 1e-10
