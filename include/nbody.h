@@ -235,8 +235,9 @@ int nbody_autotune_step(nbody_ctx *ctx, int64_t n, const double *xm, const doubl
 
 /*
  * nsteps steps of one system of n bodies in place with the path recorded for n by
- * nbody_autotune_step (path 0, identical to nbody_step with thr = NULL, if n was never tuned).
- * Thresholds are taken at the call's start.
+ * nbody_autotune_step (path 0, identical to nbody_step with thr = NULL, if n was never tuned, or
+ * when the context's precision is not binary64). Thresholds are taken at the call's start.
+ * nbody_set_params forgets the recorded paths.
  */
 int nbody_step_auto(nbody_ctx *ctx, int64_t n, double *xm, double *v, int32_t nsteps, void *stream);
 

@@ -378,6 +378,7 @@ int nbody_set_params(nbody_ctx *c, const nbody_params *p) {
   if (!c) return NBODY_E_INVAL;
   if (!params_ok(p)) return fail(c, NBODY_E_INVAL, "invalid parameters");
   c->p = *p;
+  c->step_path.clear();   // choices of the small-N switch were timed with the old parameters
   return NBODY_OK;
 }
 
@@ -940,7 +941,8 @@ int nbody_step_auto(nbody_ctx *c, int64_t n, double *xm, double *v, int32_t nste
   TRY(check_dev(c, v, "v", true));
   if (nsteps < 0) return fail(c, NBODY_E_INVAL, "nsteps < 0");
   const auto it = c->step_path.find(n);
-  const int32_t path = it == c->step_path.end() ? 0 : it->second;
+  // the persistent path integrates in binary64 only
+  const int32_t path = it == c->step_path.end() || c->p.precision != NBODY_PREC_F64 ? 0 : it->second;
   return run_step_path(c, n, xm, v, nsteps, path, (hipStream_t)stream);
 }
 
