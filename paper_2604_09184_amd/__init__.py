@@ -263,7 +263,7 @@ class Context:
             raise NBodyError("radius must be a contiguous float64 tensor")
         log = {"merges": torch.zeros((max(cap, 1), 3), dtype=torch.int32, device=device),
                "time": torch.zeros(max(cap, 1), dtype=torch.float64, device=device),
-               "count": torch.zeros(1, dtype=torch.int64, device=device)}
+               "count": torch.zeros(1, dtype=torch.int64, device=device), "cap": int(cap)}
         col = Collisions(_ptr(radius), float(f), _ptr(log["merges"]), _ptr(log["time"]), int(cap),
                          _ptr(log["count"]))
         return col, log
@@ -272,7 +272,7 @@ class Context:
         out = dict(zip(self._CE_STATS, stats.cpu().tolist()))
         if log is not None:
             cnt = int(log["count"].item())
-            k = min(cnt, log["merges"].shape[0])
+            k = min(cnt, log["cap"])
             out["mergers"] = cnt
             out["merges"] = log["merges"][:k].cpu().numpy()
             out["merge_times"] = log["time"][:k].cpu().numpy()

@@ -151,3 +151,24 @@ def test_merge_arguments_checked(nb):
         ctx.step_hybrid(X, V, 1, radius=Rd, f=float("nan"))
     with pytest.raises(nb.NBodyError):
         ctx.step_hybrid(X, V, 1, radius=Rd.float(), f=1.0)
+
+
+def test_merge_log_truncated_at_capacity(nb):
+    """With room for two entries the log keeps two of the five mergers (any two of the oracle's) and
+    the count still says five; cap = 0 needs no log buffers."""
+    say("merge log capacity")
+    p = diskgen.PARAMS
+    ctx = nb.Context(nb.Params(**p))
+    d = diskgen.workload("disk2048")
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    omg = oracle.step_merge(d["x"], d["v"], d["m"], d["radius"], 300.0, p, 10, thr=othr)[6]
+    for cap in (2, 0):
+        X, V = dev_state(d["x"], d["v"], d["m"])
+        thr = ctx.rcrit(X, V)
+        Rd = torch.tensor(d["radius"], device=DEV)
+        out = ctx.step_hybrid(X, V, 10, thr=thr, radius=Rd, f=300.0, cap=cap)
+        say(f"  cap {cap}: count {out['mergers']}, logged {len(out['merges'])}")
+        assert out["mergers"] == len(omg)
+        assert len(out["merges"]) == min(cap, len(omg))
+        logged = {tuple(r) for r in np.asarray(out["merges"]).tolist()}
+        assert logged <= {tuple(r) for r in np.asarray(omg).tolist()}
