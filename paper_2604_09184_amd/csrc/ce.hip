@@ -302,8 +302,9 @@ __device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale
     cur[0] = e[c];
 #pragma unroll
     for (int j = 1; j <= c; ++j) {
+      // 1/((n_c/n_{c-j})^2 - 1) is a constant once the loops are unrolled: a multiplication
       const double ratio = (double)(c + 1) / (double)(c + 1 - j);
-      cur[j] = cur[j - 1] + (cur[j - 1] - prev[j - 1]) / (ratio * ratio - 1.0);
+      cur[j] = cur[j - 1] + (cur[j - 1] - prev[j - 1]) * (1.0 / (ratio * ratio - 1.0));
     }
     if (c >= 2) err[c] = fmax(err[c], fabs(cur[c] - cur[c - 1]) * iscale);
     if (c == want) out = cur[c];
