@@ -203,8 +203,16 @@ def variant_hybrid(nb, p):
     sec, stats = timed(lambda: ctx.step_hybrid(X, V, 100, thr=thr, radius=R, f=300.0))
     out["hybrid_merge_f300"] = {"seconds": round(sec, 4), "ms_per_step": round(sec * 10, 4),
                                 "mergers": stats["mergers"], "bodies_left": int((X[:, 3] > 0).sum().item())}
-    # the 32768-body disk, whose close pairs percolate into groups too large for the direct
-    # integrator: 10 steps plain, hybrid, and hybrid with one intermediate level (s = 8)
+    return out
+
+
+def variant_levels(nb, p):
+    """The 32768-body disk, whose close pairs percolate into groups too large for the direct
+    integrator: 10 steps plain, hybrid, and hybrid with one intermediate changeover level (s = 8)."""
+    import torch
+
+    import diskgen
+    ctx = nb.Context(nb.Params(**p))
     d = diskgen.workload("disk32768")
     xm, v4 = diskgen.pack4(d["x"], d["v"], d["m"])
     big = {}
@@ -223,8 +231,7 @@ def variant_hybrid(nb, p):
                      "E_rel_drift": float(abs(e1["E"] - e0["E"]) / abs(e0["E"]))}
         if st is not None:
             big[name]["groups"] = {k: st[k] for k in ("groups", "largest", "bodies", "too_large")}
-    out["disk32768_10_steps"] = big
-    return out
+    return {"workload": "disk32768", "steps": 10, **big}
 
 
 def variant_small_n(nb, p):
@@ -282,7 +289,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)   # the clock ramps up over the first ~0.2 s of load
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--only", choices=["split", "batched", "adjoint", "hybrid", "small_n"],
+    ap.add_argument("--only", choices=["split", "batched", "adjoint", "hybrid", "levels", "small_n"],
                     help="run only this variant and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -302,7 +309,7 @@ def main():
     if args.only:
         p = diskgen.PARAMS
         fn = {"split": variant_split, "batched": variant_batched, "adjoint": variant_adjoint,
-              "hybrid": variant_hybrid, "small_n": variant_small_n}[args.only]
+              "hybrid": variant_hybrid, "levels": variant_levels, "small_n": variant_small_n}[args.only]
         print(json.dumps({args.only: fn(nb, p)}), flush=True)
         return
     if args.calibrate_copy:
@@ -371,6 +378,8 @@ def main():
         variants["adjoint"] = variant_adjoint(nb, p)
         print("[bench] variant: hybrid step (disk2048)", file=sys.stderr, flush=True)
         variants["hybrid"] = variant_hybrid(nb, p)
+        print("[bench] variant: changeover levels (disk32768)", file=sys.stderr, flush=True)
+        variants["levels"] = variant_levels(nb, p)
         print("[bench] variant: small-N switch", file=sys.stderr, flush=True)
         variants["small_n"] = variant_small_n(nb, p)
 
