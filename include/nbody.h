@@ -209,11 +209,14 @@ typedef struct nbody_levels {
  * call, merged half kicks), but the drift A integrates H_A in full: the close pairs found by each
  * kick's pair loop form the close-encounter groups of the drift that follows, integrated as in
  * nbody_drift_groups. The step then conserves the full energy E instead of the K-weighted E'.
- * lv (may be NULL: no intermediate levels): multi-level changeover (see nbody_levels); contacts
- * are then looked for by the direct integrator at the deepest level and merger times are within
- * that level's substep. col (may be NULL): collisions as perfect mergers in every step's drift
- * (merged masses take part in the kicks that follow; rc stays fixed for the call). stats as for nbody_drift_groups, summed
- * over the steps (stats[1] the maximum). Binary64 only.
+ * n bodies; xm, v as for nbody_step; thr as from nbody_rcrit, or NULL (computed at the call's
+ * start); nsteps >= 0. lv (may be NULL: no intermediate levels): multi-level changeover (see
+ * nbody_levels; levels outside 0..4 or substeps < 1 are rejected); contacts are then looked for by
+ * the direct integrator at the deepest level and merger times are within that level's substep.
+ * col (may be NULL): collisions as perfect mergers in every step's drift (merged masses take part
+ * in the kicks that follow; rc stays fixed for the call). stats (device int64 [6]) as for
+ * nbody_drift_groups, summed over the steps (stats[1] the maximum). Binary64 only: a context in
+ * split precision is rejected. Returns NBODY_OK, NBODY_E_INVAL, NBODY_E_NOMEM or NBODY_E_HIP.
  */
 int nbody_step_hybrid(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr,
                       int32_t nsteps, const nbody_levels *lv, const nbody_collisions *col,
