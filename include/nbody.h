@@ -197,11 +197,16 @@ int nbody_drift_groups(nbody_ctx *ctx, int64_t n, double *xm, double *v, const d
  * kick(tau/2s) drift_{l+1}(tau/s) kick(tau/2s), the kick acting on the close pairs with the
  * potential W_l K_{l+1} U; at level L the close pairs still within rc_L form the groups that the
  * direct integrator takes (pair term weighted by W_L), and the other bodies follow Kepler orbits.
- * levels = 0 is the plain hybrid step; at most 4 levels.
+ * levels = 0 is the plain hybrid step; at most 4 levels. margin (finite, >= 0): with levels, the
+ * step's close-pair list is taken at (1 + margin) rc (exact-predicate thresholds H (1+margin)^6,
+ * V (1+margin)^2; the kick is unchanged, as K = 1 beyond rc), so that pairs which cross rc during the
+ * step are integrated by the drift; 0.5 keeps the full energy of the 32768-body disk to 1e-11 over
+ * 10 steps where 0 drifts by 2e-9.
  */
 typedef struct nbody_levels {
   int32_t levels;
   int32_t substeps;
+  double margin;
 } nbody_levels;
 
 /*

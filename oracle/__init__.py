@@ -56,7 +56,7 @@ def _lib():
         "or_ce_drift_group_levels": (ctypes.c_int, [P, ctypes.c_int, P, P, P, P, ctypes.c_int, P, D, D]),
         "or_drift_levels": (ctypes.c_int, [I, P, P, P, P, I, P, P, P, ctypes.c_int, ctypes.c_int, P, D, D]),
         "or_step_levels": (ctypes.c_int, [I, P, P, P, P, ctypes.c_int, P, P, P, D, P, ctypes.c_int, ctypes.c_int,
-                                          P, D, P, P, I, P]),
+                                          P, D, P, P, I, P, D]),
         "or_jump": (None, [I, P, P, P, P, D]),
         "or_drift": (ctypes.c_int, [I, P, P, P, D, P]),
         "or_drift_q": (ctypes.c_int, [I, P, P, P, D]),
@@ -262,10 +262,10 @@ def drift_levels(x, v, m, pairs, thr_levels, p, levels, substeps, h, tol=1e-18):
     return x, v, st
 
 
-def step_levels(x, v, m, p, nsteps, levels, substeps, thr=None, tol=1e-18, R=None, f=0.0, cap=4096):
+def step_levels(x, v, m, p, nsteps, levels, substeps, thr=None, tol=1e-18, R=None, f=0.0, cap=4096, margin=0.0):
     """nsteps hybrid steps whose close-encounter drift runs through `levels` intermediate changeover
-    levels (time steps dt / substeps^l); with R, collisions merge bodies. Returns x, v, m, R,
-    status, stats, merges and their times."""
+    levels (time steps dt / substeps^l), the step's close pairs listed at (1 + margin) rc; with R,
+    collisions merge bodies. Returns x, v, m, R, status, stats, merges and their times."""
     x = _f64(x).copy(); v = _f64(v).copy(); m = _f64(m).copy()
     R = None if R is None else _f64(R).copy()
     rc, H, V = (None, None, None) if thr is None else (_f64(t) for t in thr)
@@ -274,7 +274,7 @@ def step_levels(x, v, m, p, nsteps, levels, substeps, thr=None, tol=1e-18, R=Non
     cnt = ctypes.c_int64(0)
     st = _lib().or_step_levels(len(m), _p(x), _p(v), _p(m), _p(_prm(p)), int(nsteps), _p(rc), _p(H), _p(V),
                                float(tol), _p(stats), int(levels), int(substeps), _p(R), float(f), _p(merges),
-                               _p(mtime), cap, ctypes.byref(cnt))
+                               _p(mtime), cap, ctypes.byref(cnt), float(margin))
     if st < 0:
         raise ValueError("levels must be 0..4 and substeps >= 1")
     mg, mt = _merge_log(merges, mtime, cnt.value)

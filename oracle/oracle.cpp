@@ -1074,11 +1074,14 @@ int or_drift_levels(int64_t n, double *x, double *v, const double *m, const int3
 }
 
 // nsteps hybrid steps with L intermediate changeover levels (time steps dt / s^l) and, when R is
-// given, collisions as perfect mergers (radius factor f; m and R in/out, mergers logged).
+// given, collisions as perfect mergers (radius factor f; m and R in/out, mergers logged). With
+// L > 0 and margin > 0 the step's close-pair list (and the kick's close/far decision, which gives
+// the same weight beyond rc since K = 1 there) uses the thresholds H (1+margin)^6, V (1+margin)^2,
+// so that pairs crossing rc within the step belong to the drift's pairs.
 int or_step_levels(int64_t n, double *x, double *v, double *m, const double *prm, int nsteps,
                    const double *rc_in, const double *H_in, const double *V_in, double tol, int64_t *stats,
                    int L, int sub, double *R, double f, int32_t *merges, double *mtime, int64_t cap,
-                   int64_t *count) {
+                   int64_t *count, double margin) {
   Params p{prm[0], prm[1], prm[2], prm[3], prm[4], prm[5]};
   if (L < 0 || L > 4 || sub < 1) return -1;
   Levels lv{L, sub, n, std::vector<double>((size_t)(L + 1) * n), std::vector<double>((size_t)(L + 1) * n),
@@ -1100,7 +1103,15 @@ int or_step_levels(int64_t n, double *x, double *v, double *m, const double *prm
   std::vector<int64_t> log;
   std::vector<long double> time;
   MergeCtx mc{f, n, 0, &log, &time};
-  const int st = steps_hybrid(n, x, v, m, p, nsteps, lv.rc.data(), lv.H.data(), lv.V.data(), tol, stats,
+  std::vector<double> Hl(lv.H.begin(), lv.H.begin() + n), Vl(lv.V.begin(), lv.V.begin() + n);
+  if (L > 0 && margin > 0) {
+    const double g = 1.0 + margin, g2 = g * g, g6 = (g2 * g2) * g2;
+    for (int64_t i = 0; i < n; i++) {
+      Hl[i] = Hl[i] * g6;
+      Vl[i] = Vl[i] * g2;
+    }
+  }
+  const int st = steps_hybrid(n, x, v, m, p, nsteps, lv.rc.data(), Hl.data(), Vl.data(), tol, stats,
                               R, R ? &mc : nullptr, &lv);
   *count = put_log(log, time, cap, merges, mtime);
   return st;

@@ -40,7 +40,7 @@ class Collisions(ctypes.Structure):
 
 class Levels(ctypes.Structure):
     """nbody_levels: intermediate changeover levels of the hybrid step."""
-    _fields_ = [("levels", ctypes.c_int32), ("substeps", ctypes.c_int32)]
+    _fields_ = [("levels", ctypes.c_int32), ("substeps", ctypes.c_int32), ("margin", ctypes.c_double)]
 
 
 @dataclasses.dataclass
@@ -291,16 +291,18 @@ class Context:
                     "nbody_drift_groups")
         return self._ce_result(stats, log)
 
-    def step_hybrid(self, xm, v, nsteps, thr=None, radius=None, f=1.0, cap=4096, levels=0, substeps=8):
+    def step_hybrid(self, xm, v, nsteps, thr=None, radius=None, f=1.0, cap=4096, levels=0, substeps=8,
+                    margin=0.5):
         """nsteps hybrid steps in place (close-encounter groups integrated in the drift); with
         levels > 0, the drift of the bodies with close partners runs through that many
-        intermediate changeover levels (time steps dt / substeps^l); with radius (float64 [n],
+        intermediate changeover levels (time steps dt / substeps^l), the close pairs listed at
+        (1 + margin) rc; with radius (float64 [n],
         in/out), collisions merge bodies. Returns the statistics as a dict (with the merger log
         when colliding)."""
         _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
         stats = torch.zeros(6, dtype=torch.int64, device=xm.device)
         col, log = self._collisions(radius, f, cap, xm.device)
-        lv = Levels(int(levels), int(substeps))
+        lv = Levels(int(levels), int(substeps), float(margin))
         self._check(lib().nbody_step_hybrid(self._h, xm.shape[0], _ptr(xm), _ptr(v), _ptr(thr), int(nsteps),
                                             ctypes.byref(lv), ctypes.byref(col) if col else None, _ptr(stats),
                                             _stream()), "nbody_step_hybrid")

@@ -32,7 +32,7 @@ enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MO
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GMARK, B_GIN, B_GSIZE,
              B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_HGOUT, B_LTHR, B_ADEG, B_AOFF,
-             B_AFILL, B_ADJ, B_LSKIP, B_AOWN, B_ATERM, B_ATOT, B_NUM };
+             B_AFILL, B_ADJ, B_LSKIP, B_AOWN, B_ATERM, B_ATOT, B_ETHR, B_NUM };
 
 }  // namespace
 
@@ -584,8 +584,10 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   if (c->p.precision != NBODY_PREC_F64) return fail(c, NBODY_E_INVAL, "the hybrid step runs in binary64");
   const int L = lv ? lv->levels : 0;
   const int sub = lv ? lv->substeps : 1;
+  const double margin = lv ? lv->margin : 0.0;
   if (L < 0 || L >= kMaxLevels) return fail(c, NBODY_E_INVAL, "levels must be 0..%d", kMaxLevels - 1);
   if (L > 0 && sub < 1) return fail(c, NBODY_E_INVAL, "substeps must be >= 1");
+  if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(c, NBODY_E_INVAL, "margin must be finite and >= 0");
   CeCollide cc;
   TRY(collide_args(c, (int)n, col, cc));
   hipStream_t st = (hipStream_t)stream;
@@ -613,8 +615,17 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (hybrid step)");
   GroupBufs g;
   TRY(group_bufs(c, N, g));
+  // with levels and a margin, the pair loop lists the pairs within (1 + margin) rc
+  const double *thr_list = thr;
+  if (L > 0 && margin > 0.0) {
+    double4 *te = (double4 *)ensure(c, B_ETHR, (size_t)n * sizeof(double4));
+    if (!te) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (list thresholds)");
+    const double f = 1.0 + margin, f2 = f * f, f6 = (f2 * f2) * f2;
+    HIPCHK(c, launch_thr_scale((const double4 *)thr, N, f2, f6, te, st), "list thresholds");
+    thr_list = (const double *)te;
+  }
   KickArgs a;
-  TRY(make_kick_args(c, N, xm, thr, true, false, true, a));
+  TRY(make_kick_args(c, N, xm, thr_list, true, false, true, a));
   double4 *X = (double4 *)xm;
   double4 *Vv = (double4 *)v;
   const double4 *T = (const double4 *)thr;

@@ -103,6 +103,7 @@ hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, i
 // skip[i] = 1 unless body i has a listed partner (deg > 0) and is outside the groups (in == 0);
 // with in null: skip[i] = (deg[i] > 0).
 hipError_t launch_level_mask(const int *deg, const int *in, int n, int *skip, hipStream_t st);
+hipError_t launch_thr_scale(const double4 *thr, int n, double f2, double f6, double4 *out, hipStream_t st);
 
 // adjoint.hip
 hipError_t launch_kick_vjp(const double4 *xm, const double4 *thr, const int *perm, const double2 *uni,

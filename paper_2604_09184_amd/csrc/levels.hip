@@ -58,9 +58,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_fill(const int32_t *__restrict__
 }
 
 // Each row in ascending neighbour index, so that the kicks sum in an order that does not depend on
-// the atomics above: one wave per row; a row of up to 256 entries is placed by rank (the entries
+// the atomics above: one wave per row; a row of up to 512 entries is placed by rank (the entries
 // are distinct; lane l holds entries l, l + 64, ...), a longer one by insertion sort in one lane.
-constexpr int kSortChunks = 4;
+constexpr int kSortChunks = 8;
 __global__ __launch_bounds__(kBlock) void k_adj_sort(const int *__restrict__ off,
                                                      const int *__restrict__ deg, int n,
                                                      int *__restrict__ adj) {
@@ -185,6 +185,21 @@ __global__ __launch_bounds__(kBlock) void k_level_mask(const int *__restrict__ d
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   skip[i] = in ? !(deg[i] > 0 && !in[i]) : (deg[i] > 0);
+}
+
+// Thresholds of the close-pair list with a margin: rc kept, H f6, V f2 and the prefilter bound T f2
+// (f2 = (1 + margin)^2, f6 = f2^3).
+__global__ __launch_bounds__(kBlock) void k_thr_scale(const double4 *__restrict__ thr, int n, double f2,
+                                                      double f6, double4 *__restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double4 t = thr[i];
+  out[i] = make_double4(t.x, t.y * f6, t.z * f2, t.w * f2);
+}
+
+hipError_t launch_thr_scale(const double4 *thr, int n, double f2, double f6, double4 *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_thr_scale, dim3(nblocks(n)), dim3(kBlock), 0, st, thr, n, f2, f6, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n,

@@ -44,16 +44,17 @@ def rel_err(X, V, ox, ov):
     return ex, ev
 
 
-@pytest.mark.parametrize("L,s,steps", [(1, 8, 10), (2, 4, 5)])
-def test_levels_match_oracle(ctx, L, s, steps):
-    say(f"levels L={L} s={s} disk2048 x{steps}")
+@pytest.mark.parametrize("L,s,steps,margin", [(1, 8, 10, 0.0), (1, 8, 10, 0.5), (2, 4, 5, 0.5)])
+def test_levels_match_oracle(ctx, L, s, steps, margin):
+    say(f"levels L={L} s={s} margin={margin} disk2048 x{steps}")
     p = diskgen.PARAMS
     d = diskgen.workload("disk2048")
     X, V = dev_state(d)
     thr = ctx.rcrit(X, V)
-    stats = ctx.step_hybrid(X, V, steps, thr=thr, levels=L, substeps=s)
+    stats = ctx.step_hybrid(X, V, steps, thr=thr, levels=L, substeps=s, margin=margin)
     othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
-    ox, ov, om, oR, st, ostats, _, _ = oracle.step_levels(d["x"], d["v"], d["m"], p, steps, L, s, thr=othr)
+    ox, ov, om, oR, st, ostats, _, _ = oracle.step_levels(d["x"], d["v"], d["m"], p, steps, L, s, thr=othr,
+                                                          margin=margin)
     ex, ev = rel_err(X, V, ox, ov)
     say(f"  {stats}; oracle {ostats}; state rel err x {ex:.2e} v {ev:.2e}")
     assert st == 0 and stats["unfinished"] == 0 and stats["too_large"] == 0
@@ -83,9 +84,10 @@ def test_levels_split_the_percolating_group(ctx):
     thr = ctx.rcrit(X, V)
     plain = ctx.step_hybrid(X.clone(), V.clone(), 1, thr=thr)
     assert plain["too_large"] >= 1          # groups above 64 bodies (only Kepler orbits)
-    stats = ctx.step_hybrid(X, V, 2, thr=thr, levels=1, substeps=8)
+    stats = ctx.step_hybrid(X, V, 2, thr=thr, levels=1, substeps=8, margin=0.5)
     othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
-    ox, ov, om, oR, st, ostats, _, _ = oracle.step_levels(d["x"], d["v"], d["m"], p, 2, 1, 8, thr=othr)
+    ox, ov, om, oR, st, ostats, _, _ = oracle.step_levels(d["x"], d["v"], d["m"], p, 2, 1, 8, thr=othr,
+                                                          margin=0.5)
     ex, ev = rel_err(X, V, ox, ov)
     say(f"  plain {plain}; levels {stats}; oracle {ostats}; state rel err x {ex:.2e} v {ev:.2e}")
     assert stats["too_large"] == 0 and stats["unfinished"] == 0 and stats["largest"] <= 64
@@ -101,6 +103,27 @@ def test_levels_arguments_checked(nb, ctx):
         ctx.step_hybrid(X, V, 1, levels=5)
     with pytest.raises(nb.NBodyError):
         ctx.step_hybrid(X, V, 1, levels=1, substeps=0)
+    with pytest.raises(nb.NBodyError):
+        ctx.step_hybrid(X, V, 1, levels=1, margin=-0.1)
+
+
+def test_levels_margin_conserves_energy_on_the_percolating_disk(ctx):
+    """The 32768-body disk, 10 steps with one level (s = 8): listing the close pairs at 1.5 rc lets
+    the drift integrate the pairs that cross rc within a step, and the full energy E is kept to
+    1e-10 (measured ~1e-11), where the list at rc drifts by ~2e-9 over the same steps."""
+    say("levels margin energy disk32768 x10")
+    d = diskgen.workload("disk32768")
+    dE = {}
+    for margin in (0.0, 0.5):
+        X, V = dev_state(d)
+        thr = ctx.rcrit(X, V)
+        e0 = ctx.energy(X, V, thr)
+        st = ctx.step_hybrid(X, V, 10, thr=thr, levels=1, substeps=8, margin=margin)
+        e1 = ctx.energy(X, V, thr)
+        dE[margin] = abs(e1["E"] - e0["E"]) / abs(e0["E"])
+        assert st["too_large"] == 0 and st["list_overflows"] == 0
+    say(f"  dE/E: margin 0 {dE[0.0]:.2e}, margin 0.5 {dE[0.5]:.2e}")
+    assert dE[0.5] < 1e-10 and dE[0.5] < dE[0.0] / 20
 
 
 def test_levels_with_mergers_match_oracle(ctx):
@@ -112,10 +135,10 @@ def test_levels_with_mergers_match_oracle(ctx):
     X, V = dev_state(d)
     thr = ctx.rcrit(X, V)
     R = torch.tensor(d["radius"], device=DEV)
-    out = ctx.step_hybrid(X, V, 10, thr=thr, levels=1, substeps=8, radius=R, f=300.0)
+    out = ctx.step_hybrid(X, V, 10, thr=thr, levels=1, substeps=8, radius=R, f=300.0, margin=0.5)
     othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
     ox, ov, om, oR, st, ostats, omg, omt = oracle.step_levels(d["x"], d["v"], d["m"], p, 10, 1, 8, thr=othr,
-                                                              R=d["radius"], f=300.0)
+                                                              R=d["radius"], f=300.0, margin=0.5)
     srt = lambda mg: np.asarray(mg).reshape(-1, 3)[np.lexsort(np.asarray(mg).reshape(-1, 3).T[::-1])]
     say(f"  gpu {out['mergers']} mergers {srt(out['merges']).tolist()}; oracle {srt(omg).tolist()}")
     assert st == 0 and out["unfinished"] == 0

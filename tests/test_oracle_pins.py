@@ -739,3 +739,19 @@ def test_level_drift_converges_to_the_HA_flow(params, disk2048_groups):
         assert st == 0
         errs[s] = abs(HA(x1, v1, lv[0][0]) - HA(x, v, lv[0][0])) / abs(HA(x, v, lv[0][0]))
     assert errs[32] < 1e-12 and errs[32] < errs[2] / 50
+
+
+def test_list_margin_changes_only_the_list(params, disk2048_groups):
+    """Listing close pairs at (1 + margin) rc (thresholds H (1+margin)^6, V (1+margin)^2) leaves the
+    kick bit for bit (beyond rc the changeover weight is K/r^3 - K'/r^2 = 1/r^3, the far-pair
+    weight) and gives a list that contains the list at rc."""
+    d, (rc, H, V), _ = disk2048_groups
+    g = 1.5
+    g2 = g * g
+    H2, V2 = H * ((g2 * g2) * g2), V * g2
+    a0 = oracle.kick_acc(d["x"], d["m"], (rc, H, V), params)[0]
+    a1 = oracle.kick_acc(d["x"], d["m"], (rc, H2, V2), params)[0]
+    np.testing.assert_array_equal(a0, a1)
+    p0 = {tuple(r) for r in oracle.encounters(d["x"], (rc, H, V)).tolist()}
+    p1 = {tuple(r) for r in oracle.encounters(d["x"], (rc, H2, V2)).tolist()}
+    assert p0 < p1 and len(p1) > 2 * len(p0)
