@@ -9,12 +9,13 @@
 // sweeps with 2, 4, ..., 16 substeps over a macro step H, extrapolated to zero substep length as a
 // polynomial in (H/n)^2 (Aitken-Neville); a macro step is accepted when the last two extrapolants
 // agree to the tolerance relative to the group's largest position and velocity, and halved
-// otherwise.
+// otherwise. With intermediate changeover levels the [1 - K] factor becomes the product of the
+// levels' [1 - K_l]; with collisions, members in contact merge (see k_ce_drift).
 //
-// One wave per group of at most 64 bodies: lane l holds one body, the pair sums visit the members
-// in ascending body index (the same order whatever lane holds which body), the positions of the
-// others arrive by lane shuffles, and every step-size decision is taken on wave-wide maxima, so the
-// whole integration is uniform across the wave and deterministic.
+// One workgroup of four waves per group of at most 64 bodies (the work layout is described at the
+// integrator below): the positions of other members arrive by lane shuffles, every step-size
+// decision is taken on wave-wide reductions of identical data in every wave, so the integration is
+// uniform across the workgroup and deterministic.
 #include "internal.hpp"
 #include "kepler_core.hpp"
 
