@@ -9,6 +9,11 @@
  *   H_B  the all-pairs mutual gravity weighted by a smooth changeover K(r_ij) (the "kick"),
  *   H_C  the total-momentum term (the "jump"),
  * and flags pairs closer than the critical radius of equation rcrit as close encounters.
+ * Beyond the plain step (nbody_step) the library integrates the close-encounter part of H_A for
+ * groups of close pairs (nbody_step_hybrid: direct integration, intermediate changeover levels,
+ * collisions as perfect mergers), advances ensembles of systems in one launch
+ * (nbody_step_batched), picks the fastest path for small systems (nbody_step_auto), and
+ * differentiates the step (nbody_*_vjp).
  *
  * Conventions shared by every entry point
  *   - Return value: NBODY_OK (0) or a negative NBODY_E_* code; the message of the last failure

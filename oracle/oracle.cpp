@@ -26,8 +26,10 @@
 //    V_i = cV*vv_i, cV = (n2*dt)*(n2*dt), vv_i = fma(vz,vz,fma(vy,vy,vx*vx)).
 //    In real arithmetic this is r_ij < max(rc_i, rc_j).
 //  * Step: B(dt/2) C(dt/2) A(dt) C(dt/2) B(dt/2) (operator order of the democratic heliocentric
-//    method the paper cites); A is the Kepler drift about mu = G m0; the [1-K] part of H_A is not
-//    integrated here.
+//    method the paper cites); A is the Kepler drift about mu = G m0. The plain step leaves the
+//    [1-K] part of H_A out; the hybrid steps integrate it for every close-encounter group
+//    (Gragg-Bulirsch-Stoer in long double), optionally through intermediate changeover levels and
+//    with collisions as perfect mergers (readings at those routines below).
 //  * Kepler drift: f and g functions with the eccentric-anomaly difference form of Kepler's
 //    equation (elliptic) or its hyperbolic analogue, solved by safeguarded Newton iteration in
 //    long double.
