@@ -690,11 +690,14 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
       HIPCHK(c, launch_drift(X, Vv, N, tau, mu, nullptr, st, lskip), "level drift");
       return NBODY_OK;
     }
+    // the closing half kick of a substep and the opening half kick of the next act at the same
+    // positions: one kick over the whole substep length
     const double ts = tau / sub;
+    HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
     for (int k = 0; k < sub; ++k) {
-      HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
       TRY(drift_levels(l + 1, ts));
-      HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
+      HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, k + 1 < sub ? ts : 0.5 * ts,
+                                  st), "level kick");
     }
     return NBODY_OK;
   };
