@@ -69,6 +69,23 @@ const char *nbody_last_error(const nbody_ctx *ctx);
 const char *nbody_version(void);
 
 /*
+ * Workspace reservation. The context's workspace grows on demand, and growing it waits for the
+ * whole device (hipDeviceSynchronize) before the old block is freed. nbody_reserve sizes it in
+ * advance for systems of up to n bodies, so that later calls of that size enqueue their work
+ * without allocating or synchronizing. what = a bitwise OR of
+ *   NBODY_RESERVE_KICK  partial sums and momentum of nbody_kick / nbody_step / nbody_bench_pairs,
+ *   NBODY_RESERVE_LIST  encounter emission (nbody_encounters, nbody_step with a list or counts),
+ *   NBODY_RESERVE_CE    the close-encounter part acc_ce of nbody_kick.
+ * Sizes depend on n and on the "target_waves" and "emit_slots" tuning values at the time of the
+ * call. Synchronizes `stream` before returning. Returns NBODY_E_INVAL for unknown flags,
+ * NBODY_E_NOMEM if the device memory is not available.
+ */
+#define NBODY_RESERVE_KICK 1u
+#define NBODY_RESERVE_LIST 2u
+#define NBODY_RESERVE_CE 4u
+int nbody_reserve(nbody_ctx *ctx, int64_t n, uint32_t what, void *stream);
+
+/*
  * Critical radius and encounter thresholds (eq. rcrit), one row per body:
  *   rc_i = max(n1 R_Hill,i, n2 dt |v_i|),  R_Hill,i = |x_i| (m_i / (3 m0))^(1/3),
  *   H_i  = cH * ((r2_i*r2_i)*r2_i) * (mu_i*mu_i),  cH = ((n1*n1*n1)*(n1*n1*n1))/9, mu_i = m_i/m0,
@@ -186,7 +203,9 @@ typedef struct nbody_collisions {
  * groups, [3] groups of more than 64 bodies (moved on Kepler orbits only: the result is then not
  * the H_A flow, and no contacts are found in them), [4] groups whose integration did not finish,
  * [5] (nbody_step_hybrid only) encounter lists that exceeded the internal capacity of
- * max(16 n, 65536) pairs.
+ * max(16 n, 65536) pairs (the groups of that evaluation were built from the first pairs only).
+ * Non-zero [3], [4] or [5] mean that part of the result is not the method's; the call still
+ * returns NBODY_OK (the state is valid), and the Python binding raises a warning for each.
  */
 int nbody_drift_groups(nbody_ctx *ctx, int64_t n, double *xm, double *v, const double *thr,
                        const int32_t *labels, double h, const nbody_collisions *col, int64_t *stats,

@@ -64,6 +64,7 @@ def _lib():
         "or_step_jvp": (ctypes.c_int, [I, P, P, P, P, P, P, P, ctypes.c_int, P, P, P, P]),
         "or_energy": (None, [I, P, P, P, P, P, P, P, P]),
         "or_num_threads": (ctypes.c_int, []),
+        "or_set_threads": (None, [ctypes.c_int]),
         "or_kick_jvp": (None, [I, P, P, P, P, P, P, P, P, P]),
         "or_drift_jvp": (None, [I, P, P, P, P, P, D, P, P]),
         "or_jump_jvp": (None, [I, P, P, P, P, P, P, P, D, P]),
@@ -93,6 +94,11 @@ def _prm(p):
 
 def num_threads():
     return _lib().or_num_threads()
+
+
+def set_threads(k):
+    """Number of OpenMP threads of the following oracle calls."""
+    _lib().or_set_threads(int(k))
 
 
 def thresholds(x, v, m, p):

@@ -1279,5 +1279,6 @@ void or_energy(int64_t n, const double *x, const double *v, const double *m, con
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int k) { omp_set_num_threads(k > 0 ? k : 1); }
 
 }  // extern "C"

@@ -12,6 +12,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
+import warnings
 
 import torch
 
@@ -21,9 +22,19 @@ LIB_PATH = os.path.join(_HERE, "libnbody.so")
 PREC_F64 = 0
 PREC_SPLIT = 1
 
+RESERVE_KICK = 1
+RESERVE_LIST = 2
+RESERVE_CE = 4
+
 
 class NBodyError(RuntimeError):
     pass
+
+
+class NBodyWarning(RuntimeWarning):
+    """A call finished, but part of its result is not the method's: a close-encounter group too
+    large for the direct integrator (moved on Kepler orbits only), an integration that did not
+    finish, or an encounter list longer than the hybrid step's internal capacity."""
 
 
 class _Params(ctypes.Structure):
@@ -64,6 +75,7 @@ _I32 = ctypes.c_int32
 
 # name -> argument types after the context pointer
 EXPORTS = {
+    "nbody_reserve": [_I64, ctypes.c_uint32, _P],
     "nbody_rcrit": [_I64, _P, _P, _P, _P],
     "nbody_kick": [_I64, _P, _P, _P, _D, _P, _P, _P],
     "nbody_encounters": [_I64, _P, _P, _P, _I64, _P, _P],
@@ -170,6 +182,10 @@ class Context:
             raise NBodyError(f"{name} failed ({rc}): {msg.decode() if msg else ''}")
 
     # ------------------------------------------------------------ entry points
+    def reserve(self, n, what=RESERVE_KICK | RESERVE_LIST):
+        """Sizes the context's workspace for n bodies in advance (synchronizes the stream)."""
+        self._check(lib().nbody_reserve(self._h, int(n), int(what), _stream()), "nbody_reserve")
+
     def rcrit(self, xm, v, thr=None):
         _body(xm, "xm"); _body(v, "v")
         if thr is None:
@@ -218,12 +234,24 @@ class Context:
                                       _stream()), "nbody_drift")
         return status
 
-    def step(self, xm, v, nsteps, thr=None, pairs_cap=None, step_counts=False):
+    def step(self, xm, v, nsteps, thr=None, pairs_cap=None, step_counts=False, out=None):
         """nsteps steps in place. With pairs_cap, also returns the final encounter list (pairs, count).
         With step_counts, also returns the int64 tensor of close-pair counts at the nsteps + 1 force
-        evaluations. Returns None, (pairs, count), counts or ((pairs, count), counts)."""
+        evaluations. Returns None, (pairs, count), counts or ((pairs, count), counts).
+        out = (pairs int32 (cap, 2), count int64 (1,)) device tensors to write the list into, in place
+        of pairs_cap: the call then enqueues its work without creating tensors or waiting, and
+        returns None (read count when the stream has finished)."""
         _body(xm, "xm"); _body(v, "v"); _body(thr, "thr")
         n = xm.shape[0]
+        if out is not None:
+            pairs, count = out
+            if pairs.dtype != torch.int32 or pairs.dim() != 2 or pairs.shape[1] != 2 or not pairs.is_contiguous():
+                raise NBodyError("out pairs must be a contiguous int32 (cap, 2) tensor")
+            if count.dtype != torch.int64 or count.numel() < 1:
+                raise NBodyError("out count must be an int64 tensor")
+            self._check(lib().nbody_step(self._h, n, _ptr(xm), _ptr(v), _ptr(thr), int(nsteps), _ptr(pairs),
+                                         pairs.shape[0], _ptr(count), None, _stream()), "nbody_step")
+            return None
         sc = torch.zeros(int(nsteps) + 1, dtype=torch.int64, device=xm.device) if step_counts else None
         if pairs_cap is None:
             self._check(lib().nbody_step(self._h, n, _ptr(xm), _ptr(v), _ptr(thr), int(nsteps), None, 0,
@@ -270,6 +298,17 @@ class Context:
 
     def _ce_result(self, stats, log):
         out = dict(zip(self._CE_STATS, stats.cpu().tolist()))
+        if out["too_large"]:
+            warnings.warn(f"{out['too_large']} close-encounter group(s) above 64 bodies moved on Kepler orbits "
+                          f"only (largest {out['largest']}); intermediate changeover levels (levels > 0) "
+                          f"split such groups", NBodyWarning, stacklevel=3)
+        if out["unfinished"]:
+            warnings.warn(f"{out['unfinished']} close-encounter integration(s) did not finish", NBodyWarning,
+                          stacklevel=3)
+        if out["list_overflows"]:
+            warnings.warn(f"{out['list_overflows']} encounter list(s) exceeded the hybrid step's capacity of "
+                          f"max(16 n, 65536) pairs: groups were built from a truncated list", NBodyWarning,
+                          stacklevel=3)
         if log is not None:
             cnt = int(log["count"].item())
             k = min(cnt, log["cap"])

@@ -139,19 +139,30 @@ void plan(const nbody_ctx *c, int n, int &S, int &chunk) {
 
 // Lane permutation grouping spatially close bodies into waves (no effect on any result bit);
 // null below the size where it pays.
+// Workspace of the lane permutation for n bodies (the cell counters start at zero; the kernels
+// leave them at zero after every use).
+int locality_bufs(nbody_ctx *c, int n, hipStream_t st) {
+  const int nb = nblocks(n);
+  const bool fresh = c->buf[B_CCOUNT].p == nullptr;
+  if (!ensure(c, B_PERM, (size_t)n * sizeof(int)) ||
+      !ensure(c, B_CELL, (size_t)n * sizeof(unsigned short)) ||
+      !ensure(c, B_RANGE, (size_t)nb * sizeof(float2)) ||
+      !ensure(c, B_CCOUNT, (size_t)locality_cells() * sizeof(unsigned)) ||
+      !ensure(c, B_CCURSOR, (size_t)locality_cells() * sizeof(unsigned)))
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (locality)");
+  if (fresh)
+    HIPCHK(c, hipMemsetAsync(c->buf[B_CCOUNT].p, 0, (size_t)locality_cells() * sizeof(unsigned), st), "memset");
+  return NBODY_OK;
+}
+
 int locality(nbody_ctx *c, int n, const double4 *xm, hipStream_t st, const int **perm) {
   *perm = nullptr;
   if (n < c->locality_min_n) return NBODY_OK;
-  const int nb = nblocks(n);
-  int *p = (int *)ensure(c, B_PERM, (size_t)n * sizeof(int));
-  unsigned short *cell = (unsigned short *)ensure(c, B_CELL, (size_t)n * sizeof(unsigned short));
-  float2 *range = (float2 *)ensure(c, B_RANGE, (size_t)nb * sizeof(float2));
-  const bool fresh = c->buf[B_CCOUNT].p == nullptr;
-  unsigned *count = (unsigned *)ensure(c, B_CCOUNT, (size_t)locality_cells() * sizeof(unsigned));
-  unsigned *cursor = (unsigned *)ensure(c, B_CCURSOR, (size_t)locality_cells() * sizeof(unsigned));
-  if (!p || !cell || !range || !count || !cursor) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (locality)");
-  if (fresh) HIPCHK(c, hipMemsetAsync(count, 0, (size_t)locality_cells() * sizeof(unsigned), st), "memset");
-  HIPCHK(c, launch_locality(xm, n, range, cell, count, cursor, p, st), "locality");
+  TRY(locality_bufs(c, n, st));
+  int *p = (int *)c->buf[B_PERM].p;
+  HIPCHK(c, launch_locality(xm, n, (float2 *)c->buf[B_RANGE].p, (unsigned short *)c->buf[B_CELL].p,
+                            (unsigned *)c->buf[B_CCOUNT].p, (unsigned *)c->buf[B_CCURSOR].p, p, st),
+         "locality");
   *perm = p;
   return NBODY_OK;
 }
@@ -383,6 +394,28 @@ int nbody_set_params(nbody_ctx *c, const nbody_params *p) {
 }
 
 const char *nbody_last_error(const nbody_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int nbody_reserve(nbody_ctx *c, int64_t n, uint32_t what, void *stream) {
+  TRY(check_n(c, n));
+  if (what & ~(uint32_t)(NBODY_RESERVE_KICK | NBODY_RESERVE_LIST | NBODY_RESERVE_CE))
+    return fail(c, NBODY_E_INVAL, "unknown reservation flags 0x%x", what);
+  hipStream_t st = (hipStream_t)stream;
+  const int N = (int)n;
+  KickArgs a;
+  TRY(make_kick_args(c, N, nullptr, nullptr, (what & NBODY_RESERVE_KICK) != 0, (what & NBODY_RESERVE_CE) != 0,
+                     (what & NBODY_RESERVE_LIST) != 0, a));
+  if ((what & NBODY_RESERVE_LIST) &&
+      (!ensure(c, B_ROWTOT, (size_t)n * sizeof(int64_t)) || !ensure(c, B_BSUM, (size_t)nblocks(n) * sizeof(int64_t))))
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (emission)");
+  const int nbf = fin_blocks(n);
+  if (!ensure(c, B_THR, (size_t)n * sizeof(double4)) || !ensure(c, B_MOM_A, (size_t)nbf * sizeof(double4)) ||
+      !ensure(c, B_MOM_B, (size_t)nbf * sizeof(double4)) ||
+      !ensure(c, B_MPART, (size_t)nblocks(n) * sizeof(double2)) || !ensure(c, B_UNI, sizeof(double2)))
+    return fail(c, NBODY_E_NOMEM, "workspace allocation failed (step)");
+  if (N >= c->locality_min_n) TRY(locality_bufs(c, N, st));
+  HIPCHK(c, hipStreamSynchronize(st), "reserve sync");
+  return NBODY_OK;
+}
 
 int nbody_rcrit(nbody_ctx *c, int64_t n, const double *xm, const double *v, double *thr,
                 void *stream) {

@@ -63,6 +63,27 @@ __device__ __forceinline__ double close_weight(double r2, double rcij, double f_
   return K / r3 - (dKdy / span) / r2;
 }
 
+// As close_weight for a pair inside the changeover span (y < 1): stores w and returns true. At
+// y >= 1 the pair has the far weight 1/r^3 and the function returns false, so that the caller
+// keeps its own far-pair value: a pair flagged only by thresholds widened beyond rc (the list
+// margin of the changeover levels) then gets exactly the bits of an unflagged pair.
+__device__ __forceinline__ bool close_weight_inner(double r2, double rcij, double f_in, double &w) {
+  const double r = sqrt(r2);
+  const double span = (1.0 - f_in) * rcij;
+  const double y = (r - f_in * rcij) / span;
+  if (y >= 1.0) return false;
+  if (y <= 0.0) {
+    w = 0.0;
+    return true;
+  }
+  const double r3 = r2 * r;
+  const double D = 2.0 * y * y - 2.0 * y + 1.0;
+  const double K = y * y / D;
+  const double dKdy = 2.0 * y * (1.0 - y) / (D * D);
+  w = K / r3 - (dKdy / span) / r2;
+  return true;
+}
+
 // m * r^-3 from the hardware reciprocal-square-root seed (relative error about 2^-24) and the
 // second-order expansion of (1 - e)^(-3/2), e = 1 - r2 y^2: result within a few ulp.
 // c15 = 1.5 and c1875 = 1.875 arrive as kernel arguments: kept in loop-invariant registers

@@ -30,8 +30,8 @@ __device__ __forceinline__ void close_part(const double4 *__restrict__ thr, int 
       const double4 ti = thr[ii];
       const double4 tq = thr[j];
       if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
-        if (FORCE) {
-          const double w = close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
+        double w;
+        if (FORCE && close_weight_inner(r2, ti.x > tq.x ? ti.x : tq.x, f_in, w)) {
           const double sn = UNI ? w : mj * w;
           if (CE) {
             const double ds = s - sn;

@@ -64,6 +64,9 @@ def test_invalid_arguments_rejected_on_host(L):
         assert L.nbody_encounters(h, 10, None, None, None, 0, None, None) == E_INVAL
         assert L.nbody_step(h, 10, None, None, None, 1, None, 0, None, None, None) == E_INVAL
         assert L.nbody_validate(h, 10, None, None, None, None) == E_INVAL
+        assert L.nbody_reserve(h, 10, 8, None) == E_INVAL          # unknown reservation flag
+        assert b"flags" in L.nbody_last_error(h)
+        assert L.nbody_reserve(h, 0, 1, None) == E_INVAL
         assert L.nbody_validate(h, 0, 64, 64, 64, None) == E_INVAL
         # misaligned pointer is refused before any device call
         assert L.nbody_rcrit(h, 10, 8, 8, 8, None) == E_INVAL

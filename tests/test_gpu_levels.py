@@ -73,7 +73,7 @@ def test_zero_levels_is_the_hybrid_step(ctx):
     assert torch.equal(X1, X2) and torch.equal(V1, V2)
 
 
-def test_levels_split_the_percolating_group(ctx):
+def test_levels_split_the_percolating_group(nb, ctx):
     """The 32768-body disk: its close pairs form one group of 9470 bodies, too large for the direct
     integrator; one intermediate level (s = 8) hands it only small groups. 2 steps against the
     oracle's recursion."""
@@ -82,7 +82,8 @@ def test_levels_split_the_percolating_group(ctx):
     d = diskgen.workload("disk32768")
     X, V = dev_state(d)
     thr = ctx.rcrit(X, V)
-    plain = ctx.step_hybrid(X.clone(), V.clone(), 1, thr=thr)
+    with pytest.warns(nb.NBodyWarning, match="Kepler orbits only"):
+        plain = ctx.step_hybrid(X.clone(), V.clone(), 1, thr=thr)
     assert plain["too_large"] >= 1          # groups above 64 bodies (only Kepler orbits)
     stats = ctx.step_hybrid(X, V, 2, thr=thr, levels=1, substeps=8, margin=0.5)
     othr = oracle.thresholds(d["x"], d["v"], d["m"], p)

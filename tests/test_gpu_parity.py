@@ -574,10 +574,12 @@ def test_step_hybrid_matches_oracle_and_conserves_energy(ctx):
     assert dE < 3e-10
 
 
-def test_step_hybrid_reports_oversized_groups(ctx):
-    """A clump of 300 bodies forms one group above the 64 a wave integrates: reported."""
+def test_step_hybrid_reports_oversized_groups(nb, ctx):
+    """A clump of 300 bodies forms one group above the 64 a wave integrates: reported in the
+    statistics and as a warning of the binding."""
     say("step_hybrid clump")
     d = cluster_disk(4096, 300)
     X, V = to_dev(d)
-    stats = ctx.step_hybrid(X, V, 1)
+    with pytest.warns(nb.NBodyWarning, match="Kepler orbits only"):
+        stats = ctx.step_hybrid(X, V, 1)
     assert stats["too_large"] >= 1 and stats["largest"] >= 0

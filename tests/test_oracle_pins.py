@@ -48,6 +48,36 @@ def test_changeover_endpoints_and_symmetry():
         assert d > 0
 
 
+def test_changeover_interior_values():
+    """Hand values of the changeover of reading 1 (Chambers' K = y^2/(2y^2 - 2y + 1)): at y = 1/4,
+    D = 1/8 - 1/2 + 1 = 5/8, so K = (1/16)/(5/8) = 1/10 and dK/dy = 2y(1-y)/D^2 = (3/8)(64/25) = 24/25;
+    at y = 3/4, K = (9/16)/(10/16) = 9/10 with the same slope; at y = 1/2, D = 1/2 and the slope is
+    (1/2)/(1/4) = 2. Any other symmetric C1 step (for instance 3y^2 - 2y^3, which gives 5/32 and 9/8
+    at y = 1/4 and slope 3/2 at 1/2) fails these."""
+    for y, K, dK in ((0.25, 0.1, 0.96), (0.75, 0.9, 0.96), (0.5, 0.5, 2.0)):
+        k, d = oracle.changeover(y)
+        assert abs(k - K) <= 2e-17 and abs(d - dK) <= 4e-16, (y, k, d)
+
+
+def test_kick_in_changeover_span_closed_form(params):
+    """Two bodies inside the changeover span, with hand-made thresholds (H = 0, V = rc^2, so the
+    pair is close exactly when r < rc = 1) and f_in = 1/2: at r = 0.625, y = (0.625 - 0.5)/0.5 = 1/4,
+    K = 1/10, dK/dr = (24/25)/0.5, and the kick weight is w = K/r^3 - (dK/dr)/r^2
+    = 0.1/0.244140625 - 1.92/0.390625 = 0.4096 - 4.9152 = -4.5056 (the changeover's slope pushes the
+    pair apart); the close-encounter part is 1/r^3 - w = 4.096 + 4.5056 = 8.6016. This pins the
+    kick's interior form (the gradient of K/r, eq. Hb) to numbers worked out by hand."""
+    p = P(f_in=0.5)
+    x = np.array([[1.0, 0.0, 0.0], [1.0, 0.375, 0.5]])      # |d| = 0.625
+    m = np.array([2e-3, 5e-3])
+    thr = (np.array([1.0, 1.0]), np.zeros(2), np.array([1.0, 1.0]))
+    acc, ce, _ = oracle.kick_acc(x, m, thr, p)
+    d = np.array([0.0, 0.375, 0.5])
+    np.testing.assert_allclose(acc[0], 5e-3 * -4.5056 * d, rtol=1e-14)
+    np.testing.assert_allclose(acc[1], -2e-3 * -4.5056 * d, rtol=1e-14)
+    np.testing.assert_allclose(ce[0], 5e-3 * 8.6016 * d, rtol=1e-14)
+    np.testing.assert_allclose(acc[0] + ce[0], 5e-3 * d / 0.625 ** 3, rtol=1e-15)
+
+
 def test_changeover_quad_agrees():
     for y in np.linspace(0.0, 1.0, 21):
         assert abs(oracle.changeover(y)[0] - oracle.changeover(y, quad=True)[0]) < 4e-16
