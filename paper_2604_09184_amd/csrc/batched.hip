@@ -44,7 +44,7 @@ struct BatchArgs {
   double4 *part;         // workspace [grid][2 * kWaves][64]: partial sums of cut row blocks
   unsigned long long *npairs;  // [nsys] close pairs at the final positions (or null)
   unsigned *queue;
-  double G, m0, dt, f_in, cH, cV, n1, n2dt, c15, c1875;
+  double G, m0, dt, f_in, cH, cV, n1, n2dt, c15;
 };
 
 __device__ __forceinline__ int size_class(int n) {
@@ -117,12 +117,12 @@ __device__ __forceinline__ bool tile_equal_mass(const double4 *X, int N, double 
 template <bool UNI>
 __device__ __forceinline__ void pair_lds(const double4 &xi, const double4 &pj, uint32_t tj, int j,
                                          const double4 *__restrict__ thr, int ii, bool valid,
-                                         uint32_t tw, double f_in, double c15, double c1875,
+                                         uint32_t tw, double f_in, double c15,
                                          double (&acc)[3], unsigned &npairs, bool count) {
   const uint32_t U = tw > tj ? tw : tj;
   const double dx = pj.x - xi.x, dy = pj.y - xi.y, dz = pj.z - xi.z;
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  double s = UNI ? rinv3(r2, c15, c1875) : m_rinv3(r2, pj.w, c15, c1875);
+  double s = UNI ? rinv3(r2, c15) : m_rinv3(r2, pj.w, c15);
   if (hiword(r2) <= U) {
     if (j == ii) {
       s = 0.0;
@@ -148,11 +148,11 @@ template <bool UNI>
 __device__ __forceinline__ void kick_rows(const double4 *X, const uint32_t *T,
                                           const double4 *__restrict__ thr, int ii, bool valid,
                                           uint32_t tw, int j0, int j1, double f_in, double c15,
-                                          double c1875, double (&acc)[3], unsigned &npairs,
+                                          double (&acc)[3], unsigned &npairs,
                                           bool count) {
   const double4 xi = X[ii];
-  // 1.5 held in a VGPR for the whole loop: the expansion's fma already reads 1.875 from an SGPR,
-  // and one VOP3 instruction reads at most one scalar operand
+  // 1.5 held in a VGPR for the whole loop: one VOP3 instruction reads at most one scalar operand,
+  // and the correction's fma already reads the j-body's data from SGPRs
   double c15v;
   asm volatile("v_mov_b64 %0, %1" : "=v"(c15v) : "s"(c15));
   int j = j0;
@@ -166,11 +166,11 @@ __device__ __forceinline__ void kick_rows(const double4 *X, const uint32_t *T,
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      pair_lds<UNI>(xi, p[q], t[q], j + q, thr, ii, valid, tw, f_in, c15v, c1875, acc, npairs, count);
+      pair_lds<UNI>(xi, p[q], t[q], j + q, thr, ii, valid, tw, f_in, c15v, acc, npairs, count);
   }
   for (; j < j1; ++j)
     pair_lds<UNI>(xi, X[j], __builtin_amdgcn_readfirstlane(T[j]), j, thr, ii, valid, tw, f_in, c15v,
-                  c1875, acc, npairs, count);
+                  acc, npairs, count);
 }
 
 // v += h G a (napply times) for body ii; adds m v to P.
@@ -209,7 +209,7 @@ __device__ __forceinline__ void kick_wave(const BatchArgs &a, int64_t o, int N, 
     const bool valid = i < N;
     const int ii = valid ? i : N - 1;
     double acc[3] = {0.0, 0.0, 0.0};
-    kick_rows<UNI>(X, T, a.thr + o, ii, valid, rows_tw(T, ii), 0, N, a.f_in, a.c15, a.c1875, acc,
+    kick_rows<UNI>(X, T, a.thr + o, ii, valid, rows_tw(T, ii), 0, N, a.f_in, a.c15, acc,
                    npairs, count);
     if (valid) kick_apply<UNI>(a, o, X, ii, acc, h, napply, P);
   }
@@ -238,7 +238,7 @@ __device__ __forceinline__ void kick_group(const BatchArgs &a, int64_t o, int N,
     const int ii = valid ? i : N - 1;
     double acc[3] = {0.0, 0.0, 0.0};
     kick_rows<UNI>(X, T, a.thr + o, ii, valid, rows_tw(T, ii), c0 * jc, min(N, c1 * jc), a.f_in,
-                   a.c15, a.c1875, acc, npairs, count);
+                   a.c15, acc, npairs, count);
     if (c0 == 0 && c1 == C) {
       if (valid) kick_apply<UNI>(a, o, X, ii, acc, h, napply, P);
     } else {
@@ -380,7 +380,7 @@ hipError_t launch_batched(const BatchLaunch &b, hipStream_t st) {
   a.offs = b.offs; a.order = b.order; a.cfg = b.cfg; a.nsys = b.nsys; a.nsteps = b.nsteps;
   a.xm = b.xm; a.v = b.v; a.thr = b.thr; a.part = b.part; a.npairs = b.npairs; a.queue = b.queue;
   a.G = b.G; a.m0 = b.m0; a.dt = b.dt; a.f_in = b.f_in; a.cH = b.cH; a.cV = b.cV; a.n1 = b.n1;
-  a.n2dt = b.n2dt; a.c15 = 1.5; a.c1875 = 1.875;
+  a.n2dt = b.n2dt; a.c15 = 1.5;
   hipError_t e = hipMemsetAsync(b.queue, 0, sizeof(unsigned), st);
   if (e != hipSuccess) return e;
   if (b.npairs) {

@@ -24,7 +24,11 @@ __device__ __forceinline__ void close_part(const double4 *__restrict__ thr, int 
   const uint32_t tj = hiword(thr[j].w);
   const uint32_t U = tw > tj ? tw : tj;
   if (hiword(r2) <= U) {
-    if (j == ii) {
+    // j taken through an empty asm statement: the compiler otherwise turns j == ii into a
+    // per-lane induction variable that costs a vector add on every pair of the fast path
+    int jj = j;
+    asm volatile("" : "+s"(jj));
+    if (jj == ii) {
       s = 0.0;
     } else {
       const double4 ti = thr[ii];
@@ -41,8 +45,8 @@ __device__ __forceinline__ void close_part(const double4 *__restrict__ thr, int 
           }
           s = sn;
         }
-        if (EMIT && valid && j > ii) {
-          if (nc < R) rowbuf[((size_t)blockIdx.y * R + nc) * n + ii] = j;
+        if (EMIT && valid && jj > ii) {
+          if (nc < R) rowbuf[((size_t)blockIdx.y * R + nc) * n + ii] = jj;
           ++nc;
         }
       }
@@ -55,14 +59,14 @@ template <bool EMIT, bool CE, bool SPLIT, bool UNI>
 __device__ __forceinline__ void pair_force(const double4 *__restrict__ thr, const double4 &pi,
                                            const double4 &pj, int ii, bool valid, uint32_t tw, int j,
                                            int n, double f_in, int *__restrict__ rowbuf, int R,
-                                           double c15, double c1875, bool screened, double (&a)[3],
+                                           double c15, bool screened, double (&a)[3],
                                            double (&ce)[3], int &nc) {
   const double dx = pj.x - pi.x;
   const double dy = pj.y - pi.y;
   const double dz = pj.z - pi.z;
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   const double mj = UNI ? 1.0 : pj.w;
-  double s = SPLIT ? m_rinv3_split(r2, mj) : (UNI ? rinv3(r2, c15, c1875) : m_rinv3(r2, mj, c15, c1875));
+  double s = SPLIT ? m_rinv3_split(r2, mj) : (UNI ? rinv3(r2, c15) : m_rinv3(r2, mj, c15));
   if (screened)
     close_part<true, EMIT, CE, UNI>(thr, ii, valid, tw, j, n, f_in, rowbuf, R, r2, dx, dy, dz, mj, s,
                                     ce, nc);
@@ -91,15 +95,15 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
                                            const double4 *__restrict__ thr, double4 pi, int ii,
                                            bool valid, uint32_t tw, int j0, int j1, int n,
                                            double f_in, int *__restrict__ rowbuf, int R,
-                                           double c15, double c1875, double (&a)[3],
+                                           double c15, double (&a)[3],
                                            double (&ce)[3], int &nc) {
   const int lane = threadIdx.x & 63;
   // lanes past n hold body n - 1, a real body: the box stays conservative
   const double bx0 = wave_min_f64(pi.x), bx1 = wave_max_f64(pi.x);
   const double by0 = wave_min_f64(pi.y), by1 = wave_max_f64(pi.y);
   const double bz0 = wave_min_f64(pi.z), bz1 = wave_max_f64(pi.z);
-  // 1.5 held in a VGPR for the whole loop: the expansion's fma already reads 1.875 from an SGPR,
-  // and one VOP3 instruction reads at most one scalar operand
+  // 1.5 held in a VGPR for the whole loop: one VOP3 instruction reads at most one scalar operand,
+  // and the j-body's coordinates arrive in SGPRs
   double c15v;
   asm volatile("v_mov_b64 %0, %1" : "=v"(c15v) : "s"(c15));
   for (int jb = j0; jb < j1; jb += 64) {
@@ -132,20 +136,29 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
       }
       continue;
     }
-    // j-bodies fetched two at a time, so their scalar loads overlap
+    // j-bodies two at a time; the scalar loads of the next two are issued before the arithmetic
+    // of the current two, so their latency hides behind it
     int j = jb;
-    for (; j + 2 <= je; j += 2) {
-      double4 pq[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) pq[q] = xm[j + q];
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-        pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, pq[q], ii, valid, tw, j + q, n, f_in, rowbuf, R,
-                                         c15v, c1875, (mask >> (j + q - jb)) & 1ull, a, ce, nc);
+    if (j + 2 <= je) {
+      double4 c0 = xm[j], c1 = xm[j + 1];
+      for (; j + 4 <= je; j += 2) {
+        const double4 n0 = xm[j + 2], n1 = xm[j + 3];
+        pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, c0, ii, valid, tw, j, n, f_in, rowbuf, R, c15v,
+                                         (mask >> (j - jb)) & 1ull, a, ce, nc);
+        pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, c1, ii, valid, tw, j + 1, n, f_in, rowbuf, R, c15v,
+                                         (mask >> (j + 1 - jb)) & 1ull, a, ce, nc);
+        c0 = n0;
+        c1 = n1;
+      }
+      pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, c0, ii, valid, tw, j, n, f_in, rowbuf, R, c15v,
+                                       (mask >> (j - jb)) & 1ull, a, ce, nc);
+      pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, c1, ii, valid, tw, j + 1, n, f_in, rowbuf, R, c15v,
+                                       (mask >> (j + 1 - jb)) & 1ull, a, ce, nc);
+      j += 2;
     }
     for (; j < je; ++j)
       pair_force<EMIT, CE, SPLIT, UNI>(thr, pi, xm[j], ii, valid, tw, j, n, f_in, rowbuf, R, c15v,
-                                       c1875, (mask >> (j - jb)) & 1ull, a, ce, nc);
+                                       (mask >> (j - jb)) & 1ull, a, ce, nc);
   }
 }
 
@@ -159,7 +172,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                                                   double f_in, double4 *__restrict__ part,
                                                   double4 *__restrict__ part_ce,
                                                   int *__restrict__ cnt, int *__restrict__ rowbuf,
-                                                  int R, double c15, double c1875) {
+                                                  int R, double c15) {
   const int lane_body = blockIdx.x * kBlock + threadIdx.x;
   const bool valid = lane_body < n;
   const int lb = valid ? lane_body : n - 1;
@@ -181,10 +194,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
   }
   if (uniform)
     pairs_loop<FORCE, EMIT, CE, SPLIT, true>(xm, thr, pi, ii, valid, tw, j0, j1, n, f_in, rowbuf, R,
-                                             c15, c1875, a, ce, nc);
+                                             c15, a, ce, nc);
   else
     pairs_loop<FORCE, EMIT, CE, SPLIT, false>(xm, thr, pi, ii, valid, tw, j0, j1, n, f_in, rowbuf,
-                                              R, c15, c1875, a, ce, nc);
+                                              R, c15, a, ce, nc);
   if (!valid) return;
   const size_t o = (size_t)blockIdx.y * n + ii;
   if (FORCE) {
@@ -203,7 +216,7 @@ template <bool F, bool E, bool C, bool S>
 static void go(const KickArgs &a, hipStream_t st) {
   dim3 grid(nblocks(a.n), a.nchunk);
   hipLaunchKernelGGL((k_pairs<F, E, C, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.uni,
-                     a.n, a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5, 1.875);
+                     a.n, a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5);
 }
 
 hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool split,
