@@ -54,6 +54,29 @@ __device__ __forceinline__ void close_part(const double4 *__restrict__ thr, int 
   }
 }
 
+// r^-3 (times m_j unless all masses are equal) of one pair, and the offsets it multiplies.
+template <bool SPLIT, bool UNI>
+__device__ __forceinline__ double pair_weight(const double4 &pi, const double4 &pj, double c15,
+                                              double &dx, double &dy, double &dz, double &r2) {
+  dx = pj.x - pi.x;
+  dy = pj.y - pi.y;
+  dz = pj.z - pi.z;
+  r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  return SPLIT ? m_rinv3_split(r2, UNI ? 1.0 : pj.w)
+               : (UNI ? rinv3(r2, c15) : m_rinv3(r2, pj.w, c15));
+}
+
+// One pair of a j-block with no close pair: the fast path alone.
+template <bool SPLIT, bool UNI>
+__device__ __forceinline__ void pair_far(const double4 &pi, const double4 &pj, double c15,
+                                         double (&a)[3]) {
+  double dx, dy, dz, r2;
+  const double s = pair_weight<SPLIT, UNI>(pi, pj, c15, dx, dy, dz, r2);
+  a[0] = fma(s, dx, a[0]);
+  a[1] = fma(s, dy, a[1]);
+  a[2] = fma(s, dz, a[2]);
+}
+
 // One pair of the force loop: r^-3 on the fast path; close_part only for a screened-in j.
 template <bool EMIT, bool CE, bool SPLIT, bool UNI>
 __device__ __forceinline__ void pair_force(const double4 *__restrict__ thr, const double4 &pi,
@@ -61,15 +84,11 @@ __device__ __forceinline__ void pair_force(const double4 *__restrict__ thr, cons
                                            int n, double f_in, int *__restrict__ rowbuf, int R,
                                            double c15, bool screened, double (&a)[3],
                                            double (&ce)[3], int &nc) {
-  const double dx = pj.x - pi.x;
-  const double dy = pj.y - pi.y;
-  const double dz = pj.z - pi.z;
-  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  const double mj = UNI ? 1.0 : pj.w;
-  double s = SPLIT ? m_rinv3_split(r2, mj) : (UNI ? rinv3(r2, c15) : m_rinv3(r2, mj, c15));
+  double dx, dy, dz, r2;
+  double s = pair_weight<SPLIT, UNI>(pi, pj, c15, dx, dy, dz, r2);
   if (screened)
-    close_part<true, EMIT, CE, UNI>(thr, ii, valid, tw, j, n, f_in, rowbuf, R, r2, dx, dy, dz, mj, s,
-                                    ce, nc);
+    close_part<true, EMIT, CE, UNI>(thr, ii, valid, tw, j, n, f_in, rowbuf, R, r2, dx, dy, dz,
+                                    UNI ? 1.0 : pj.w, s, ce, nc);
   a[0] = fma(s, dx, a[0]);
   a[1] = fma(s, dy, a[1]);
   a[2] = fma(s, dz, a[2]);
@@ -136,8 +155,26 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
       }
       continue;
     }
-    // j-bodies two at a time; the scalar loads of the next two are issued before the arithmetic
-    // of the current two, so their latency hides behind it
+    if (mask == 0 && je - jb == 64) {
+      // the common case: a whole block with no pair near enough to need the predicate. No
+      // per-j branch; the j-bodies alternate between two pairs of scalar registers, each pair
+      // loaded one step ahead of its use (the last step reloads bodies 62 and 63, unused)
+      const double4 *__restrict__ xb = xm + jb;
+      double4 c0 = xb[0], c1 = xb[1];
+      for (int k = 0; k < 64; k += 4) {
+        const double4 n0 = xb[k + 2], n1 = xb[k + 3];
+        pair_far<SPLIT, UNI>(pi, c0, c15v, a);
+        pair_far<SPLIT, UNI>(pi, c1, c15v, a);
+        const int kk = min(k + 4, 62);
+        c0 = xb[kk];
+        c1 = xb[kk + 1];
+        pair_far<SPLIT, UNI>(pi, n0, c15v, a);
+        pair_far<SPLIT, UNI>(pi, n1, c15v, a);
+      }
+      continue;
+    }
+    // a block with screened-in j (or a partial block): j-bodies two at a time, the scalar loads
+    // of the next two issued before the arithmetic of the current two
     int j = jb;
     if (j + 2 <= je) {
       double4 c0 = xm[j], c1 = xm[j + 1];
@@ -165,7 +202,7 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
 // Register budget for seven waves per SIMD (72 VGPRs): enough to keep two j-bodies in flight
 // without spilling, and enough waves to hide the scalar-load and reciprocal-square-root latency.
 template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_pairs(const double4 *__restrict__ xm,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(const double4 *__restrict__ xm,
                                                   const double4 *__restrict__ thr,
                                                   const int *__restrict__ perm,
                                                   const double2 *__restrict__ uni, int n, int chunk,
