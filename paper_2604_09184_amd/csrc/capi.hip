@@ -317,7 +317,7 @@ int group_bufs(nbody_ctx *c, int n, GroupBufs &g) {
   g.gfill = (int *)ensure(c, B_GFILL, b);
   g.gmem = (int *)ensure(c, B_GMEM, b);
   g.groot = (int *)ensure(c, B_GROOT, b);
-  g.counter = (int *)ensure(c, B_GCNT, 2 * sizeof(int));
+  g.counter = (int *)ensure(c, B_GCNT, kGroupCounters * sizeof(int));
   if (!g.mark || !g.in || !g.gsize || !g.gstart || !g.gfill || !g.gmem || !g.groot || !g.counter)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
   return NBODY_OK;

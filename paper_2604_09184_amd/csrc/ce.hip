@@ -15,9 +15,12 @@
 // One workgroup of four waves per group of at most 64 bodies (the work layout is described at the
 // integrator below): the positions of other members arrive by lane shuffles, every step-size
 // decision is taken on wave-wide reductions of identical data in every wave, so the integration is
-// uniform across the workgroup and deterministic.
+// uniform across the workgroup and deterministic. The launch holds only resident workgroups; they
+// take groups from a queue until the device-side group count is exhausted.
 #include "internal.hpp"
 #include "kepler_core.hpp"
+
+#include <algorithm>
 
 namespace nbk {
 using namespace nbd;
@@ -33,10 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_gmark(const int *__restrict__ label,
     gsize[i] = 0;
     gfill[i] = 0;
   }
-  if (i == 0) {
-    counter[0] = 0;
-    counter[1] = 0;
-  }
+  if (i < kGroupCounters) counter[i] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_gmark2(const int *__restrict__ label, int n,
@@ -88,11 +88,11 @@ __global__ __launch_bounds__(kBlock) void k_gfill(const int *__restrict__ label,
 // same state, so the waves stay in step without further exchange.
 //
 // Within a wave, body slot s (0 <= s < k) sits on the P lanes s P + r, r = 0 .. P - 1, with
-// P = min(64/kp, 16) and kp the power of two at or above k: replica r sums the pair terms of every
+// P = min(kp, 64/kp) and kp the power of two at or above k: replica r sums the pair terms of every
 // P-th member, and the replicas' partial sums meet in a butterfly inside a 16-lane row made of DPP
 // moves (lane exchanges xor 1 and xor 2, then the half-row and row mirrors), each stage an addition
-// of two equal-sized partial sums in either order, so every replica ends with the same bits. Small
-// groups thus spread their pair sums over the whole wave.
+// of two equal-sized partial sums in either order, so every replica ends with the same bits. A group
+// of up to 8 bodies thus needs one pair term per replica and log2(kp) butterfly stages.
 constexpr int kCeWaves = 4;
 constexpr int kMaxMacroSteps = 20000;
 constexpr int kMaxBisections = 80;       // contact-time bisection: at most 80 halvings of a step
@@ -438,15 +438,12 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
 // becomes massless, of zero radius, parked on a circular orbit of radius kParkRadius about the
 // central mass at the angle 2 pi j/n, and is held fixed for the rest of the drift. Each merger is
 // logged as {step, survivor, removed} with its time within the drift.
-__global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
-    double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
-    const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
-    const int *__restrict__ groot, const int *__restrict__ ngroups, double G, double m0,
-    double f_in, double h, double tol, unsigned long long *__restrict__ stats, CeCollide col,
-    LevelThr lt) {
-  __shared__ CeShared sh;
-  const int w = blockIdx.x;
-  if (w >= *ngroups) return;
+__device__ __forceinline__ void ce_group(
+    int w, CeShared &sh, double4 *__restrict__ xm, double4 *__restrict__ v,
+    const double4 *__restrict__ thr, const int *__restrict__ gmem, const int *__restrict__ gstart,
+    const int *__restrict__ gsize, const int *__restrict__ groot, double G, double m0, double f_in,
+    double h, double tol, unsigned long long *__restrict__ stats, const CeCollide &col,
+    const LevelThr &lt) {
   const int r = groot[w];
   const int k = gsize[r];
   const int base = gstart[r];
@@ -469,7 +466,7 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
   const int lane = threadIdx.x & 63;
   int kp = 1;
   while (kp < k) kp <<= 1;
-  L.P = min(64 / kp, 16);
+  L.P = min(kp, 64 / kp);
   L.slot = lane / L.P;
   L.rep = lane & (L.P - 1);
   L.iters = (k + L.P - 1) / L.P;
@@ -610,6 +607,26 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
   }
 }
 
+// Resident workgroups take groups from a queue (counter[2]) until all counter[0] groups are done.
+__global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
+    double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
+    const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
+    const int *__restrict__ groot, int *__restrict__ counter, double G, double m0, double f_in,
+    double h, double tol, unsigned long long *__restrict__ stats, CeCollide col, LevelThr lt) {
+  __shared__ CeShared sh;
+  __shared__ int next;
+  const int ng = counter[0];
+  while (true) {
+    if (threadIdx.x == 0) next = atomicAdd(counter + 2, 1);
+    __syncthreads();
+    const int w = next;
+    __syncthreads();
+    if (w >= ng) break;
+    ce_group(w, sh, xm, v, thr, gmem, gstart, gsize, groot, G, m0, f_in, h, tol, stats, col, lt);
+    __syncthreads();
+  }
+}
+
 // stats[5] += 1 when an encounter list was truncated (count > cap): its groups are incomplete.
 __global__ void k_list_overflow(const int64_t *__restrict__ count, int64_t cap,
                                 unsigned long long *__restrict__ stats) {
@@ -635,14 +652,26 @@ hipError_t launch_group_lists(const int *label, int n, int *mark, int *in, int *
 }
 
 hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
-                           const int *gstart, const int *gsize, const int *groot,
-                           const int *ngroups, int max_groups, double G, double m0, double f_in,
-                           double h, double tol, unsigned long long *stats, const CeCollide &col,
-                           const LevelThr &lt, hipStream_t st) {
-  if (max_groups > 0)
-    hipLaunchKernelGGL(k_ce_drift, dim3(max_groups), dim3(64 * kCeWaves), 0, st, xm, v, thr, gmem,
-                       gstart, gsize,
-                       groot, ngroups, G, m0, f_in, h, tol, stats, col, lt);
+                           const int *gstart, const int *gsize, const int *groot, int *counter,
+                           int max_groups, double G, double m0, double f_in, double h, double tol,
+                           unsigned long long *stats, const CeCollide &col, const LevelThr &lt,
+                           hipStream_t st) {
+  // resident workgroups only: the queue hands out the groups (the device count is not known here)
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, per = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ce_drift, 64 * kCeWaves, 0);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per) * prop.multiProcessorCount;
+  }
+  const int grid = std::min(max_groups, resident);
+  if (grid > 0)
+    hipLaunchKernelGGL(k_ce_drift, dim3(grid), dim3(64 * kCeWaves), 0, st, xm, v, thr, gmem, gstart,
+                       gsize, groot, counter, G, m0, f_in, h, tol, stats, col, lt);
   return hipGetLastError();
 }
 

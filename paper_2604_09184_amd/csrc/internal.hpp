@@ -82,11 +82,14 @@ struct LevelThr {
   int nl;
 };
 
+// counter [kGroupCounters]: [0] groups, [1] member slots allocated, [2] queue of the drift kernel
+// (zeroed by launch_group_lists).
+constexpr int kGroupCounters = 8;
 hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
-                           const int *gstart, const int *gsize, const int *groot,
-                           const int *ngroups, int max_groups, double G, double m0, double f_in,
-                           double h, double tol, unsigned long long *stats, const CeCollide &col,
-                           const LevelThr &lt, hipStream_t st);
+                           const int *gstart, const int *gsize, const int *groot, int *counter,
+                           int max_groups, double G, double m0, double f_in, double h, double tol,
+                           unsigned long long *stats, const CeCollide &col, const LevelThr &lt,
+                           hipStream_t st);
 
 // levels.hip: symmetric adjacency of a pair list (rows sorted by neighbour index), the level kicks
 // over it and the masks of the level drifts.
