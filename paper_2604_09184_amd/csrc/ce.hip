@@ -98,10 +98,32 @@ constexpr int kMaxMacroSteps = 20000;
 constexpr int kMaxBisections = 80;       // contact-time bisection: at most 80 halvings of a step
 constexpr double kParkRadius = 1e6;      // orbit radius of bodies merged away
 
+// x from the lane that DPP control CTRL names (within a 16-lane row), in two 32-bit moves.
+template <int CTRL>
+__device__ __forceinline__ double ce_dpp(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Largest value over the wave, uniform: DPP maxima inside each 16-lane row, then the four rows
+// through scalar registers.
 __device__ __forceinline__ double wave_max_d(double x) {
+  x = fmax(x, ce_dpp<0xB1>(x));
+  x = fmax(x, ce_dpp<0x4E>(x));
+  x = fmax(x, ce_dpp<0x141>(x));
+  x = fmax(x, ce_dpp<0x140>(x));
+  const long long b = __double_as_longlong(x);
+  double m = 0.0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-  return x;
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), 16 * r);
+    const double q = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    m = r == 0 ? q : fmax(m, q);
+  }
+  return m;
 }
 
 // r^-1 to a few ulp: the hardware reciprocal square root (relative error about 2^-24) refined by
@@ -171,6 +193,7 @@ __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const Ce
 //
 // With intermediate changeover levels the pair potential is weighted by W = prod_l [1 - K_l] (one
 // factor per level, each with its own rc_l), and the coefficient is G m_j (W/r^3 - W'(r)/r^2).
+template <bool NL1>
 __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p, const CeLane &L,
                                         const CeShared &sh, double &a0, double &a1, double &a2) {
   const double dx = __shfl(z[0], p.src, 64) - z[0];
@@ -181,7 +204,7 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
   const double r = r2 * ir;
   const double f_in = L.f_in;
   double c;
-  if (L.nl == 1) {
+  if (NL1) {
     const bool mine = L.rc > p.m.rc;
     const double rcij = mine ? L.rc : p.m.rc;
     const double isp = mine ? L.ispan : p.m.ispan;
@@ -211,14 +234,6 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
   a2 = fma(cm, dz, a2);
 }
 
-// x from the lane that DPP control CTRL names (within a 16-lane row), in two 32-bit moves.
-template <int CTRL>
-__device__ __forceinline__ double ce_dpp(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 template <int CTRL>
 __device__ __forceinline__ void ce_row_add(double &a0, double &a1, double &a2) {
@@ -231,22 +246,23 @@ __device__ __forceinline__ void ce_row_add(double &a0, double &a1, double &a2) {
 constexpr int kCeRegPartners = 4;
 
 // f = (v, a) of this lane's body at the state z.
+template <bool NL1>
 __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, const CeShared &sh,
                                        const CePartner (&pr)[kCeRegPartners], bool alive,
                                        double (&f)[6]) {
   const int P = L.P;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (L.iters == 1) {
-    ce_pair(z, pr[0], L, sh, a0, a1, a2);
+    ce_pair<NL1>(z, pr[0], L, sh, a0, a1, a2);
   } else {
     // independent terms side by side (masked beyond the members)
 #pragma unroll
-    for (int u = 0; u < kCeRegPartners; ++u) ce_pair(z, pr[u], L, sh, a0, a1, a2);
+    for (int u = 0; u < kCeRegPartners; ++u) ce_pair<NL1>(z, pr[u], L, sh, a0, a1, a2);
     for (int it = kCeRegPartners; it < L.iters; it += kCeRegPartners) {
 #pragma unroll
       for (int u = 0; u < kCeRegPartners; ++u) {
         const CePartner p = ce_partner(L.rep + (it + u) * P, L, sh);
-        ce_pair(z, p, L, sh, a0, a1, a2);
+        ce_pair<NL1>(z, p, L, sh, a0, a1, a2);
       }
     }
   }
@@ -267,19 +283,20 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
 }
 
 // Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
+template <bool NL1>
 __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, const CeLane &L,
                                          const CeShared &sh, const CePartner (&pr)[kCeRegPartners],
                                          bool alive, double (&est)[6]) {
   const double hs = H / ns;
   double zm[6], zc[6], f[6];
-  ce_rhs(y, L, sh, pr, alive, f);
+  ce_rhs<NL1>(y, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
     zc[i] = y[i] + hs * f[i];
   }
   for (int s = 1; s < ns; ++s) {
-    ce_rhs(zc, L, sh, pr, alive, f);
+    ce_rhs<NL1>(zc, L, sh, pr, alive, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const double zn = zm[i] + 2.0 * hs * f[i];
@@ -287,7 +304,7 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
       zc[i] = zn;
     }
   }
-  ce_rhs(zc, L, sh, pr, alive, f);
+  ce_rhs<NL1>(zc, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zc[i] + zm[i] + hs * f[i]);
 }
@@ -317,6 +334,7 @@ __device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale
 
 // One macro-step attempt over H from y (all four waves together): returns the accepted column
 // (identical in every wave) or -1; y1 receives the accepted extrapolant.
+template <bool NL1>
 __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool alive, const CeLane &L,
                                           CeShared &sh, const CePartner (&pr)[kCeRegPartners],
                                           int &buf, double (&y1)[6]) {
@@ -328,7 +346,7 @@ __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool a
   for (int cc = 0; cc < 2; ++cc) {
     const int c = cc == 0 ? L.wv : 7 - L.wv;
     double est[6];
-    ce_sweep(y, H, 2 * c + 2, L, sh, pr, alive, est);
+    ce_sweep<NL1>(y, H, 2 * c + 2, L, sh, pr, alive, est);
     if (L.rep == 0)
 #pragma unroll
       for (int i = 0; i < 6; ++i) sh.est[buf][c][i][L.slot] = est[i];
@@ -393,6 +411,7 @@ __device__ __forceinline__ int ce_contact(const double (&y)[6], double fR, const
 // followed by a contact test and the integration stops at the first step that ends in contact: y
 // then holds that step's start, done the time covered before it and Hc its length. Returns 0
 // (covered), 1 (contact) or 2 (H halved 60 times in a row, or too many macro steps).
+template <bool NL1, bool COL>
 __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool check, bool alive,
                                           double fR, const CeLane &L, CeShared &sh,
                                           const CePartner (&pr)[kCeRegPartners], int &buf,
@@ -403,14 +422,14 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
     if (++macro > kMaxMacroSteps) return 2;
     if (fabs(H) > fabs(Ltot - t)) H = Ltot - t;
     double y1[6];
-    const int c = ce_attempt(y, H, alive, L, sh, pr, buf, y1);
+    const int c = ce_attempt<NL1>(y, H, alive, L, sh, pr, buf, y1);
     if (c < 0) {
       H = H / 2.0;
       if (++halvings > 60) return 2;
       continue;
     }
     halvings = 0;
-    if (check && ce_contact(y1, fR, L, sh, pr) >= 0) {
+    if (COL && check && ce_contact(y1, fR, L, sh, pr) >= 0) {
       done = t;
       Hc = H;
       return 1;
@@ -438,6 +457,7 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
 // becomes massless, of zero radius, parked on a circular orbit of radius kParkRadius about the
 // central mass at the angle 2 pi j/n, and is held fixed for the rest of the drift. Each merger is
 // logged as {step, survivor, removed} with its time within the drift.
+template <bool NL1, bool COL>
 __device__ __forceinline__ void ce_group(
     int w, CeShared &sh, double4 *__restrict__ xm, double4 *__restrict__ v,
     const double4 *__restrict__ thr, const int *__restrict__ gmem, const int *__restrict__ gstart,
@@ -481,7 +501,7 @@ __device__ __forceinline__ void ce_group(
   L.ispan = 1.0 / ((1.0 - f_in) * L.rc);
   L.rank = 0;
   for (int q = 0; q < k; ++q) L.rank += gmem[base + q] < b;
-  const bool collide = col.radius != nullptr;
+  const bool collide = COL;
   const double R0 = collide ? col.radius[b] : 0.0;
   if (L.wv == 0 && L.rep == 0 && L.act) {
     sh.owner[L.rank] = L.slot;
@@ -516,7 +536,7 @@ __device__ __forceinline__ void ce_group(
       L_int = phase == 1 ? mid : hi;
     }
     double done = 0.0, Hc = 0.0;
-    const int st = ce_advance(y, L_int, collide && phase == 0, alive, fR, L, sh, pr, buf, done, Hc);
+    const int st = ce_advance<NL1, COL>(y, L_int, collide && phase == 0, alive, fR, L, sh, pr, buf, done, Hc);
     if (st == 2) { status = 1; break; }
     if (phase == 0) {
       if (st == 0) break;
@@ -608,6 +628,7 @@ __device__ __forceinline__ void ce_group(
 }
 
 // Resident workgroups take groups from a queue (counter[2]) until all counter[0] groups are done.
+template <bool NL1, bool COL>
 __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
     const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
@@ -622,7 +643,7 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     const int w = next;
     __syncthreads();
     if (w >= ng) break;
-    ce_group(w, sh, xm, v, thr, gmem, gstart, gsize, groot, G, m0, f_in, h, tol, stats, col, lt);
+    ce_group<NL1, COL>(w, sh, xm, v, thr, gmem, gstart, gsize, groot, G, m0, f_in, h, tol, stats, col, lt);
     __syncthreads();
   }
 }
@@ -657,21 +678,28 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
                            unsigned long long *stats, const CeCollide &col, const LevelThr &lt,
                            hipStream_t st) {
   // resident workgroups only: the queue hands out the groups (the device count is not known here)
-  static int resident = 0;
-  if (resident == 0) {
-    int dev = 0, per = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ce_drift, 64 * kCeWaves, 0);
-    if (e != hipSuccess) return e;
-    resident = std::max(1, per) * prop.multiProcessorCount;
-  }
-  const int grid = std::min(max_groups, resident);
-  if (grid > 0)
-    hipLaunchKernelGGL(k_ce_drift, dim3(grid), dim3(64 * kCeWaves), 0, st, xm, v, thr, gmem, gstart,
-                       gsize, groot, counter, G, m0, f_in, h, tol, stats, col, lt);
+  if (max_groups <= 0) return hipSuccess;
+  const bool nl1 = lt.nl == 1, col_on = col.radius != nullptr;
+#define NBK_CE(A, B)                                                                                \
+  do {                                                                                              \
+    static int resident = 0;                                                                        \
+    if (resident == 0) {                                                                            \
+      int dev = 0, per = 0;                                                                         \
+      hipDeviceProp_t prop;                                                                         \
+      hipError_t e = hipGetDevice(&dev);                                                            \
+      if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);                                  \
+      if (e == hipSuccess)                                                                          \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ce_drift<A, B>, 64 * kCeWaves, 0); \
+      if (e != hipSuccess) return e;                                                                \
+      resident = std::max(1, per) * prop.multiProcessorCount;                                       \
+    }                                                                                               \
+    hipLaunchKernelGGL((k_ce_drift<A, B>), dim3(std::min(max_groups, resident)), dim3(64 * kCeWaves), \
+                       0, st, xm, v, thr, gmem, gstart, gsize, groot, counter, G, m0, f_in, h, tol,  \
+                       stats, col, lt);                                                             \
+  } while (0)
+  if (nl1) { if (col_on) NBK_CE(true, true); else NBK_CE(true, false); }
+  else { if (col_on) NBK_CE(false, true); else NBK_CE(false, false); }
+#undef NBK_CE
   return hipGetLastError();
 }
 
