@@ -196,9 +196,14 @@ __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const Ce
 template <bool NL1>
 __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p, const CeLane &L,
                                         const CeShared &sh, double &a0, double &a1, double &a2) {
-  const double dx = __shfl(z[0], p.src, 64) - z[0];
-  const double dy = __shfl(z[1], p.src, 64) - z[1];
-  const double dz = __shfl(z[2], p.src, 64) - z[2];
+  // a term that does not count (no member, or the lane's own body) is moved 1e30 away: there the
+  // changeover weight is exactly zero, so the term adds exactly zero with no branch. The exchange
+  // runs on every lane (a lane shuffle reads only from active lanes), and the offset is added to
+  // its result
+  const double off = p.use ? 0.0 : 1e30;
+  const double dx = (__shfl(z[0], p.src, 64) - z[0]) + off;
+  const double dy = (__shfl(z[1], p.src, 64) - z[1]) + off;
+  const double dz = (__shfl(z[2], p.src, 64) - z[2]) + off;
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double ir = ce_rinv(r2);
   const double r = r2 * ir;
@@ -228,7 +233,7 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
     }
     c = ir * ir * (W * ir - dW);
   }
-  const double cm = p.use ? c * p.m.Gm : 0.0;
+  const double cm = c * p.m.Gm;
   a0 = fma(cm, dx, a0);
   a1 = fma(cm, dy, a1);
   a2 = fma(cm, dz, a2);
@@ -245,14 +250,20 @@ __device__ __forceinline__ void ce_row_add(double &a0, double &a1, double &a2) {
 // Partners of a lane kept in registers; members beyond them are read from LDS.
 constexpr int kCeRegPartners = 4;
 
-// f = (v, a) of this lane's body at the state z.
-template <bool NL1>
+// f = (v, a) of this lane's body at the state z. PT > 0: P = PT replicas and one partner per
+// replica (groups of up to 8 bodies), known at compile time; PT = 0: P and the partner count from L.
+template <bool NL1, int PT>
 __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, const CeShared &sh,
                                        const CePartner (&pr)[kCeRegPartners], bool alive,
                                        double (&f)[6]) {
-  const int P = L.P;
+  const int P = PT > 0 ? PT : L.P;
+  // the central term first: it does not depend on the partners, so its latency overlaps their
+  // exchange
+  const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+  const double ir = ce_rinv(r2);
+  const double s = -L.Gm0 * (ir * ir * ir);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  if (L.iters == 1) {
+  if (PT > 0 || L.iters == 1) {
     ce_pair<NL1>(z, pr[0], L, sh, a0, a1, a2);
   } else {
     // independent terms side by side (masked beyond the members)
@@ -270,9 +281,6 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
   if (P >= 4) ce_row_add<0x4E>(a0, a1, a2);    // quad_perm [2, 3, 0, 1]: lane xor 2
   if (P >= 8) ce_row_add<0x141>(a0, a1, a2);   // half-row mirror: lane i <-> 7 - i
   if (P >= 16) ce_row_add<0x140>(a0, a1, a2);  // row mirror: lane i <-> 15 - i
-  const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
-  const double ir = ce_rinv(r2);
-  const double s = -L.Gm0 * (ir * ir * ir);
   // a body merged away is held fixed
   f[0] = alive ? z[3] : 0.0;
   f[1] = alive ? z[4] : 0.0;
@@ -283,20 +291,20 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
 }
 
 // Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
-template <bool NL1>
+template <bool NL1, int PT>
 __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, const CeLane &L,
                                          const CeShared &sh, const CePartner (&pr)[kCeRegPartners],
                                          bool alive, double (&est)[6]) {
   const double hs = H / ns;
   double zm[6], zc[6], f[6];
-  ce_rhs<NL1>(y, L, sh, pr, alive, f);
+  ce_rhs<NL1, PT>(y, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
     zc[i] = y[i] + hs * f[i];
   }
   for (int s = 1; s < ns; ++s) {
-    ce_rhs<NL1>(zc, L, sh, pr, alive, f);
+    ce_rhs<NL1, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const double zn = zm[i] + 2.0 * hs * f[i];
@@ -304,7 +312,7 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
       zc[i] = zn;
     }
   }
-  ce_rhs<NL1>(zc, L, sh, pr, alive, f);
+  ce_rhs<NL1, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zc[i] + zm[i] + hs * f[i]);
 }
@@ -334,7 +342,7 @@ __device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale
 
 // One macro-step attempt over H from y (all four waves together): returns the accepted column
 // (identical in every wave) or -1; y1 receives the accepted extrapolant.
-template <bool NL1>
+template <bool NL1, int PT>
 __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool alive, const CeLane &L,
                                           CeShared &sh, const CePartner (&pr)[kCeRegPartners],
                                           int &buf, double (&y1)[6]) {
@@ -346,7 +354,7 @@ __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool a
   for (int cc = 0; cc < 2; ++cc) {
     const int c = cc == 0 ? L.wv : 7 - L.wv;
     double est[6];
-    ce_sweep<NL1>(y, H, 2 * c + 2, L, sh, pr, alive, est);
+    ce_sweep<NL1, PT>(y, H, 2 * c + 2, L, sh, pr, alive, est);
     if (L.rep == 0)
 #pragma unroll
       for (int i = 0; i < 6; ++i) sh.est[buf][c][i][L.slot] = est[i];
@@ -411,7 +419,7 @@ __device__ __forceinline__ int ce_contact(const double (&y)[6], double fR, const
 // followed by a contact test and the integration stops at the first step that ends in contact: y
 // then holds that step's start, done the time covered before it and Hc its length. Returns 0
 // (covered), 1 (contact) or 2 (H halved 60 times in a row, or too many macro steps).
-template <bool NL1, bool COL>
+template <bool NL1, bool COL, int PT>
 __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool check, bool alive,
                                           double fR, const CeLane &L, CeShared &sh,
                                           const CePartner (&pr)[kCeRegPartners], int &buf,
@@ -422,7 +430,7 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
     if (++macro > kMaxMacroSteps) return 2;
     if (fabs(H) > fabs(Ltot - t)) H = Ltot - t;
     double y1[6];
-    const int c = ce_attempt<NL1>(y, H, alive, L, sh, pr, buf, y1);
+    const int c = ce_attempt<NL1, PT>(y, H, alive, L, sh, pr, buf, y1);
     if (c < 0) {
       H = H / 2.0;
       if (++halvings > 60) return 2;
@@ -536,7 +544,17 @@ __device__ __forceinline__ void ce_group(
       L_int = phase == 1 ? mid : hi;
     }
     double done = 0.0, Hc = 0.0;
-    const int st = ce_advance<NL1, COL>(y, L_int, collide && phase == 0, alive, fR, L, sh, pr, buf, done, Hc);
+    // the replica layout of groups of up to 8 bodies is a compile-time constant of the integrator
+    const bool chk = collide && phase == 0;
+    int st;
+    if (L.iters == 1 && L.P == 2)
+      st = ce_advance<NL1, COL, 2>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
+    else if (L.iters == 1 && L.P == 4)
+      st = ce_advance<NL1, COL, 4>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
+    else if (L.iters == 1 && L.P == 8)
+      st = ce_advance<NL1, COL, 8>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
+    else
+      st = ce_advance<NL1, COL, 0>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
     if (st == 2) { status = 1; break; }
     if (phase == 0) {
       if (st == 0) break;
