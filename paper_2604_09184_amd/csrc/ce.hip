@@ -173,6 +173,7 @@ struct CePartner {
   int src, q;
   bool use;
   CeMember m;
+  double rcij, isp;   // the pair's critical radius max(rc_i, rc_j) and 1/((1 - f_in) rc_ij)
 };
 
 __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const CeShared &sh) {
@@ -183,6 +184,9 @@ __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const Ce
   p.src = sh.owner[qq] * L.P;
   p.use = L.act && valid && sh.owner[qq] != L.slot;
   p.m = sh.mem[qq];
+  const bool mine = L.rc > p.m.rc;
+  p.rcij = mine ? L.rc : p.m.rc;
+  p.isp = mine ? L.ispan : p.m.ispan;
   return p;
 }
 
@@ -210,9 +214,7 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
   const double f_in = L.f_in;
   double c;
   if (NL1) {
-    const bool mine = L.rc > p.m.rc;
-    const double rcij = mine ? L.rc : p.m.rc;
-    const double isp = mine ? L.ispan : p.m.ispan;
+    const double rcij = p.rcij, isp = p.isp;
     const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
     const double omy = 1.0 - y;
     const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
@@ -303,18 +305,24 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
     zm[i] = y[i];
     zc[i] = y[i] + hs * f[i];
   }
-  for (int s = 1; s < ns; ++s) {
+  // z_{m+1} = z_{m-1} + 2 hs f(z_m), m = 1 .. ns - 1, two steps per iteration so that the two state
+  // arrays trade roles without copies (ns is even: one step is left over at the end)
+  const double h2 = 2.0 * hs;
+  for (int s = 1; s + 1 < ns; s += 2) {
     ce_rhs<NL1, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const double zn = zm[i] + 2.0 * hs * f[i];
-      zm[i] = zc[i];
-      zc[i] = zn;
-    }
+    for (int i = 0; i < 6; ++i) zm[i] = zm[i] + h2 * f[i];
+    ce_rhs<NL1, PT>(zm, L, sh, pr, alive, f);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zc[i] = zc[i] + h2 * f[i];
   }
   ce_rhs<NL1, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zc[i] + zm[i] + hs * f[i]);
+  for (int i = 0; i < 6; ++i) zm[i] = zm[i] + h2 * f[i];
+  // now zm = z_ns and zc = z_{ns-1}
+  ce_rhs<NL1, PT>(zm, L, sh, pr, alive, f);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zm[i] + zc[i] + hs * f[i]);
 }
 
 // Aitken-Neville over the eight sweeps (substep counts 2c + 2) of one component: T[c][0] = e[c],
@@ -430,7 +438,7 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
     if (++macro > kMaxMacroSteps) return 2;
     if (fabs(H) > fabs(Ltot - t)) H = Ltot - t;
     double y1[6];
-    const int c = ce_attempt<NL1, PT>(y, H, alive, L, sh, pr, buf, y1);
+    const int c = ce_attempt<NL1, PT>(y, H, COL ? alive : true, L, sh, pr, buf, y1);
     if (c < 0) {
       H = H / 2.0;
       if (++halvings > 60) return 2;
