@@ -111,6 +111,19 @@ int nbody_kick(nbody_ctx *ctx, int64_t n, const double *xm, const double *thr, d
                double *acc, double *acc_ce, void *stream);
 
 /*
+ * nbody_kick without allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kick and outputs
+ * as nbody_kick, with its workspace (partial sums, equal-mass flag) in a 32 MiB device array
+ * the library holds per device until the process ends, instead of the context's workspace. It
+ * calls no allocating routine. Sizes whose workspace exceeds the array (n above about 1e6, or
+ * about 5e5 with acc_ce) are rejected with NBODY_E_INVAL. The j-chunk count may be lower than
+ * nbody_kick's, so sums may differ from it in the last bits. Calls that overlap on one device
+ * (other streams or threads) share the array and race.
+ */
+int nbody_kick_noalloc(nbody_ctx *ctx, int64_t n, const double *xm, const double *thr, double *v,
+                       double h, double *acc, double *acc_ce, void *stream);
+
+/*
  * Close-encounter pairs (the pairs inside the critical radius, eq. rcrit): i < j with
  *   (r2*r2)*r2 < max(H_i, H_j)  or  r2 < max(V_i, V_j),
  *   r2 = fma(dz,dz,fma(dy,dy,dx*dx)), d = x_j - x_i,

@@ -78,6 +78,7 @@ EXPORTS = {
     "nbody_reserve": [_I64, ctypes.c_uint32, _P],
     "nbody_rcrit": [_I64, _P, _P, _P, _P],
     "nbody_kick": [_I64, _P, _P, _P, _D, _P, _P, _P],
+    "nbody_kick_noalloc": [_I64, _P, _P, _P, _D, _P, _P, _P],
     "nbody_encounters": [_I64, _P, _P, _P, _I64, _P, _P],
     "nbody_jump": [_I64, _P, _P, _D, _P],
     "nbody_drift": [_I64, _P, _P, _D, _P, _P],
@@ -200,6 +201,14 @@ class Context:
             _body(t, nm)
         self._check(lib().nbody_kick(self._h, xm.shape[0], _ptr(xm), _ptr(thr), _ptr(v), float(h),
                                      _ptr(acc), _ptr(acc_ce), _stream()), "nbody_kick")
+        return acc
+
+    def kick_noalloc(self, xm, thr, v=None, h=0.0, acc=None, acc_ce=None):
+        """nbody_kick with the workspace in the library's per-device array (no allocation)."""
+        for t, nm in ((xm, "xm"), (thr, "thr"), (v, "v"), (acc, "acc"), (acc_ce, "acc_ce")):
+            _body(t, nm)
+        self._check(lib().nbody_kick_noalloc(self._h, xm.shape[0], _ptr(xm), _ptr(thr), _ptr(v), float(h),
+                                             _ptr(acc), _ptr(acc_ce), _stream()), "nbody_kick_noalloc")
         return acc
 
     def accelerations(self, xm, thr, with_ce=False):
