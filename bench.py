@@ -136,6 +136,16 @@ def variant_batched(nb, p):
     X = torch.tensor(xm, device="cuda:0")
     V = torch.tensor(v4, device="cuda:0")
     ctx = nb.Context(nb.Params(**p))
+    # every tile code applied to all classes, 20 steps each (on copies): what the autotuner chooses from
+    per_code = {}
+    for code in range(4):
+        ctx.set_batched_tiles([code] * 6)
+        Xc, Vc = X.clone(), V.clone()
+        ctx.step_batched(offs, Xc, Vc, 2)
+        Xc, Vc = X.clone(), V.clone()
+        t_code, _ = timed(lambda: ctx.step_batched(offs, Xc, Vc, 20))
+        per_code[code] = round(t_code * 1e3, 2)
+    ctx.set_batched_tiles([0] * 6)
     t_tune, tiles = timed(lambda: ctx.autotune_batched(offs, X, V, nsteps=10))
     sec, _ = timed(lambda: ctx.step_batched(offs, X, V, 100))
     sizes = offs[1:] - offs[:-1]
@@ -144,6 +154,7 @@ def variant_batched(nb, p):
     return {"workload": "ensemble4096", "systems": len(sizes), "bodies": int(offs[-1]), "steps": 100,
             "pairs_per_s": pairs / sec, "seconds": round(sec, 4), "tiles": tiles,
             "autotune_seconds": round(t_tune, 3),
+            "ms_20_steps_per_uniform_code": per_code,
             "roofline": {"bound": "alu", "kernel": "k_batched (binary64, one launch)",
                          "achieved": round(ach, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(ach / FP64_VECTOR_PEAK_TFLOPS, 4)}}

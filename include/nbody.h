@@ -323,21 +323,24 @@ int nbody_tune(nbody_ctx *ctx, const char *name, int64_t value);
  * HOST array of nsys+1 int64 with offs[0] = 0 and 1 <= offs[s+1]-offs[s] <= 2048. npairs
  * (device uint64 [nsys], may be NULL) receives each system's number of close pairs at its final
  * positions. Workgroups take systems largest first; the tile used for a system (one workgroup
- * or one wave per system) comes from the context's table of size classes (N <= 64, 128, 256,
- * 512, 1024, 2048). The result of a system depends only on its own bodies and its tile, not on
+ * or one wave per system, one or two bodies per lane) comes from the context's table of size
+ * classes (N <= 64, 128, 256, 512, 1024, 2048). The result of a system depends only on its own bodies and its tile, not on
  * the rest of the ensemble. The call returns when the work is complete.
  */
 int nbody_step_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, double *xm, double *v,
                        int32_t nsteps, uint64_t *npairs, void *stream);
 
 /*
- * Autotuner of the batched tiles. Tile codes: 0 = one workgroup (eight waves) per system, 1 = one
- * wave per system (applies to systems of at most 256 bodies; larger ones use 0). One sweep over
- * the classes present, largest first: the whole ensemble is timed for nsteps steps (on scratch
- * copies; xm and v are not modified) with each code for that class, the other classes keeping
- * theirs; the other code replaces the current one only if it is more than 3 % faster. Use
- * nsteps of 10 or more: very short runs favour the wave tile. get/set read or replace the table (host array of 6 codes);
- * get returns the number of classes.
+ * Autotuner of the batched tiles ("self-tuning routines", section "The GENGA code"). A tile code
+ * is a bit set: bit 0 set = one wave per system (applies to systems of at most 256 bodies; larger
+ * ones run as if it were clear), clear = one workgroup (eight waves) per system; bit 1 set = each
+ * lane of the kick owns two bodies (one j-body read serves two pairs), clear = one. Codes 0 .. 3.
+ * One sweep over the classes present, largest first: the whole ensemble is timed for nsteps steps
+ * (on scratch copies; xm and v are not modified) with each admissible code for that class, in
+ * order and then in reverse order, the other classes keeping theirs; another code replaces the
+ * current one only if it is more than 3 % faster. Use nsteps of 10 or more: very short runs
+ * favour the wave tile. get/set read or replace the table (host array of 6 codes); get returns the
+ * number of classes.
  */
 int nbody_autotune_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, const double *xm,
                            const double *v, int32_t nsteps, void *stream);

@@ -2,13 +2,14 @@
 // nsteps steps B C A C B, all in one persistent launch.
 //
 // Scheduling: workgroups take systems from an atomic queue ordered largest first (longest
-// processing time first). A system runs with one of two tiles chosen per size class:
+// processing time first). A system runs with the tile its size class's code names:
 //   group tile - the eight waves of the workgroup share one system (up to 2048 bodies),
-//   wave tile  - every wave owns a system of its own (up to 256 bodies).
-// Once a workgroup meets a wave-tile system it stays in that mode: the queue is sorted, so
-// everything after it is small as well.
+//   wave tile  - every wave owns a system of its own (up to 256 bodies),
+// and, in either, one or two bodies per lane in the kick (two: each j-body read from LDS serves
+// two pairs, half the LDS traffic per pair). Once a workgroup meets a wave-tile system it stays in
+// that mode: the queue is sorted, so everything after it is small as well.
 //
-// Group-tile balance: the kick of a system with rb row blocks of 64 bodies is cut into rb * C
+// Group-tile balance: the kick of a system with rb row blocks of 64 (or 128) bodies is cut into rb * C
 // tiles (row block, j-chunk), C = 8 / gcd(rb, 8), so that every wave gets the same number of
 // consecutive tiles. A wave accumulates the chunks of one row block in registers; a row block
 // cut by a wave boundary leaves one partial sum per wave in a small per-workgroup scratch area
@@ -29,6 +30,7 @@ constexpr int kBB = 512;                 // threads per workgroup of the batched
 constexpr int kWaves = kBB / 64;
 constexpr int kMaxGroupN = 2048;
 constexpr int kMaxWaveN = 256;
+constexpr int kMaxIpl = 2;               // bodies per lane of the kick: 1 or 2
 static_assert(kWaves * kMaxWaveN == kMaxGroupN, "LDS regions of the two tiles coincide");
 static_assert(kWaves == kBatchedWaves, "scratch sizing on the host");
 
@@ -112,8 +114,36 @@ __device__ __forceinline__ bool tile_equal_mass(const double4 *X, int N, double 
   return lo == hi;
 }
 
-// One pair (ii, j) of the LDS kick: adds the contribution of body j (position/mass pj, prefilter
-// word tj) to acc.
+// The close-pair part of one pair that passed the per-pair prefilter: the exact predicate and the
+// changeover weight. Kept out of line: it is rarely taken, and inlined into the unrolled pair loop
+// its temporaries would crowd out the registers of the common path.
+struct CloseOut {
+  double s;
+  unsigned counted;
+};
+
+template <bool UNI>
+__device__ __attribute__((noinline)) CloseOut close_lds(double r2, double s, double mj, int j, int ii,
+                                                        bool valid, bool count,
+                                                        const double4 *__restrict__ thr,
+                                                        double f_in) {
+  CloseOut o{s, 0u};
+  if (j == ii) {
+    o.s = 0.0;
+    return o;
+  }
+  const double4 ti = thr[ii];
+  const double4 tq = thr[j];
+  if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
+    const double w = close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
+    o.s = UNI ? w : mj * w;
+    if (count && valid && j > ii) o.counted = 1u;
+  }
+  return o;
+}
+
+// One pair (ii, j) of the LDS kick: r^-3, and for a pair that passes the per-pair prefilter
+// hi(r2) <= max(T_i, T_j) the close-pair part.
 template <bool UNI>
 __device__ __forceinline__ void pair_lds(const double4 &xi, const double4 &pj, uint32_t tj, int j,
                                          const double4 *__restrict__ thr, int ii, bool valid,
@@ -124,53 +154,58 @@ __device__ __forceinline__ void pair_lds(const double4 &xi, const double4 &pj, u
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   double s = UNI ? rinv3(r2, c15) : m_rinv3(r2, pj.w, c15);
   if (hiword(r2) <= U) {
-    if (j == ii) {
-      s = 0.0;
-    } else {
-      const double4 ti = thr[ii];
-      const double4 tq = thr[j];
-      if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
-        const double w = close_weight(r2, ti.x > tq.x ? ti.x : tq.x, f_in);
-        s = UNI ? w : pj.w * w;
-        if (count && valid && j > ii) ++npairs;
-      }
-    }
+    const CloseOut o = close_lds<UNI>(r2, s, pj.w, j, ii, valid, count, thr, f_in);
+    s = o.s;
+    npairs += o.counted;
   }
   acc[0] = fma(s, dx, acc[0]);
   acc[1] = fma(s, dy, acc[1]);
   acc[2] = fma(s, dz, acc[2]);
 }
 
-// Adds to acc the accelerations (without G; without m when UNI) on body ii from bodies j0..j1-1
-// in LDS, in ascending j. tw = wave maximum of the prefilter words of the wave's bodies. The
-// j-bodies are read four at a time, so one LDS address serves all four.
-template <bool UNI>
+// Adds to acc[k] the accelerations (without G; without m when UNI) on the bodies ii[k],
+// k < IPL, of every lane from the bodies j0..j1-1 in LDS, in ascending j. Each j-body read from LDS
+// (one broadcast address for the wave) serves IPL pairs per lane; the j-bodies are read 4 / IPL at
+// a time. tw = wave maximum of the prefilter words of the lanes' bodies. (A block screen as in the
+// single-system pair kernel does not pay here: a wave's bodies span a large part of a small
+// system, so few j-blocks would pass it.)
+template <bool UNI, int IPL>
 __device__ __forceinline__ void kick_rows(const double4 *X, const uint32_t *T,
-                                          const double4 *__restrict__ thr, int ii, bool valid,
-                                          uint32_t tw, int j0, int j1, double f_in, double c15,
-                                          double (&acc)[3], unsigned &npairs,
-                                          bool count) {
-  const double4 xi = X[ii];
-  // 1.5 held in a VGPR for the whole loop: one VOP3 instruction reads at most one scalar operand,
-  // and the correction's fma already reads the j-body's data from SGPRs
+                                          const double4 *__restrict__ thr, const int (&ii)[IPL],
+                                          const bool (&valid)[IPL], uint32_t tw, int j0, int j1,
+                                          double f_in, double c15, double (&acc)[IPL][3],
+                                          unsigned &npairs, bool count) {
+  double4 xi[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) xi[k] = X[ii[k]];
+  // 1.5 held in a VGPR for the whole loop: one VOP3 instruction reads at most one scalar operand
   double c15v;
   asm volatile("v_mov_b64 %0, %1" : "=v"(c15v) : "s"(c15));
+  // JU j-bodies per iteration: four pairs per lane in flight
+  constexpr int JU = 4 / IPL;
   int j = j0;
-  for (; j + 4 <= j1; j += 4) {
-    double4 p[4];
-    uint32_t t[4];
+  for (; j + JU <= j1; j += JU) {
+    double4 p[JU];
+    uint32_t t[JU];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < JU; ++q) {
       p[q] = X[j + q];
       t[q] = __builtin_amdgcn_readfirstlane(T[j + q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      pair_lds<UNI>(xi, p[q], t[q], j + q, thr, ii, valid, tw, f_in, c15v, acc, npairs, count);
+    for (int q = 0; q < JU; ++q)
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+        pair_lds<UNI>(xi[k], p[q], t[q], j + q, thr, ii[k], valid[k], tw, f_in, c15v, acc[k], npairs,
+                      count);
   }
-  for (; j < j1; ++j)
-    pair_lds<UNI>(xi, X[j], __builtin_amdgcn_readfirstlane(T[j]), j, thr, ii, valid, tw, f_in, c15v,
-                  acc, npairs, count);
+  for (; j < j1; ++j) {
+    const double4 p = X[j];
+    const uint32_t t = __builtin_amdgcn_readfirstlane(T[j]);
+#pragma unroll
+    for (int k = 0; k < IPL; ++k)
+      pair_lds<UNI>(xi[k], p, t, j, thr, ii[k], valid[k], tw, f_in, c15v, acc[k], npairs, count);
+  }
 }
 
 // v += h G a (napply times) for body ii; adds m v to P.
@@ -193,91 +228,112 @@ __device__ __forceinline__ void kick_apply(const BatchArgs &a, int64_t o, const 
   P[0] += m * vi.x; P[1] += m * vi.y; P[2] += m * vi.z;
 }
 
-__device__ __forceinline__ uint32_t rows_tw(const uint32_t *T, int ii) {
-  return __builtin_amdgcn_readfirstlane(wave_max_u32(T[ii]));
+// The lane's bodies of row block r (IPL * 64 bodies): ii[k] = r IPL 64 + k 64 + lane (clamped to
+// N - 1 past the end) and the wave maximum of their prefilter words.
+template <int IPL>
+__device__ __forceinline__ uint32_t row_bodies(const uint32_t *T, int N, int r, int (&ii)[IPL],
+                                               bool (&valid)[IPL]) {
+  const int lane = threadIdx.x & 63;
+  uint32_t t = 0;
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    const int i = (r * IPL + k) * 64 + lane;
+    valid[k] = i < N;
+    ii[k] = valid[k] ? i : N - 1;
+    t = max(t, T[ii[k]]);
+  }
+  return __builtin_amdgcn_readfirstlane(wave_max_u32(t));
 }
 
 // Kick of a wave-tile system: the wave owns every row block.
-template <bool UNI>
+template <bool UNI, int IPL>
 __device__ __forceinline__ void kick_wave(const BatchArgs &a, int64_t o, int N, const double4 *X,
                                           const uint32_t *T, double h, int napply, bool count,
                                           double (&P)[3], unsigned &npairs) {
-  const int lane = threadIdx.x & 63;
   P[0] = P[1] = P[2] = 0.0;
-  for (int r = 0; r * 64 < N; ++r) {
-    const int i = r * 64 + lane;
-    const bool valid = i < N;
-    const int ii = valid ? i : N - 1;
-    double acc[3] = {0.0, 0.0, 0.0};
-    kick_rows<UNI>(X, T, a.thr + o, ii, valid, rows_tw(T, ii), 0, N, a.f_in, a.c15, acc,
-                   npairs, count);
-    if (valid) kick_apply<UNI>(a, o, X, ii, acc, h, napply, P);
+  for (int r = 0; r * IPL * 64 < N; ++r) {
+    int ii[IPL];
+    bool valid[IPL];
+    const uint32_t tw = row_bodies<IPL>(T, N, r, ii, valid);
+    double acc[IPL][3] = {};
+    kick_rows<UNI, IPL>(X, T, a.thr + o, ii, valid, tw, 0, N, a.f_in, a.c15, acc, npairs, count);
+#pragma unroll
+    for (int k = 0; k < IPL; ++k)
+      if (valid[k]) kick_apply<UNI>(a, o, X, ii[k], acc[k], h, napply, P);
   }
 }
 
-// Kick of a group-tile system: wave w takes tiles [w per, (w+1) per) of the rb * C tiles, tile
-// t = (row block t / C, j-chunk t % C).
-template <bool UNI>
+// Kick of a group-tile system: rb row blocks of IPL * 64 bodies; wave w takes tiles
+// [w per, (w+1) per) of the rb * C tiles, tile t = (row block t / C, j-chunk t % C).
+template <bool UNI, int IPL>
 __device__ __forceinline__ void kick_group(const BatchArgs &a, int64_t o, int N, const double4 *X,
                                            const uint32_t *T, double h, int napply, bool count,
                                            double (&P)[3], unsigned &npairs) {
   // wave index made provably uniform, so that the tile bounds and the j-loop live in SGPRs
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int rb = (N + 63) >> 6;
+  const int rb = (N + IPL * 64 - 1) / (IPL * 64);
   const int low = rb & -rb;                                  // largest power of two dividing rb
   const int C = kWaves / (low < kWaves ? low : kWaves);      // kWaves / gcd(rb, kWaves)
   const int per = rb * C / kWaves;
   const int jc = (N + C - 1) / C;
-  double4 *slot = a.part + (size_t)blockIdx.x * (2 * kWaves * 64);
+  double4 *slot = a.part + (size_t)blockIdx.x * (2 * kWaves * 64 * kMaxIpl);
   P[0] = P[1] = P[2] = 0.0;
   const int t0 = w * per, t1 = t0 + per;
   for (int r = t0 / C; r * C < t1; ++r) {
     const int c0 = max(t0, r * C) - r * C, c1 = min(t1, (r + 1) * C) - r * C;
-    const int i = r * 64 + lane;
-    const bool valid = i < N;
-    const int ii = valid ? i : N - 1;
-    double acc[3] = {0.0, 0.0, 0.0};
-    kick_rows<UNI>(X, T, a.thr + o, ii, valid, rows_tw(T, ii), c0 * jc, min(N, c1 * jc), a.f_in,
-                   a.c15, acc, npairs, count);
+    int ii[IPL];
+    bool valid[IPL];
+    const uint32_t tw = row_bodies<IPL>(T, N, r, ii, valid);
+    double acc[IPL][3] = {};
+    kick_rows<UNI, IPL>(X, T, a.thr + o, ii, valid, tw, c0 * jc, min(N, c1 * jc), a.f_in, a.c15,
+                        acc, npairs, count);
     if (c0 == 0 && c1 == C) {
-      if (valid) kick_apply<UNI>(a, o, X, ii, acc, h, napply, P);
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+        if (valid[k]) kick_apply<UNI>(a, o, X, ii[k], acc[k], h, napply, P);
     } else {
-      slot[(2 * w + (r == t0 / C ? 0 : 1)) * 64 + lane] = make_double4(acc[0], acc[1], acc[2], 0.0);
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+        slot[((2 * w + (r == t0 / C ? 0 : 1)) * kMaxIpl + k) * 64 + lane] =
+            make_double4(acc[k][0], acc[k][1], acc[k][2], 0.0);
     }
   }
   __syncthreads();
-  // row blocks cut by a wave boundary, in order; the k-th goes to wave k
-  int k = 0, rprev = -1;
+  // row blocks cut by a wave boundary, in order; the q-th goes to wave q
+  int q = 0, rprev = -1;
   for (int bnd = 1; bnd < kWaves; ++bnd) {
     const int tb = bnd * per;
     if (tb % C == 0) continue;
     const int r = tb / C;
     if (r == rprev) continue;
     rprev = r;
-    if (k++ != w) continue;
-    const int i = r * 64 + lane;
+    if (q++ != w) continue;
     const int wl = ((r + 1) * C - 1) / per;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int q = (r * C) / per; q <= wl; ++q) {
-      const double4 s = slot[(2 * q + (r == (q * per) / C ? 0 : 1)) * 64 + lane];
-      acc[0] += s.x; acc[1] += s.y; acc[2] += s.z;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      const int i = (r * IPL + k) * 64 + lane;
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (int u = (r * C) / per; u <= wl; ++u) {
+        const double4 s = slot[((2 * u + (r == (u * per) / C ? 0 : 1)) * kMaxIpl + k) * 64 + lane];
+        acc[0] += s.x; acc[1] += s.y; acc[2] += s.z;
+      }
+      if (i < N) kick_apply<UNI>(a, o, X, i, acc, h, napply, P);
     }
-    if (i < N) kick_apply<UNI>(a, o, X, i, acc, h, napply, P);
   }
 }
 
-template <bool GROUP, bool UNI>
+template <bool GROUP, bool UNI, int IPL>
 __device__ __forceinline__ void kick_system(const BatchArgs &a, int64_t o, int N, const double4 *X,
                                             const uint32_t *T, double h, int napply, bool count,
                                             double (&P)[3], unsigned &npairs) {
-  if (GROUP) kick_group<UNI>(a, o, N, X, T, h, napply, count, P, npairs);
-  else kick_wave<UNI>(a, o, N, X, T, h, napply, count, P, npairs);
+  if (GROUP) kick_group<UNI, IPL>(a, o, N, X, T, h, napply, count, P, npairs);
+  else kick_wave<UNI, IPL>(a, o, N, X, T, h, napply, count, P, npairs);
 }
 
-template <bool GROUP, bool UNI>
+template <bool GROUP, bool UNI, int IPL>
 __device__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red);
 
-template <bool GROUP>
+template <bool GROUP, int IPL>
 __device__ void run_system(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red) {
   const int64_t o = a.offs[s];
   const int N = (int)(a.offs[s + 1] - o);
@@ -291,11 +347,11 @@ __device__ void run_system(const BatchArgs &a, int s, double4 *X, uint32_t *T, d
     T[i] = hiword(th.w);
   }
   tile_sync<GROUP>();
-  if (tile_equal_mass<GROUP>(X, N, red)) run_steps<GROUP, true>(a, s, X, T, red);
-  else run_steps<GROUP, false>(a, s, X, T, red);
+  if (tile_equal_mass<GROUP>(X, N, red)) run_steps<GROUP, true, IPL>(a, s, X, T, red);
+  else run_steps<GROUP, false, IPL>(a, s, X, T, red);
 }
 
-template <bool GROUP, bool UNI>
+template <bool GROUP, bool UNI, int IPL>
 __device__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red) {
   const int64_t o = a.offs[s];
   const int N = (int)(a.offs[s + 1] - o);
@@ -305,7 +361,7 @@ __device__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, do
   const double mu = a.G * a.m0;
   double P[3];
   unsigned npairs = 0;
-  kick_system<GROUP, UNI>(a, o, N, X, T, h, 1, a.nsteps == 0 && a.npairs, P, npairs);
+  kick_system<GROUP, UNI, IPL>(a, o, N, X, T, h, 1, a.nsteps == 0 && a.npairs, P, npairs);
   for (int step = 1; step <= a.nsteps; ++step) {
     tile_sum3<GROUP>(P, red);
     const double s1x = h * (P[0] / a.m0), s1y = h * (P[1] / a.m0), s1z = h * (P[2] / a.m0);
@@ -328,7 +384,7 @@ __device__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, do
     }
     tile_sync<GROUP>();
     const bool last = step == a.nsteps;
-    kick_system<GROUP, UNI>(a, o, N, X, T, h, last ? 1 : 2, last && a.npairs, P, npairs);
+    kick_system<GROUP, UNI, IPL>(a, o, N, X, T, h, last ? 1 : 2, last && a.npairs, P, npairs);
   }
   for (int i = t; i < N; i += nt) a.xm[o + i] = X[i];
   if (a.npairs) {
@@ -362,15 +418,20 @@ __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (idx >= a.nsys) return;
     const int s = a.order[idx];
     const int N = (int)(a.offs[s + 1] - a.offs[s]);
-    if (a.cfg[size_class(N)] == 1 && N <= kMaxWaveN) break;
-    run_system<true>(a, s, X, T, red);
+    const int cfg = a.cfg[size_class(N)];
+    if ((cfg & kTileWave) && N <= kMaxWaveN) break;
+    if (cfg & kTileIpl2) run_system<true, 2>(a, s, X, T, red);
+    else run_system<true, 1>(a, s, X, T, red);
   }
   // wave phase: wave 0 runs the system just taken, the other waves take their own
   double4 *WX = X + w * kMaxWaveN;
   uint32_t *WT = T + w * kMaxWaveN;
   int my = w == 0 ? idx : pop_wave(a.queue);
   while (my < a.nsys) {
-    run_system<false>(a, a.order[my], WX, WT, nullptr);
+    const int s = a.order[my];
+    const int N = (int)(a.offs[s + 1] - a.offs[s]);
+    if (a.cfg[size_class(N)] & kTileIpl2) run_system<false, 2>(a, s, WX, WT, nullptr);
+    else run_system<false, 1>(a, s, WX, WT, nullptr);
     my = pop_wave(a.queue);
   }
 }

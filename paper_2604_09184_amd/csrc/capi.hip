@@ -280,7 +280,7 @@ int run_batched(nbody_ctx *c, int32_t nsys, const int32_t *tiles, double4 *xm, d
   int32_t *d_order = (int32_t *)ensure(c, B_B_ORDER, (size_t)nsys * sizeof(int32_t));
   int32_t *d_cfg = (int32_t *)ensure(c, B_B_CFG, kBuckets * sizeof(int32_t));
   double4 *d_thr = (double4 *)ensure(c, B_B_THR, (size_t)total * sizeof(double4));
-  double4 *d_part = (double4 *)ensure(c, B_B_PART, (size_t)b.grid * 2 * kBatchedWaves * 64 * sizeof(double4));
+  double4 *d_part = (double4 *)ensure(c, B_B_PART, (size_t)b.grid * 2 * kBatchedWaves * 2 * 64 * sizeof(double4));
   unsigned *d_q = (unsigned *)ensure(c, B_B_QUEUE, 256);
   if (!d_offs || !d_order || !d_cfg || !d_thr || !d_part || !d_q)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (batched)");
@@ -1101,33 +1101,48 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
   int32_t trial[kBuckets];
   std::copy(c->tiles, c->tiles + kBuckets, trial);
   // one sweep of coordinate descent, largest class first: the whole ensemble (on scratch copies)
-  // is timed with each admissible tile of one class while the other classes keep theirs, so the
-  // measure includes how the classes fill each other's gaps in the queue
+  // is timed with each admissible tile code of one class (one workgroup or one wave per system,
+  // one or two bodies per lane) while the other classes keep theirs, so the measure includes how
+  // the classes fill each other's gaps in the queue
+  auto time_run = [&](double *ms_out) -> int {
+    hipError_t e = hipMemcpyAsync(txm, xm, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(tv, v, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune copy");
+    TRY(run_batched(c, nsys, trial, txm, tv, nsteps, nullptr, st));
+    float ms = 0.f;
+    e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune timing");
+    *ms_out = ms;
+    return NBODY_OK;
+  };
   for (int b = kBuckets - 1; b >= 0 && rc == NBODY_OK; --b) {
-    if (nmax[b] == 0 || nmax[b] > batched_max_wave_n()) continue;
+    if (nmax[b] == 0) continue;
     const int incumbent = trial[b];
-    const int other = 1 - incumbent;
-    // a warm-up run, then incumbent, other, other, incumbent: the clock drifts upward during the
-    // first runs, and this order cancels a linear drift
-    const int seq[5] = {incumbent, incumbent, other, other, incumbent};
-    double t_code[2] = {0.0, 0.0};
-    for (int r = 0; r < 5 && rc == NBODY_OK; ++r) {
-      trial[b] = seq[r];
-      hipError_t e = hipMemcpyAsync(txm, xm, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
-      if (e == hipSuccess) e = hipMemcpyAsync(tv, v, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
-      if (e == hipSuccess) e = hipEventRecord(e0, st);
-      if (e != hipSuccess) { rc = hip_fail(c, e, "autotune copy"); break; }
-      rc = run_batched(c, nsys, trial, txm, tv, nsteps, nullptr, st);
-      if (rc != NBODY_OK) break;
-      float ms = 0.f;
-      e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) { rc = hip_fail(c, e, "autotune timing"); break; }
-      if (r > 0) t_code[seq[r]] += ms;
+    int cand[kTileCodes], nc = 0;
+    cand[nc++] = incumbent;
+    for (int code = 0; code < kTileCodes; ++code)
+      if (code != incumbent && (!(code & kTileWave) || nmax[b] <= batched_max_wave_n())) cand[nc++] = code;
+    if (nc == 1) continue;
+    // a warm-up run, then the candidates in order and in reverse order: the clock drifts during
+    // the first runs, and the symmetric order cancels a linear drift
+    double t_code[kTileCodes] = {0.0, 0.0, 0.0, 0.0}, ms = 0.0;
+    trial[b] = incumbent;
+    rc = time_run(&ms);
+    for (int r = 0; r < 2 * nc && rc == NBODY_OK; ++r) {
+      const int code = cand[r < nc ? r : 2 * nc - 1 - r];
+      trial[b] = code;
+      rc = time_run(&ms);
+      t_code[code] += ms;
     }
-    // the other tile must win by more than the run-to-run spread to replace the incumbent
-    trial[b] = t_code[other] < 0.97 * t_code[incumbent] ? other : incumbent;
+    if (rc != NBODY_OK) break;
+    // another code must win by more than the run-to-run spread to replace the incumbent
+    int best = incumbent;
+    for (int q = 1; q < nc; ++q)
+      if (t_code[cand[q]] < 0.97 * t_code[best]) best = cand[q];
+    trial[b] = best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1158,7 +1173,8 @@ int nbody_get_batched_tiles(const nbody_ctx *c, int32_t *tiles, int32_t n) {
 int nbody_set_batched_tiles(nbody_ctx *c, const int32_t *tiles, int32_t n) {
   if (!c || !tiles || n != kBuckets) return NBODY_E_INVAL;
   for (int b = 0; b < kBuckets; ++b)
-    if (tiles[b] < 0 || tiles[b] > 1) return fail(c, NBODY_E_INVAL, "tile code %d out of range (0 or 1)", tiles[b]);
+    if (tiles[b] < 0 || tiles[b] >= kTileCodes)
+      return fail(c, NBODY_E_INVAL, "tile code %d out of range (0 .. %d)", tiles[b], kTileCodes - 1);
   for (int b = 0; b < kBuckets; ++b) c->tiles[b] = tiles[b];
   return NBODY_OK;
 }

@@ -125,13 +125,16 @@ hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count
 // batched.hip
 constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048
 constexpr int kBatchedWaves = 8;   // waves per workgroup of the batched kernel
+// Tile code of a size class: bit 0 set = one wave per system (systems of at most 256 bodies),
+// clear = one workgroup per system; bit 1 set = two bodies per lane in the kick, clear = one.
+constexpr int kTileWave = 1, kTileIpl2 = 2, kTileCodes = 4;
 struct BatchLaunch {
   const int64_t *offs;
   const int32_t *order;
-  const int32_t *cfg;   // [kBuckets] 1 = one wave per system, 0 = one workgroup per system
+  const int32_t *cfg;   // [kBuckets] tile codes
   int nsys, nsteps, grid;
   double4 *xm, *v, *thr;
-  double4 *part;        // [grid][2 * kBatchedWaves][64]
+  double4 *part;        // [grid][2 * kBatchedWaves][2][64]
   unsigned long long *npairs;
   unsigned *queue;
   double G, m0, dt, f_in, cH, cV, n1, n2dt;

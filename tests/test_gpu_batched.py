@@ -55,7 +55,7 @@ def rel_state_err(a, b):
 
 
 @pytest.mark.parametrize("masses", ["equal", "mixed"])
-@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_batched_matches_single_system_runs(nb, tile, masses):
     say(f"batched tile={tile} masses={masses} sizes={SIZES}")
     p = diskgen.PARAMS
@@ -108,7 +108,10 @@ def test_autotune_and_rejections(nb):
     X, V = to_dev(x, v, m)
     X0, V0 = X.clone(), V.clone()
     tiles = ctx.autotune_batched(offs, X, V, nsteps=2)
-    assert len(tiles) == 6 and all(t in (0, 1) for t in tiles)
+    # codes 0 .. 3: bit 0 one wave per system (systems of at most 256 bodies), bit 1 two bodies
+    # per lane; the class of the 1500-body systems cannot take the wave tile
+    assert len(tiles) == 6 and all(t in (0, 1, 2, 3) for t in tiles)
+    assert tiles[5] in (0, 2)
     assert torch.equal(X, X0) and torch.equal(V, V0)          # tuning works on copies
     ctx.step_batched(offs, X, V, 3)
     ref = nb.Context(nb.Params(**diskgen.PARAMS))
@@ -122,7 +125,9 @@ def test_autotune_and_rejections(nb):
     with pytest.raises(nb.NBodyError):
         ctx.step_batched(np.array([1, 5]), X, V, 1)
     with pytest.raises(nb.NBodyError):
-        ctx.set_batched_tiles([2] * 6)
+        ctx.set_batched_tiles([4] * 6)
+    with pytest.raises(nb.NBodyError):
+        ctx.set_batched_tiles([-1] * 6)
 
 
 def test_full_ensemble_in_bench_configuration(nb):
