@@ -335,11 +335,10 @@ int nbody_step_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, double
  * is a bit set: bit 0 set = one wave per system (applies to systems of at most 256 bodies; larger
  * ones run as if it were clear), clear = one workgroup (eight waves) per system; bit 1 set = each
  * lane of the kick owns two bodies (one j-body read serves two pairs), clear = one. Codes 0 .. 3.
- * One sweep over the classes present, largest first: the whole ensemble is timed for nsteps steps
- * (on scratch copies; xm and v are not modified) with each admissible code for that class, in
- * order and then in reverse order, the other classes keeping theirs; another code replaces the
- * current one only if it is more than 3 % faster. Use nsteps of 10 or more: very short runs
- * favour the wave tile. get/set read or replace the table (host array of 6 codes); get returns the
+ * Every class present is timed on its own systems (the others skipped) for nsteps steps (on
+ * scratch copies; xm and v are not modified) with each admissible code, in order and then in
+ * reverse order; another code replaces the current one only if it is more than 2 % faster. Use
+ * nsteps of 10 or more: very short runs favour the wave tile. get/set read or replace the table (host array of 6 codes); get returns the
  * number of classes.
  */
 int nbody_autotune_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, const double *xm,

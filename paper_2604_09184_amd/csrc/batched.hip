@@ -331,10 +331,10 @@ __device__ __forceinline__ void kick_system(const BatchArgs &a, int64_t o, int N
 }
 
 template <bool GROUP, bool UNI, int IPL>
-__device__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red);
+__device__ __forceinline__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red);
 
 template <bool GROUP, int IPL>
-__device__ void run_system(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red) {
+__device__ __forceinline__ void run_system(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red) {
   const int64_t o = a.offs[s];
   const int N = (int)(a.offs[s + 1] - o);
   const int t = GROUP ? (int)threadIdx.x : (int)(threadIdx.x & 63);
@@ -352,7 +352,7 @@ __device__ void run_system(const BatchArgs &a, int s, double4 *X, uint32_t *T, d
 }
 
 template <bool GROUP, bool UNI, int IPL>
-__device__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red) {
+__device__ __forceinline__ void run_steps(const BatchArgs &a, int s, double4 *X, uint32_t *T, double *red) {
   const int64_t o = a.offs[s];
   const int N = (int)(a.offs[s + 1] - o);
   const int t = GROUP ? (int)threadIdx.x : (int)(threadIdx.x & 63);

@@ -269,8 +269,9 @@ int grid_size(nbody_ctx *c, int *grid) {
 
 // Launches the persistent kernel over the systems laid out by host offsets h_offs with the tile
 // table `tiles` (host, kBuckets codes).
+// only_class >= 0: run only the systems of that size class (the others are left untouched).
 int run_batched(nbody_ctx *c, int32_t nsys, const int32_t *tiles, double4 *xm, double4 *v, int32_t nsteps,
-                unsigned long long *npairs, hipStream_t st) {
+                unsigned long long *npairs, hipStream_t st, int only_class = -1) {
   std::vector<int64_t> &h_offs = c->h_offs;
   std::vector<int32_t> &h_order = c->h_order;
   const int64_t total = h_offs[nsys];
@@ -284,15 +285,18 @@ int run_batched(nbody_ctx *c, int32_t nsys, const int32_t *tiles, double4 *xm, d
   unsigned *d_q = (unsigned *)ensure(c, B_B_QUEUE, 256);
   if (!d_offs || !d_order || !d_cfg || !d_thr || !d_part || !d_q)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (batched)");
-  h_order.resize(nsys);
-  std::iota(h_order.begin(), h_order.end(), 0);
+  h_order.clear();
+  for (int32_t s = 0; s < nsys; ++s)
+    if (only_class < 0 || size_class_host(h_offs[s + 1] - h_offs[s]) == only_class) h_order.push_back(s);
   std::stable_sort(h_order.begin(), h_order.end(), [&](int32_t a, int32_t b) {
     return h_offs[a + 1] - h_offs[a] > h_offs[b + 1] - h_offs[b];
   });
+  const int32_t nrun = (int32_t)h_order.size();
   HIPCHK(c, hipMemcpyAsync(d_offs, h_offs.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
-  HIPCHK(c, hipMemcpyAsync(d_order, h_order.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+  if (nrun > 0)
+    HIPCHK(c, hipMemcpyAsync(d_order, h_order.data(), nrun * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
   HIPCHK(c, hipMemcpyAsync(d_cfg, tiles, kBuckets * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
-  b.offs = d_offs; b.order = d_order; b.cfg = d_cfg; b.nsys = nsys; b.nsteps = nsteps;
+  b.offs = d_offs; b.order = d_order; b.cfg = d_cfg; b.nsys = nrun; b.nsteps = nsteps;
   b.xm = xm; b.v = v; b.thr = d_thr; b.part = d_part; b.npairs = npairs; b.queue = d_q;
   const nbody_params &p = c->p;
   b.G = p.G; b.m0 = p.m0; b.dt = p.dt; b.f_in = p.f_in;
@@ -1100,16 +1104,15 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
   int rc = NBODY_OK;
   int32_t trial[kBuckets];
   std::copy(c->tiles, c->tiles + kBuckets, trial);
-  // one sweep of coordinate descent, largest class first: the whole ensemble (on scratch copies)
-  // is timed with each admissible tile code of one class (one workgroup or one wave per system,
-  // one or two bodies per lane) while the other classes keep theirs, so the measure includes how
-  // the classes fill each other's gaps in the queue
+  // every class present is timed on its own systems (the others skipped; on scratch copies) with
+  // each admissible tile code: one workgroup or one wave per system, one or two bodies per lane
+  int only = -1;
   auto time_run = [&](double *ms_out) -> int {
     hipError_t e = hipMemcpyAsync(txm, xm, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(tv, v, (size_t)tot * sizeof(double4), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(e0, st);
     if (e != hipSuccess) return hip_fail(c, e, "autotune copy");
-    TRY(run_batched(c, nsys, trial, txm, tv, nsteps, nullptr, st));
+    TRY(run_batched(c, nsys, trial, txm, tv, nsteps, nullptr, st, only));
     float ms = 0.f;
     e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1126,6 +1129,7 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
     for (int code = 0; code < kTileCodes; ++code)
       if (code != incumbent && (!(code & kTileWave) || nmax[b] <= batched_max_wave_n())) cand[nc++] = code;
     if (nc == 1) continue;
+    only = b;
     // a warm-up run, then the candidates in order and in reverse order: the clock drifts during
     // the first runs, and the symmetric order cancels a linear drift
     double t_code[kTileCodes] = {0.0, 0.0, 0.0, 0.0}, ms = 0.0;
@@ -1138,10 +1142,10 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
       t_code[code] += ms;
     }
     if (rc != NBODY_OK) break;
-    // another code must win by more than the run-to-run spread to replace the incumbent
+    // another code must win by more than the run-to-run spread (2 %) to replace the incumbent
     int best = incumbent;
     for (int q = 1; q < nc; ++q)
-      if (t_code[cand[q]] < 0.97 * t_code[best]) best = cand[q];
+      if (t_code[cand[q]] < 0.98 * t_code[best]) best = cand[q];
     trial[b] = best;
   }
   (void)hipEventDestroy(e0);
