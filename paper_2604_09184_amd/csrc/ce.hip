@@ -173,7 +173,9 @@ struct CePartner {
   int src, q;
   bool use;
   CeMember m;
-  double rcij, isp;   // the pair's critical radius max(rc_i, rc_j) and 1/((1 - f_in) rc_ij)
+  // the pair's critical radius max(rc_i, rc_j) and 1/((1 - f_in) rc_ij) of the step's level, and
+  // of the first intermediate level when there is one
+  double rcij, isp, rcij1, isp1;
 };
 
 __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const CeShared &sh) {
@@ -187,6 +189,14 @@ __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const Ce
   const bool mine = L.rc > p.m.rc;
   p.rcij = mine ? L.rc : p.m.rc;
   p.isp = mine ? L.ispan : p.m.ispan;
+  p.rcij1 = p.rcij;
+  p.isp1 = p.isp;
+  if (L.nl >= 2) {
+    const double ri = sh.lrc[1][L.rank], rj = sh.lrc[1][qq];
+    const bool mine1 = ri > rj;
+    p.rcij1 = mine1 ? ri : rj;
+    p.isp1 = mine1 ? sh.lisp[1][L.rank] : sh.lisp[1][qq];
+  }
   return p;
 }
 
@@ -197,7 +207,7 @@ __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const Ce
 //
 // With intermediate changeover levels the pair potential is weighted by W = prod_l [1 - K_l] (one
 // factor per level, each with its own rc_l), and the coefficient is G m_j (W/r^3 - W'(r)/r^2).
-template <bool NL1>
+template <int NL>
 __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p, const CeLane &L,
                                         const CeShared &sh, double &a0, double &a1, double &a2) {
   // a term that does not count (no member, or the lane's own body) is moved 1e30 away: there the
@@ -213,12 +223,27 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
   const double r = r2 * ir;
   const double f_in = L.f_in;
   double c;
-  if (NL1) {
+  if (NL == 1) {
     const double rcij = p.rcij, isp = p.isp;
     const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
     const double omy = 1.0 - y;
     const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
     c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
+  } else if (NL == 2) {
+    // W = [1 - K_0][1 - K_1], the two levels' constants kept with the partner
+    double W = 1.0, dW = 0.0;
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const double rcij = l == 0 ? p.rcij : p.rcij1;
+      const double isp = l == 0 ? p.isp : p.isp1;
+      const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
+      const double omy = 1.0 - y;
+      const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
+      const double omK = omy * omy * iD, dK = 2.0 * y * omy * iD * iD * isp;
+      dW = dW * omK - W * dK;
+      W = W * omK;
+    }
+    c = ir * ir * (W * ir - dW);
   } else {
     double W = 1.0, dW = 0.0;
     for (int l = 0; l < L.nl; ++l) {
@@ -254,7 +279,7 @@ constexpr int kCeRegPartners = 4;
 
 // f = (v, a) of this lane's body at the state z. PT > 0: P = PT replicas and one partner per
 // replica (groups of up to 8 bodies), known at compile time; PT = 0: P and the partner count from L.
-template <bool NL1, int PT>
+template <int NL, int PT>
 __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, const CeShared &sh,
                                        const CePartner (&pr)[kCeRegPartners], bool alive,
                                        double (&f)[6]) {
@@ -266,16 +291,16 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
   const double s = -L.Gm0 * (ir * ir * ir);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (PT > 0 || L.iters == 1) {
-    ce_pair<NL1>(z, pr[0], L, sh, a0, a1, a2);
+    ce_pair<NL>(z, pr[0], L, sh, a0, a1, a2);
   } else {
     // independent terms side by side (masked beyond the members)
 #pragma unroll
-    for (int u = 0; u < kCeRegPartners; ++u) ce_pair<NL1>(z, pr[u], L, sh, a0, a1, a2);
+    for (int u = 0; u < kCeRegPartners; ++u) ce_pair<NL>(z, pr[u], L, sh, a0, a1, a2);
     for (int it = kCeRegPartners; it < L.iters; it += kCeRegPartners) {
 #pragma unroll
       for (int u = 0; u < kCeRegPartners; ++u) {
         const CePartner p = ce_partner(L.rep + (it + u) * P, L, sh);
-        ce_pair<NL1>(z, p, L, sh, a0, a1, a2);
+        ce_pair<NL>(z, p, L, sh, a0, a1, a2);
       }
     }
   }
@@ -293,13 +318,13 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
 }
 
 // Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
-template <bool NL1, int PT>
+template <int NL, int PT>
 __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, const CeLane &L,
                                          const CeShared &sh, const CePartner (&pr)[kCeRegPartners],
                                          bool alive, double (&est)[6]) {
   const double hs = H / ns;
   double zm[6], zc[6], f[6];
-  ce_rhs<NL1, PT>(y, L, sh, pr, alive, f);
+  ce_rhs<NL, PT>(y, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
@@ -309,18 +334,18 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
   // arrays trade roles without copies (ns is even: one step is left over at the end)
   const double h2 = 2.0 * hs;
   for (int s = 1; s + 1 < ns; s += 2) {
-    ce_rhs<NL1, PT>(zc, L, sh, pr, alive, f);
+    ce_rhs<NL, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) zm[i] = zm[i] + h2 * f[i];
-    ce_rhs<NL1, PT>(zm, L, sh, pr, alive, f);
+    ce_rhs<NL, PT>(zm, L, sh, pr, alive, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) zc[i] = zc[i] + h2 * f[i];
   }
-  ce_rhs<NL1, PT>(zc, L, sh, pr, alive, f);
+  ce_rhs<NL, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) zm[i] = zm[i] + h2 * f[i];
   // now zm = z_ns and zc = z_{ns-1}
-  ce_rhs<NL1, PT>(zm, L, sh, pr, alive, f);
+  ce_rhs<NL, PT>(zm, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zm[i] + zc[i] + hs * f[i]);
 }
@@ -350,7 +375,7 @@ __device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale
 
 // One macro-step attempt over H from y (all four waves together): returns the accepted column
 // (identical in every wave) or -1; y1 receives the accepted extrapolant.
-template <bool NL1, int PT>
+template <int NL, int PT>
 __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool alive, const CeLane &L,
                                           CeShared &sh, const CePartner (&pr)[kCeRegPartners],
                                           int &buf, double (&y1)[6]) {
@@ -362,7 +387,7 @@ __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool a
   for (int cc = 0; cc < 2; ++cc) {
     const int c = cc == 0 ? L.wv : 7 - L.wv;
     double est[6];
-    ce_sweep<NL1, PT>(y, H, 2 * c + 2, L, sh, pr, alive, est);
+    ce_sweep<NL, PT>(y, H, 2 * c + 2, L, sh, pr, alive, est);
     if (L.rep == 0)
 #pragma unroll
       for (int i = 0; i < 6; ++i) sh.est[buf][c][i][L.slot] = est[i];
@@ -427,7 +452,7 @@ __device__ __forceinline__ int ce_contact(const double (&y)[6], double fR, const
 // followed by a contact test and the integration stops at the first step that ends in contact: y
 // then holds that step's start, done the time covered before it and Hc its length. Returns 0
 // (covered), 1 (contact) or 2 (H halved 60 times in a row, or too many macro steps).
-template <bool NL1, bool COL, int PT>
+template <int NL, bool COL, int PT>
 __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool check, bool alive,
                                           double fR, const CeLane &L, CeShared &sh,
                                           const CePartner (&pr)[kCeRegPartners], int &buf,
@@ -438,7 +463,7 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
     if (++macro > kMaxMacroSteps) return 2;
     if (fabs(H) > fabs(Ltot - t)) H = Ltot - t;
     double y1[6];
-    const int c = ce_attempt<NL1, PT>(y, H, COL ? alive : true, L, sh, pr, buf, y1);
+    const int c = ce_attempt<NL, PT>(y, H, COL ? alive : true, L, sh, pr, buf, y1);
     if (c < 0) {
       H = H / 2.0;
       if (++halvings > 60) return 2;
@@ -473,7 +498,7 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
 // becomes massless, of zero radius, parked on a circular orbit of radius kParkRadius about the
 // central mass at the angle 2 pi j/n, and is held fixed for the rest of the drift. Each merger is
 // logged as {step, survivor, removed} with its time within the drift.
-template <bool NL1, bool COL>
+template <int NL, bool COL>
 __device__ __forceinline__ void ce_group(
     int w, CeShared &sh, double4 *__restrict__ xm, double4 *__restrict__ v,
     const double4 *__restrict__ thr, const int *__restrict__ gmem, const int *__restrict__ gstart,
@@ -556,13 +581,13 @@ __device__ __forceinline__ void ce_group(
     const bool chk = collide && phase == 0;
     int st;
     if (L.iters == 1 && L.P == 2)
-      st = ce_advance<NL1, COL, 2>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
+      st = ce_advance<NL, COL, 2>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
     else if (L.iters == 1 && L.P == 4)
-      st = ce_advance<NL1, COL, 4>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
+      st = ce_advance<NL, COL, 4>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
     else if (L.iters == 1 && L.P == 8)
-      st = ce_advance<NL1, COL, 8>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
+      st = ce_advance<NL, COL, 8>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
     else
-      st = ce_advance<NL1, COL, 0>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
+      st = ce_advance<NL, COL, 0>(y, L_int, chk, alive, fR, L, sh, pr, buf, done, Hc);
     if (st == 2) { status = 1; break; }
     if (phase == 0) {
       if (st == 0) break;
@@ -654,7 +679,7 @@ __device__ __forceinline__ void ce_group(
 }
 
 // Resident workgroups take groups from a queue (counter[2]) until all counter[0] groups are done.
-template <bool NL1, bool COL>
+template <int NL, bool COL>
 __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
     const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
@@ -669,7 +694,7 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     const int w = next;
     __syncthreads();
     if (w >= ng) break;
-    ce_group<NL1, COL>(w, sh, xm, v, thr, gmem, gstart, gsize, groot, G, m0, f_in, h, tol, stats, col, lt);
+    ce_group<NL, COL>(w, sh, xm, v, thr, gmem, gstart, gsize, groot, G, m0, f_in, h, tol, stats, col, lt);
     __syncthreads();
   }
 }
@@ -705,7 +730,7 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
                            hipStream_t st) {
   // resident workgroups only: the queue hands out the groups (the device count is not known here)
   if (max_groups <= 0) return hipSuccess;
-  const bool nl1 = lt.nl == 1, col_on = col.radius != nullptr;
+  const bool col_on = col.radius != nullptr;
 #define NBK_CE(A, B)                                                                                \
   do {                                                                                              \
     static int resident = 0;                                                                        \
@@ -723,8 +748,9 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
                        0, st, xm, v, thr, gmem, gstart, gsize, groot, counter, G, m0, f_in, h, tol,  \
                        stats, col, lt);                                                             \
   } while (0)
-  if (nl1) { if (col_on) NBK_CE(true, true); else NBK_CE(true, false); }
-  else { if (col_on) NBK_CE(false, true); else NBK_CE(false, false); }
+  if (lt.nl == 1) { if (col_on) NBK_CE(1, true); else NBK_CE(1, false); }
+  else if (lt.nl == 2) { if (col_on) NBK_CE(2, true); else NBK_CE(2, false); }
+  else { if (col_on) NBK_CE(0, true); else NBK_CE(0, false); }
 #undef NBK_CE
   return hipGetLastError();
 }
