@@ -35,8 +35,8 @@ struct Buf {
 enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
-             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GMARK, B_GIN, B_GSIZE,
-             B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_HGOUT, B_LTHR, B_ADEG, B_AOFF,
+             B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GIN, B_GSIZE,
+             B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_LTHR, B_ADEG, B_AOFF,
              B_AFILL, B_ADJ, B_LSKIP, B_AOWN, B_ATERM, B_ATOT, B_ETHR, B_NUM };
 
 }  // namespace
@@ -314,12 +314,11 @@ int run_batched(nbody_ctx *c, int32_t nsys, const int32_t *tiles, double4 *xm, d
 constexpr double kCeTol = 1e-14;   // Bulirsch-Stoer tolerance, relative to the group's scales
 
 struct GroupBufs {
-  int *mark, *in, *gsize, *gstart, *gfill, *gmem, *groot, *counter;
+  int *in, *gsize, *gstart, *gfill, *gmem, *groot, *counter;
 };
 
 int group_bufs(nbody_ctx *c, int n, GroupBufs &g) {
   const size_t b = (size_t)n * sizeof(int);
-  g.mark = (int *)ensure(c, B_GMARK, b);
   g.in = (int *)ensure(c, B_GIN, b);
   g.gsize = (int *)ensure(c, B_GSIZE, b);
   g.gstart = (int *)ensure(c, B_GSTART, b);
@@ -327,7 +326,7 @@ int group_bufs(nbody_ctx *c, int n, GroupBufs &g) {
   g.gmem = (int *)ensure(c, B_GMEM, b);
   g.groot = (int *)ensure(c, B_GROOT, b);
   g.counter = (int *)ensure(c, B_GCNT, kGroupCounters * sizeof(int));
-  if (!g.mark || !g.in || !g.gsize || !g.gstart || !g.gfill || !g.gmem || !g.groot || !g.counter)
+  if (!g.in || !g.gsize || !g.gstart || !g.gfill || !g.gmem || !g.groot || !g.counter)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
   return NBODY_OK;
 }
@@ -357,8 +356,8 @@ int collide_args(nbody_ctx *c, int n, const nbody_collisions *col, CeCollide &cc
 // over h (the other bodies are not touched here).
 int ce_drift(nbody_ctx *c, int n, double4 *xm, double4 *v, const double4 *thr, const int *labels,
              const GroupBufs &g, double h, unsigned long long *stats, const CeCollide &col, hipStream_t st) {
-  HIPCHK(c, launch_group_lists(labels, n, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
-                               g.counter, st), "group lists");
+  HIPCHK(c, launch_group_lists(labels, n, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
+                               false, st), "group lists");
   const nbody_params &p = c->p;
   LevelThr lt{};
   lt.thr[0] = thr;
@@ -660,12 +659,12 @@ int nbody_encounter_groups(nbody_ctx *c, int64_t n, const int32_t *pairs, int64_
   TRY(check_dev(c, count, "count", true));
   TRY(check_dev(c, labels, "labels", true));
   TRY(check_dev(c, out, "out", true));
-  int *mark = (int *)ensure(c, B_GMARK, (size_t)n * sizeof(int));
-  if (!mark) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
+  int *gsize = (int *)ensure(c, B_GSIZE, (size_t)n * sizeof(int));
+  if (!gsize) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
   const int64_t want = (cap + kBlock - 1) / kBlock;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
-  HIPCHK(c, launch_groups(pairs, cap, count, (int)n, labels, mark, out, blocks, (hipStream_t)stream),
-         "groups");
+  HIPCHK(c, launch_groups(pairs, cap, count, (int)n, labels, gsize, nullptr, nullptr, out, blocks,
+                          (hipStream_t)stream), "groups");
   return NBODY_OK;
 }
 
@@ -728,8 +727,7 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   int32_t *lpairs = (int32_t *)ensure(c, B_HPAIRS, (size_t)cap * 2 * sizeof(int32_t));
   int64_t *lcount = (int64_t *)ensure(c, B_HCOUNT, sizeof(int64_t));
   int32_t *labels = (int32_t *)ensure(c, B_HLAB, (size_t)n * sizeof(int32_t));
-  int64_t *gout = (int64_t *)ensure(c, B_HGOUT, 2 * sizeof(int64_t));
-  if (!momA || !momB || !lpairs || !lcount || !labels || !gout)
+  if (!momA || !momB || !lpairs || !lcount || !labels)
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (hybrid step)");
   GroupBufs g;
   TRY(group_bufs(c, N, g));
@@ -786,7 +784,8 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     TRY(emit_list(c, a, lpairs, cap, lcount, st));
     HIPCHK(c, launch_list_overflow(lcount, cap, S, st), "list check");
     if (L == 0)
-      HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.mark, gout, ublocks, st), "groups");
+      HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.gsize, g.gfill, g.counter, nullptr, ublocks,
+                              st), "groups");
     else
       HIPCHK(c, launch_adjacency(lpairs, cap, lcount, N, la, st), "adjacency");
     return NBODY_OK;
@@ -797,10 +796,10 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   // orbits; above it, sub substeps of kick / drift_{l+1} / kick
   std::function<int(int, double)> drift_levels = [&](int l, double tau) -> int {
     if (l == L) {
-      HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.mark, gout, ublocks, st, X, lt.thr[L]),
-             "level groups");
-      HIPCHK(c, launch_group_lists(labels, N, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
-                                   g.counter, st), "group lists");
+      HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.gsize, g.gfill, g.counter, nullptr, ublocks,
+                              st, X, lt.thr[L]), "level groups");
+      HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
+                                   true, st), "group lists");
       cc.step = step;
       HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
                                 p.f_in, tau, kCeTol, S, cc, lt, st), "close-encounter drift");
@@ -826,8 +825,8 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   for (int s = 1; s <= nsteps; ++s) {
     step = s - 1;
     if (L == 0) {
-      HIPCHK(c, launch_group_lists(labels, N, g.mark, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot,
-                                   g.counter, st), "group lists");
+      HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
+                                   true, st), "group lists");
       // first jump for all; Kepler drift for the bodies in no group
       HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
                                   g.in), "jump+drift");

@@ -26,57 +26,50 @@ namespace nbk {
 using namespace nbd;
 
 // ------------------------------------------------------------------ group member lists
-// in[i] = 1 for a body that shares its group with another body; gsize[root] counts them.
-__global__ __launch_bounds__(kBlock) void k_gmark(const int *__restrict__ label, int n,
-                                                  int *__restrict__ mark, int *__restrict__ gsize,
+// Group sizes from caller-given labels (every body labelled with the smallest index of its group).
+__global__ __launch_bounds__(kBlock) void k_gzero(int n, int *__restrict__ gsize,
                                                   int *__restrict__ gfill, int *__restrict__ counter) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) {
-    mark[i] = 0;
     gsize[i] = 0;
     gfill[i] = 0;
   }
   if (i < kGroupCounters) counter[i] = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_gmark2(const int *__restrict__ label, int n,
-                                                   int *__restrict__ mark) {
+__global__ __launch_bounds__(kBlock) void k_gcount(const int *__restrict__ label, int n,
+                                                   int *__restrict__ gsize) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n && label[i] != i) mark[label[i]] = 1;
+  if (i < n) atomicAdd(gsize + label[i], 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_gsize(const int *__restrict__ label,
-                                                  const int *__restrict__ mark, int n,
-                                                  int *__restrict__ in, int *__restrict__ gsize) {
+// in[i] = 1 for a body that shares its group with another body; slices of the member array by
+// atomic allocation (counter[1]) and the roots of the groups into a list (counter[0]): where a
+// group's slice sits does not matter, each group is integrated on its own with its members ordered
+// by body index.
+__global__ __launch_bounds__(kBlock) void k_galloc(const int *__restrict__ label,
+                                                   const int *__restrict__ gsize, int n,
+                                                   int *__restrict__ in, int *__restrict__ gstart,
+                                                   int *__restrict__ groot, int *__restrict__ counter) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const int r = label[i];
-  const int g = (r != i) || mark[i];
-  in[i] = g;
-  if (g) atomicAdd(gsize + r, 1);
-}
-
-// Slices of the member array by atomic allocation (counter[1]): where a group's slice sits does
-// not matter, each group is integrated on its own with its members ordered by body index.
-__global__ __launch_bounds__(kBlock) void k_galloc(const int *__restrict__ gsize, int n,
-                                                   int *__restrict__ gstart, int *__restrict__ counter) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n && gsize[i] > 0) gstart[i] = atomicAdd(counter + 1, gsize[i]);
+  in[i] = gsize[label[i]] >= 2;
+  if (label[i] == i && gsize[i] >= 2) {
+    gstart[i] = atomicAdd(counter + 1, gsize[i]);
+    groot[atomicAdd(counter, 1)] = i;
+  }
 }
 
 // Members into their group's slots (slot order is arbitrary; the integrator orders them by body
-// index) and the roots of the groups into a list.
+// index).
 __global__ __launch_bounds__(kBlock) void k_gfill(const int *__restrict__ label,
                                                   const int *__restrict__ in, int n,
                                                   const int *__restrict__ gstart,
-                                                  int *__restrict__ gfill, int *__restrict__ gmem,
-                                                  int *__restrict__ groot, int *__restrict__ counter) {
+                                                  int *__restrict__ gfill, int *__restrict__ gmem) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n || !in[i]) return;
   const int r = label[i];
-  const int slot = atomicAdd(gfill + r, 1);
-  gmem[gstart[r] + slot] = i;
-  if (r == i) groot[atomicAdd(counter, 1)] = i;
+  gmem[gstart[r] + atomicAdd(gfill + r, 1)] = i;
 }
 
 // ------------------------------------------------------------------ integrator
@@ -711,15 +704,17 @@ hipError_t launch_list_overflow(const int64_t *count, int64_t cap, unsigned long
   return hipGetLastError();
 }
 
-hipError_t launch_group_lists(const int *label, int n, int *mark, int *in, int *gsize, int *gstart,
-                              int *gfill, int *gmem, int *groot, int *counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_gmark, dim3(nblocks(n)), dim3(kBlock), 0, st, label, n, mark, gsize, gfill,
-                     counter);
-  hipLaunchKernelGGL(k_gmark2, dim3(nblocks(n)), dim3(kBlock), 0, st, label, n, mark);
-  hipLaunchKernelGGL(k_gsize, dim3(nblocks(n)), dim3(kBlock), 0, st, label, mark, n, in, gsize);
-  hipLaunchKernelGGL(k_galloc, dim3(nblocks(n)), dim3(kBlock), 0, st, gsize, n, gstart, counter);
+hipError_t launch_group_lists(const int *label, int n, int *in, int *gsize, int *gstart, int *gfill,
+                              int *gmem, int *groot, int *counter, bool counted, hipStream_t st) {
+  if (!counted) {
+    hipLaunchKernelGGL(k_gzero, dim3(nblocks(n > kGroupCounters ? n : kGroupCounters)), dim3(kBlock),
+                       0, st, n, gsize, gfill, counter);
+    hipLaunchKernelGGL(k_gcount, dim3(nblocks(n)), dim3(kBlock), 0, st, label, n, gsize);
+  }
+  hipLaunchKernelGGL(k_galloc, dim3(nblocks(n)), dim3(kBlock), 0, st, label, gsize, n, in, gstart,
+                     groot, counter);
   hipLaunchKernelGGL(k_gfill, dim3(nblocks(n)), dim3(kBlock), 0, st, label, in, n, gstart, gfill,
-                     gmem, groot, counter);
+                     gmem);
   return hipGetLastError();
 }
 

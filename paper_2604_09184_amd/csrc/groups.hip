@@ -32,15 +32,21 @@ __device__ __forceinline__ int find_root(int *p, int x) {
   return x;
 }
 
+// parent[i] = i; the group sizes and fill counters zeroed (when given), the outputs and the list
+// counters zeroed (when given).
 __global__ __launch_bounds__(kBlock) void k_groups_init(int *__restrict__ parent,
-                                                        int *__restrict__ mark, int n,
-                                                        unsigned long long *__restrict__ out) {
+                                                        int *__restrict__ gsize,
+                                                        int *__restrict__ gfill, int n,
+                                                        unsigned long long *__restrict__ out,
+                                                        int *__restrict__ counter) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) {
     parent[i] = i;
-    mark[i] = 0;
+    gsize[i] = 0;
+    if (gfill) gfill[i] = 0;
   }
-  if (i < 2) out[i] = 0;
+  if (out && i < 2) out[i] = 0;
+  if (counter && i < kGroupCounters) counter[i] = 0;
 }
 
 // With xm and thr given, a listed pair is an edge only while it is close under thr's exact
@@ -77,40 +83,40 @@ __global__ __launch_bounds__(kBlock) void k_groups_union(const int32_t *__restri
       rj = find_root(parent, old);
     }
   }
-  if (bad) atomicAdd(out + 1, bad);
+  if (bad && out) atomicAdd(out + 1, bad);
 }
 
-// Flatten every body onto its root; a root that some other body points at starts a group.
+// Flatten every body onto its root and count the bodies of every root (gsize[root] >= 2: a group).
 __global__ __launch_bounds__(kBlock) void k_groups_flatten(int *__restrict__ parent,
-                                                           int *__restrict__ mark, int n) {
+                                                           int *__restrict__ gsize, int n) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   int r = i;
   while (parent[r] != r) r = parent[r];
   parent[i] = r;
-  if (r != i) mark[r] = 1;
+  atomicAdd(gsize + r, 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_groups_count(const int *__restrict__ mark, int n,
+__global__ __launch_bounds__(kBlock) void k_groups_count(const int *__restrict__ gsize, int n,
                                                          unsigned long long *__restrict__ out) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  unsigned long long c = (i < n && mark[i]) ? 1ull : 0ull;
+  unsigned long long c = (i < n && gsize[i] >= 2) ? 1ull : 0ull;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
 hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
-                         int32_t *labels, int *mark, int64_t *out, int union_blocks,
-                         hipStream_t st, const double4 *xm, const double4 *thr) {
+                         int32_t *labels, int *gsize, int *gfill, int *counter, int64_t *out,
+                         int union_blocks, hipStream_t st, const double4 *xm, const double4 *thr) {
   unsigned long long *o = (unsigned long long *)out;
-  hipLaunchKernelGGL(k_groups_init, dim3(nblocks(n > 2 ? n : 2)), dim3(kBlock), 0, st, labels, mark,
-                     n, o);
+  hipLaunchKernelGGL(k_groups_init, dim3(nblocks(n > kGroupCounters ? n : kGroupCounters)),
+                     dim3(kBlock), 0, st, labels, gsize, gfill, n, o, counter);
   if (cap > 0)
     hipLaunchKernelGGL(k_groups_union, dim3(union_blocks), dim3(kBlock), 0, st, pairs, cap, count, n,
                        labels, o, xm, thr);
-  hipLaunchKernelGGL(k_groups_flatten, dim3(nblocks(n)), dim3(kBlock), 0, st, labels, mark, n);
-  hipLaunchKernelGGL(k_groups_count, dim3(nblocks(n)), dim3(kBlock), 0, st, mark, n, o);
+  hipLaunchKernelGGL(k_groups_flatten, dim3(nblocks(n)), dim3(kBlock), 0, st, labels, gsize, n);
+  if (o) hipLaunchKernelGGL(k_groups_count, dim3(nblocks(n)), dim3(kBlock), 0, st, gsize, n, o);
   return hipGetLastError();
 }
 

@@ -56,8 +56,11 @@ hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, ui
                         hipStream_t st, const int *skip = nullptr);
 
 // ce.hip
-hipError_t launch_group_lists(const int *label, int n, int *mark, int *in, int *gsize, int *gstart,
-                              int *gfill, int *gmem, int *groot, int *counter, hipStream_t st);
+// Member lists of the groups (gsize >= 2) of the labels: in[i], gstart/gmem slices, root list
+// groot and counter[0] = groups. counted: gsize, gfill and counter come from launch_groups;
+// otherwise they are computed from the labels here.
+hipError_t launch_group_lists(const int *label, int n, int *in, int *gsize, int *gstart, int *gfill,
+                              int *gmem, int *groot, int *counter, bool counted, hipStream_t st);
 hipError_t launch_list_overflow(const int64_t *count, int64_t cap, unsigned long long *stats,
                                 hipStream_t st);
 // Collisions inside the close-encounter drift: radius null = none. Mergers are appended to
@@ -83,7 +86,7 @@ struct LevelThr {
 };
 
 // counter [kGroupCounters]: [0] groups, [1] member slots allocated, [2] queue of the drift kernel
-// (zeroed by launch_group_lists).
+// (zeroed by launch_groups or launch_group_lists).
 constexpr int kGroupCounters = 8;
 hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
                            const int *gstart, const int *gsize, const int *groot, int *counter,
@@ -118,9 +121,13 @@ hipError_t launch_drift_vjp(const double4 *xm, const double4 *v, int n, double d
                             double4 *lam_x, double4 *lam_v, hipStream_t st);
 
 // groups.hip
+// Labels of the groups of a pair list (union-find), and gsize[root] = bodies with that root (a
+// group when >= 2). gsize [n] is written; gfill [n] (may be null) zeroed and counter (may be null)
+// zeroed for launch_group_lists; out (may be null): {groups, invalid pairs}.
 hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
-                         int32_t *labels, int *mark, int64_t *out, int union_blocks,
-                         hipStream_t st, const double4 *xm = nullptr, const double4 *thr = nullptr);
+                         int32_t *labels, int *gsize, int *gfill, int *counter, int64_t *out,
+                         int union_blocks, hipStream_t st, const double4 *xm = nullptr,
+                         const double4 *thr = nullptr);
 
 // batched.hip
 constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048
