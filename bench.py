@@ -28,11 +28,11 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch of the binary64 pair kernel from the FETCH_SIZE / WRITE_SIZE passes
 # (calibrated with a plain copy; see profiles/k_pairs_disk32768.md), valid for the kernel source
 # whose hash is stored beside it.
-PAIR_KERNEL_TRAFFIC = {"bytes": 84916895, "source_sha256": "c6d55da8f2013d92a83b07daf187384655325f969f5beb7bcaf2d5d60f0d84ef"}
+PAIR_KERNEL_TRAFFIC = {"bytes": 84721820, "source_sha256": "0ac5620c112b3d70451cb2baed1be7ef5086ddeb453055c1db518d6f5948c549"}
 PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/pairs.hip", "paper_2604_09184_amd/csrc/device.hpp"]
 # Binary64 flop the hardware executes per pair, 64 x (ADD + MUL + TRANS + 2 FMA) from the
 # SQ_INSTS_VALU_*_F64 counters of the same profile, for the same kernel source.
-PAIR_KERNEL_HW_FLOP = {"per_pair": 24.42, "source_sha256": PAIR_KERNEL_TRAFFIC["source_sha256"]}
+PAIR_KERNEL_HW_FLOP = {"per_pair": 22.42, "source_sha256": PAIR_KERNEL_TRAFFIC["source_sha256"]}
 HBM_PEAK_GBPS = 8000.0             # MI355X HBM3E
 
 FLOP_PER_PAIR = 20                 # N-body convention: 3 sub, 5 for r^2, rsqrt, 3 for m r^-3, 6 accumulate, 2 slack
