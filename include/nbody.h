@@ -337,9 +337,12 @@ int nbody_step_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, double
  * lane of the kick owns two bodies (one j-body read serves two pairs), clear = one. Codes 0 .. 3.
  * Every class present is timed on its own systems (the others skipped) for nsteps steps (on
  * scratch copies; xm and v are not modified) with each admissible code, in order and then in
- * reverse order; another code replaces the current one only if it is more than 2 % faster. Use
- * nsteps of 10 or more: very short runs favour the wave tile. get/set read or replace the table (host array of 6 codes); get returns the
- * number of classes.
+ * reverse order; another code replaces the current one only if it is more than 2 % faster. The
+ * resulting table is then timed on the whole ensemble against each code applied to every class
+ * (without the wave bit where a class cannot take it), again in symmetric order and with the
+ * same 2 % margin, because the classes share the launch's queue. Use nsteps of 10 or more: very
+ * short runs favour the wave tile. get/set read or replace the table (host array of 6 codes); get
+ * returns the number of classes.
  */
 int nbody_autotune_batched(nbody_ctx *ctx, int32_t nsys, const int64_t *offs, const double *xm,
                            const double *v, int32_t nsteps, void *stream);

@@ -204,12 +204,12 @@ int make_kick_args(nbody_ctx *c, int n, const double *xm, const double *thr, boo
 }
 
 int emit_list(nbody_ctx *c, const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
-              hipStream_t st) {
+              hipStream_t st, unsigned long long *overflow = nullptr) {
   const int nb = nblocks(a.n);
   int64_t *rowtot = (int64_t *)ensure(c, B_ROWTOT, (size_t)a.n * sizeof(int64_t));
   int64_t *bsum = (int64_t *)ensure(c, B_BSUM, (size_t)nb * sizeof(int64_t));
   if (!rowtot || !bsum) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (emission)");
-  HIPCHK(c, launch_emit(a, pairs, cap, count, rowtot, bsum, st), "encounter emission");
+  HIPCHK(c, launch_emit(a, pairs, cap, count, rowtot, bsum, st, overflow), "encounter emission");
   return NBODY_OK;
 }
 
@@ -663,8 +663,12 @@ int nbody_encounter_groups(nbody_ctx *c, int64_t n, const int32_t *pairs, int64_
   if (!gsize) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (groups)");
   const int64_t want = (cap + kBlock - 1) / kBlock;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
-  HIPCHK(c, launch_groups(pairs, cap, count, (int)n, labels, gsize, nullptr, nullptr, out, blocks,
-                          (hipStream_t)stream), "groups");
+  if (n <= kGroupsSmall)
+    HIPCHK(c, launch_groups_small(pairs, cap, count, (int)n, labels, gsize, out, (hipStream_t)stream,
+                                  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr), "groups");
+  else
+    HIPCHK(c, launch_groups(pairs, cap, count, (int)n, labels, gsize, nullptr, nullptr, out, blocks,
+                            (hipStream_t)stream), "groups");
   return NBODY_OK;
 }
 
@@ -779,11 +783,16 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
       lt.thr[l] = lthr + (size_t)(l - 1) * n;
     }
   }
-  // groups of the list at the current kick positions (and, with levels, its adjacency)
+  // groups of the list at the current kick positions (and, with levels, its adjacency); a list
+  // longer than cap is counted in stats[5]. Up to kGroupsSmall bodies the groups and their member
+  // lists come from one one-workgroup launch.
+  const bool small = N <= kGroupsSmall;
   auto groups_now = [&]() -> int {
-    TRY(emit_list(c, a, lpairs, cap, lcount, st));
-    HIPCHK(c, launch_list_overflow(lcount, cap, S, st), "list check");
-    if (L == 0)
+    TRY(emit_list(c, a, lpairs, cap, lcount, st, S + 5));
+    if (L == 0 && small)
+      HIPCHK(c, launch_groups_small(lpairs, cap, lcount, N, labels, g.gsize, nullptr, st, nullptr, nullptr,
+                                    g.in, g.gstart, g.gmem, g.groot, g.counter), "groups");
+    else if (L == 0)
       HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.gsize, g.gfill, g.counter, nullptr, ublocks,
                               st), "groups");
     else
@@ -796,10 +805,15 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   // orbits; above it, sub substeps of kick / drift_{l+1} / kick
   std::function<int(int, double)> drift_levels = [&](int l, double tau) -> int {
     if (l == L) {
-      HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.gsize, g.gfill, g.counter, nullptr, ublocks,
-                              st, X, lt.thr[L]), "level groups");
-      HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
-                                   true, st), "group lists");
+      if (small) {
+        HIPCHK(c, launch_groups_small(lpairs, cap, lcount, N, labels, g.gsize, nullptr, st, X, lt.thr[L], g.in,
+                                      g.gstart, g.gmem, g.groot, g.counter), "level groups");
+      } else {
+        HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.gsize, g.gfill, g.counter, nullptr, ublocks,
+                                st, X, lt.thr[L]), "level groups");
+        HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
+                                     true, st), "group lists");
+      }
       cc.step = step;
       HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
                                 p.f_in, tau, kCeTol, S, cc, lt, st), "close-encounter drift");
@@ -825,8 +839,9 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   for (int s = 1; s <= nsteps; ++s) {
     step = s - 1;
     if (L == 0) {
-      HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
-                                   true, st), "group lists");
+      if (!small)
+        HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
+                                     true, st), "group lists");
       // first jump for all; Kepler drift for the bodies in no group
       HIPCHK(c, launch_jump_drift(X, Vv, momA, nbf, N, h, p.dt, p.m0, mu, nullptr, momB, st, nullptr, nullptr,
                                   g.in), "jump+drift");
@@ -1146,6 +1161,36 @@ int nbody_autotune_batched(nbody_ctx *c, int32_t nsys, const int64_t *offs, cons
     for (int q = 1; q < nc; ++q)
       if (t_code[cand[q]] < 0.98 * t_code[best]) best = cand[q];
     trial[b] = best;
+  }
+  // then the whole ensemble: the per-class choice against each code applied to every class (where
+  // a class cannot take the wave tile, the same code without it), in symmetric order; another
+  // set must win by more than 2 %. Classes interact through the queue's load balance, which the
+  // per-class runs do not see.
+  if (rc == NBODY_OK) {
+    only = -1;
+    int32_t sets[1 + kTileCodes][kBuckets];
+    int ns = 0;
+    std::copy(trial, trial + kBuckets, sets[ns++]);
+    for (int code = 0; code < kTileCodes; ++code) {
+      for (int b = 0; b < kBuckets; ++b)
+        sets[ns][b] = (code & kTileWave) && nmax[b] > batched_max_wave_n() ? (code & ~kTileWave) : code;
+      bool dup = false;
+      for (int q = 0; q < ns && !dup; ++q) dup = std::equal(sets[q], sets[q] + kBuckets, sets[ns]);
+      if (!dup) ++ns;
+    }
+    double t_set[1 + kTileCodes] = {0.0}, ms = 0.0;
+    std::copy(sets[0], sets[0] + kBuckets, trial);
+    rc = time_run(&ms);
+    for (int r = 0; r < 2 * ns && rc == NBODY_OK; ++r) {
+      const int q = r < ns ? r : 2 * ns - 1 - r;
+      std::copy(sets[q], sets[q] + kBuckets, trial);
+      rc = time_run(&ms);
+      t_set[q] += ms;
+    }
+    int best = 0;
+    for (int q = 1; q < ns; ++q)
+      if (t_set[q] < 0.98 * t_set[best]) best = q;
+    std::copy(sets[best], sets[best] + kBuckets, trial);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -692,18 +692,6 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
   }
 }
 
-// stats[5] += 1 when an encounter list was truncated (count > cap): its groups are incomplete.
-__global__ void k_list_overflow(const int64_t *__restrict__ count, int64_t cap,
-                                unsigned long long *__restrict__ stats) {
-  if (threadIdx.x == 0 && *count > cap) atomicAdd(stats + 5, 1ull);
-}
-
-hipError_t launch_list_overflow(const int64_t *count, int64_t cap, unsigned long long *stats,
-                                hipStream_t st) {
-  hipLaunchKernelGGL(k_list_overflow, dim3(1), dim3(64), 0, st, count, cap, stats);
-  return hipGetLastError();
-}
-
 hipError_t launch_group_lists(const int *label, int n, int *in, int *gsize, int *gstart, int *gfill,
                               int *gmem, int *groot, int *counter, bool counted, hipStream_t st) {
   if (!counted) {

@@ -37,8 +37,13 @@ hipError_t launch_locality(const double4 *xm, int n, float2 *range_part, unsigne
                            unsigned *count, unsigned *cursor, int *perm, hipStream_t st);
 int locality_cells();
 hipError_t launch_mass_check(const double4 *xm, int n, double2 *part, double2 *uni, hipStream_t st);
+// The encounter list of the emission buffers, sorted by (i, j), and its length in *count (also
+// beyond cap); *overflow (may be null) is incremented when the length exceeds cap. Lists of up to
+// kEmitSmall bodies are built by one workgroup in one launch.
+constexpr int kEmitSmall = 4096;
 hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
-                       int64_t *rowtot, int64_t *bsum, hipStream_t st);
+                       int64_t *rowtot, int64_t *bsum, hipStream_t st,
+                       unsigned long long *overflow = nullptr);
 hipError_t launch_validate(const double4 *xm, const double4 *v, int n, unsigned long long *key,
                            int64_t *out, hipStream_t st);
 hipError_t launch_energy(const double4 *xm, const double4 *v, const double4 *thr, int n, double G,
@@ -61,8 +66,6 @@ hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, ui
 // otherwise they are computed from the labels here.
 hipError_t launch_group_lists(const int *label, int n, int *in, int *gsize, int *gstart, int *gfill,
                               int *gmem, int *groot, int *counter, bool counted, hipStream_t st);
-hipError_t launch_list_overflow(const int64_t *count, int64_t cap, unsigned long long *stats,
-                                hipStream_t st);
 // Collisions inside the close-encounter drift: radius null = none. Mergers are appended to
 // merges [cap][3] = {step, survivor, removed} and mtime [cap] (time within the drift); count is
 // incremented once per merger, also beyond cap.
@@ -128,6 +131,14 @@ hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count
                          int32_t *labels, int *gsize, int *gfill, int *counter, int64_t *out,
                          int union_blocks, hipStream_t st, const double4 *xm = nullptr,
                          const double4 *thr = nullptr);
+// The same for n <= kGroupsSmall in one workgroup and one launch; with in non-null also the member
+// lists of launch_group_lists (in, gstart, gmem, groot, counter). out (may be null) is written,
+// not accumulated.
+constexpr int kGroupsSmall = 4096;
+hipError_t launch_groups_small(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
+                               int32_t *labels, int *gsize, int64_t *out, hipStream_t st,
+                               const double4 *xm, const double4 *thr, int *in, int *gstart,
+                               int *gmem, int *groot, int *counter);
 
 // batched.hip
 constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048

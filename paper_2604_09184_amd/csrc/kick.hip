@@ -298,9 +298,11 @@ __global__ __launch_bounds__(kBlock) void k_rowtot(const int *__restrict__ cnt, 
   if (threadIdx.x == 0) bsum[blockIdx.x] = lds[0];
 }
 
-// Exclusive scan of the block sums in one workgroup of 1024 threads; writes the total.
+// Exclusive scan of the block sums in one workgroup of 1024 threads; writes the total, and counts
+// a list longer than cap in *overflow (when given).
 __global__ __launch_bounds__(1024) void k_scan_bsum(int64_t *__restrict__ bsum, int nb,
-                                                    int64_t *__restrict__ count) {
+                                                    int64_t *__restrict__ count, int64_t cap,
+                                                    unsigned long long *__restrict__ overflow) {
   __shared__ int64_t lds[1024];
   const int t = threadIdx.x;
   const int per = (nb + 1023) / 1024;
@@ -321,7 +323,39 @@ __global__ __launch_bounds__(1024) void k_scan_bsum(int64_t *__restrict__ bsum, 
     bsum[b] = run;
     run += x;
   }
-  if (t == 1023) *count = lds[1023];
+  if (t == 1023) {
+    *count = lds[1023];
+    if (overflow && lds[1023] > cap) atomicAdd(overflow, 1ull);
+  }
+}
+
+// The partners of row i in chunk s (c of them, c > 0) appended at off (up to cap): from the
+// partner buffer, or by an exact rescan of the chunk when they did not fit in it.
+__device__ __forceinline__ void emit_chunk(const double4 *__restrict__ xm,
+                                           const double4 *__restrict__ thr, int n, int chunk,
+                                           const int *__restrict__ rowbuf, int R, int i, int s, int c,
+                                           int32_t *__restrict__ pairs, int64_t cap, int64_t &off) {
+  if (c <= R) {
+    for (int k = 0; k < c && off < cap; ++k, ++off) {
+      pairs[2 * off] = i;
+      pairs[2 * off + 1] = rowbuf[((size_t)s * R + k) * n + i];
+    }
+    return;
+  }
+  const double4 pi = xm[i];
+  const double4 ti = thr[i];
+  const int j0 = max(i + 1, s * chunk), j1 = min(n, (s + 1) * chunk);
+  for (int j = j0; j < j1 && off < cap; ++j) {
+    const double4 pj = xm[j];
+    const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double4 tq = thr[j];
+    if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
+      pairs[2 * off] = i;
+      pairs[2 * off + 1] = j;
+      ++off;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
@@ -345,40 +379,77 @@ __global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
   }
   if (i >= n || mine == 0) return;
   int64_t off = boff[blockIdx.x] + lds[t] - mine;
-  if (off >= cap) return;
-  for (int s = 0; s < S; ++s) {
+  for (int s = 0; s < S && off < cap; ++s) {
     const int c = cnt[(size_t)s * n + i];
-    if (c == 0) continue;
-    if (c <= R) {
-      for (int k = 0; k < c && off < cap; ++k, ++off) {
-        pairs[2 * off] = i;
-        pairs[2 * off + 1] = rowbuf[((size_t)s * R + k) * n + i];
-      }
-    } else {
-      const double4 pi = xm[i];
-      const double4 ti = thr[i];
-      const int j0 = max(i + 1, s * chunk), j1 = min(n, (s + 1) * chunk);
-      for (int j = j0; j < j1 && off < cap; ++j) {
-        const double4 pj = xm[j];
-        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const double4 tq = thr[j];
-        if (close_exact(r2, ti.y, tq.y, ti.z, tq.z)) {
-          pairs[2 * off] = i;
-          pairs[2 * off + 1] = j;
-          ++off;
-        }
+    if (c != 0) emit_chunk(xm, thr, n, chunk, rowbuf, R, i, s, c, pairs, cap, off);
+  }
+}
+
+// The one-workgroup emission for n <= kEmitSmall: row totals, their scan and the emission in one
+// launch. Thread t owns the rows [t per, (t + 1) per); the first pass keeps, per row, the mask of
+// its chunks with partners in LDS, so the second pass reads only those chunks' counts.
+__global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__ xm,
+                                                     const double4 *__restrict__ thr, int n, int S,
+                                                     int chunk, const int *__restrict__ cnt,
+                                                     const int *__restrict__ rowbuf, int R,
+                                                     int32_t *__restrict__ pairs, int64_t cap,
+                                                     int64_t *__restrict__ count,
+                                                     unsigned long long *__restrict__ overflow) {
+  __shared__ unsigned long long mask[kEmitSmall];
+  __shared__ int64_t lds[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int i0 = min(n, t * per), i1 = min(n, i0 + per);
+  int64_t mine = 0;
+  for (int i = i0; i < i1; ++i) {
+    unsigned long long m = 0;
+    for (int s0 = 0; s0 < S; s0 += 8) {
+      int c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u] = s0 + u < S ? cnt[(size_t)(s0 + u) * n + i] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        mine += c[u];
+        if (c[u] != 0) m |= 1ull << (s0 + u);
       }
     }
-    if (off >= cap) return;
+    mask[i] = m;
+  }
+  lds[t] = mine;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t add = t >= o ? lds[t - o] : 0;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  if (t == 1023) {
+    *count = lds[1023];
+    if (overflow && lds[1023] > cap) atomicAdd(overflow, 1ull);
+  }
+  if (!pairs || mine == 0) return;
+  int64_t off = lds[t] - mine;
+  for (int i = i0; i < i1 && off < cap; ++i) {
+    unsigned long long m = mask[i];
+    while (m && off < cap) {
+      const int s = __builtin_ctzll(m);
+      m &= m - 1;
+      emit_chunk(xm, thr, n, chunk, rowbuf, R, i, s, cnt[(size_t)s * n + i], pairs, cap, off);
+    }
   }
 }
 
 hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
-                       int64_t *rowtot, int64_t *bsum, hipStream_t st) {
+                       int64_t *rowtot, int64_t *bsum, hipStream_t st,
+                       unsigned long long *overflow) {
+  if (a.n <= kEmitSmall && a.nchunk <= 64) {
+    hipLaunchKernelGGL(k_emit_small, dim3(1), dim3(1024), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
+                       a.cnt, a.rowbuf, a.R, cap > 0 ? pairs : nullptr, cap, count, overflow);
+    return hipGetLastError();
+  }
   const int nb = nblocks(a.n);
   hipLaunchKernelGGL(k_rowtot, dim3(nb), dim3(kBlock), 0, st, a.cnt, a.nchunk, a.n, rowtot, bsum);
-  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, count);
+  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, count, cap, overflow);
   if (pairs && cap > 0)
     hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kBlock), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
                        a.cnt, a.rowbuf, a.R, rowtot, bsum, pairs, cap);
