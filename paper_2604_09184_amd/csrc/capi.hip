@@ -37,7 +37,7 @@ enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MO
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GIN, B_GSIZE,
              B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_LTHR, B_ADEG, B_AOFF,
-             B_AFILL, B_ADJ, B_LSKIP, B_AOWN, B_ATERM, B_ATOT, B_ETHR, B_NUM };
+             B_AFILL, B_ADJ, B_LSKIP, B_ATOT, B_ETHR, B_NUM };
 
 }  // namespace
 
@@ -768,11 +768,9 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     la.off = (int *)ensure(c, B_AOFF, (size_t)n * sizeof(int));
     la.fill = (int *)ensure(c, B_AFILL, (size_t)n * sizeof(int));
     la.adj = (int *)ensure(c, B_ADJ, (size_t)cap * 2 * sizeof(int));
-    la.own = (int *)ensure(c, B_AOWN, (size_t)cap * 2 * sizeof(int));
-    la.term = (double4 *)ensure(c, B_ATERM, (size_t)cap * 2 * sizeof(double4));
     la.total = (int *)ensure(c, B_ATOT, sizeof(int));
     lskip = (int *)ensure(c, B_LSKIP, (size_t)n * sizeof(int));
-    if (!lthr || !la.deg || !la.off || !la.fill || !la.adj || !la.own || !la.term || !la.total || !lskip)
+    if (!lthr || !la.deg || !la.off || !la.fill || !la.adj || !la.total || !lskip)
       return fail(c, NBODY_E_NOMEM, "workspace allocation failed (changeover levels)");
     const double cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
     double dtl = p.dt;
@@ -805,30 +803,30 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   // orbits; above it, sub substeps of kick / drift_{l+1} / kick
   std::function<int(int, double)> drift_levels = [&](int l, double tau) -> int {
     if (l == L) {
+      // the groups, their member lists and the mask of the bodies that drift on Kepler orbits
       if (small) {
         HIPCHK(c, launch_groups_small(lpairs, cap, lcount, N, labels, g.gsize, nullptr, st, X, lt.thr[L], g.in,
-                                      g.gstart, g.gmem, g.groot, g.counter), "level groups");
+                                      g.gstart, g.gmem, g.groot, g.counter, la.deg, lskip), "level groups");
       } else {
         HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.gsize, g.gfill, g.counter, nullptr, ublocks,
                                 st, X, lt.thr[L]), "level groups");
         HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
-                                     true, st), "group lists");
+                                     true, st, la.deg, lskip), "group lists");
       }
       cc.step = step;
       HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
                                 p.f_in, tau, kCeTol, S, cc, lt, st), "close-encounter drift");
-      HIPCHK(c, launch_level_mask(la.deg, g.in, N, lskip, st), "level mask");
       HIPCHK(c, launch_drift(X, Vv, N, tau, mu, nullptr, st, lskip), "level drift");
       return NBODY_OK;
     }
     // the closing half kick of a substep and the opening half kick of the next act at the same
     // positions: one kick over the whole substep length
     const double ts = tau / sub;
-    HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
+    HIPCHK(c, launch_level_kick(X, Vv, la, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
     for (int k = 0; k < sub; ++k) {
       TRY(drift_levels(l + 1, ts));
-      HIPCHK(c, launch_level_kick(X, Vv, la, 2 * cap, N, lt, l + 1, p.G, p.f_in, k + 1 < sub ? ts : 0.5 * ts,
-                                  st), "level kick");
+      HIPCHK(c, launch_level_kick(X, Vv, la, N, lt, l + 1, p.G, p.f_in, k + 1 < sub ? ts : 0.5 * ts, st),
+             "level kick");
     }
     return NBODY_OK;
   };

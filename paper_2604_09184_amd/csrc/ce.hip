@@ -50,10 +50,14 @@ __global__ __launch_bounds__(kBlock) void k_gcount(const int *__restrict__ label
 __global__ __launch_bounds__(kBlock) void k_galloc(const int *__restrict__ label,
                                                    const int *__restrict__ gsize, int n,
                                                    int *__restrict__ in, int *__restrict__ gstart,
-                                                   int *__restrict__ groot, int *__restrict__ counter) {
+                                                   int *__restrict__ groot, int *__restrict__ counter,
+                                                   const int *__restrict__ deg,
+                                                   int *__restrict__ skip) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  in[i] = gsize[label[i]] >= 2;
+  const bool member = gsize[label[i]] >= 2;
+  in[i] = member;
+  if (skip) skip[i] = !(deg[i] > 0 && !member);
   if (label[i] == i && gsize[i] >= 2) {
     gstart[i] = atomicAdd(counter + 1, gsize[i]);
     groot[atomicAdd(counter, 1)] = i;
@@ -693,14 +697,15 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
 }
 
 hipError_t launch_group_lists(const int *label, int n, int *in, int *gsize, int *gstart, int *gfill,
-                              int *gmem, int *groot, int *counter, bool counted, hipStream_t st) {
+                              int *gmem, int *groot, int *counter, bool counted, hipStream_t st,
+                              const int *deg, int *skip) {
   if (!counted) {
     hipLaunchKernelGGL(k_gzero, dim3(nblocks(n > kGroupCounters ? n : kGroupCounters)), dim3(kBlock),
                        0, st, n, gsize, gfill, counter);
     hipLaunchKernelGGL(k_gcount, dim3(nblocks(n)), dim3(kBlock), 0, st, label, n, gsize);
   }
   hipLaunchKernelGGL(k_galloc, dim3(nblocks(n)), dim3(kBlock), 0, st, label, gsize, n, in, gstart,
-                     groot, counter);
+                     groot, counter, deg, skip);
   hipLaunchKernelGGL(k_gfill, dim3(nblocks(n)), dim3(kBlock), 0, st, label, in, n, gstart, gfill,
                      gmem);
   return hipGetLastError();

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(1024) void k_groups_small(
     int32_t *__restrict__ labels, int *__restrict__ gsize, unsigned long long *__restrict__ out,
     const double4 *__restrict__ xm, const double4 *__restrict__ thr, int *__restrict__ in,
     int *__restrict__ gstart, int *__restrict__ gmem, int *__restrict__ groot,
-    int *__restrict__ counter) {
+    int *__restrict__ counter, const int *__restrict__ deg, int *__restrict__ skip) {
   __shared__ int par[kGroupsSmall], gsz[kGroupsSmall], gst[kGroupsSmall], gfl[kGroupsSmall];
   __shared__ int ngroups, nmembers;
   __shared__ unsigned long long nbad;
@@ -188,6 +188,7 @@ __global__ __launch_bounds__(1024) void k_groups_small(
     gsize[i] = r == i ? gsz[i] : 0;
     if (in) {
       in[i] = gsz[r] >= 2;
+      if (skip) skip[i] = !(deg[i] > 0 && !(gsz[r] >= 2));
       if (r == i && gsz[i] >= 2) {
         const int s0 = atomicAdd(&nmembers, gsz[i]);
         gst[i] = s0;
@@ -220,9 +221,9 @@ __global__ __launch_bounds__(1024) void k_groups_small(
 hipError_t launch_groups_small(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
                                int32_t *labels, int *gsize, int64_t *out, hipStream_t st,
                                const double4 *xm, const double4 *thr, int *in, int *gstart,
-                               int *gmem, int *groot, int *counter) {
+                               int *gmem, int *groot, int *counter, const int *deg, int *skip) {
   hipLaunchKernelGGL(k_groups_small, dim3(1), dim3(1024), 0, st, pairs, cap, count, n, labels, gsize,
-                     (unsigned long long *)out, xm, thr, in, gstart, gmem, groot, counter);
+                     (unsigned long long *)out, xm, thr, in, gstart, gmem, groot, counter, deg, skip);
   return hipGetLastError();
 }
 

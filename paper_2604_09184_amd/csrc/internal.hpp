@@ -64,8 +64,12 @@ hipError_t launch_drift(double4 *xm, double4 *v, int n, double dt, double mu, ui
 // Member lists of the groups (gsize >= 2) of the labels: in[i], gstart/gmem slices, root list
 // groot and counter[0] = groups. counted: gsize, gfill and counter come from launch_groups;
 // otherwise they are computed from the labels here.
+// With deg and skip given, also the drift mask of the deepest changeover level:
+// skip[i] = !(deg[i] > 0 && !in[i]) (bodies with listed partners outside the groups drift on
+// Kepler orbits there).
 hipError_t launch_group_lists(const int *label, int n, int *in, int *gsize, int *gstart, int *gfill,
-                              int *gmem, int *groot, int *counter, bool counted, hipStream_t st);
+                              int *gmem, int *groot, int *counter, bool counted, hipStream_t st,
+                              const int *deg = nullptr, int *skip = nullptr);
 // Collisions inside the close-encounter drift: radius null = none. Mergers are appended to
 // merges [cap][3] = {step, survivor, removed} and mtime [cap] (time within the drift); count is
 // incremented once per merger, also beyond cap.
@@ -99,16 +103,14 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
 
 // levels.hip: symmetric adjacency of a pair list (rows sorted by neighbour index), the level kicks
 // over it and the masks of the level drifts.
-// deg/off/fill [n]; adj/own [2 cap] (neighbour and row body per slot); term [2 cap]; total: slots used.
+// deg/off/fill [n]; adj [2 cap] (the neighbour per slot); total: slots used.
 struct LevelAdj {
-  int *deg, *off, *fill, *adj, *own, *total;
-  double4 *term;
+  int *deg, *off, *fill, *adj, *total;
 };
 hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
                             const LevelAdj &g, hipStream_t st);
-hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int64_t max_edges, int n,
-                             const LevelThr &lt, int level, double G, double f_in, double h,
-                             hipStream_t st);
+hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int n, const LevelThr &lt,
+                             int level, double G, double f_in, double h, hipStream_t st);
 // skip[i] = 1 unless body i has a listed partner (deg > 0) and is outside the groups (in == 0);
 // with in null: skip[i] = (deg[i] > 0).
 hipError_t launch_level_mask(const int *deg, const int *in, int n, int *skip, hipStream_t st);
@@ -138,7 +140,8 @@ constexpr int kGroupsSmall = 4096;
 hipError_t launch_groups_small(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
                                int32_t *labels, int *gsize, int64_t *out, hipStream_t st,
                                const double4 *xm, const double4 *thr, int *in, int *gstart,
-                               int *gmem, int *groot, int *counter);
+                               int *gmem, int *groot, int *counter, const int *deg = nullptr,
+                               int *skip = nullptr);
 
 // batched.hip
 constexpr int kBuckets = 6;   // size classes: N <= 64, 128, 256, 512, 1024, 2048

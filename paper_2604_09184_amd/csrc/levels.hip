@@ -39,21 +39,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_count(const int32_t *__restrict_
   }
 }
 
-// adj[slot] = neighbour, own[slot] = the row's body.
+// adj[slot] = neighbour.
 __global__ __launch_bounds__(kBlock) void k_adj_fill(const int32_t *__restrict__ pairs, int64_t cap,
                                                      const int64_t *__restrict__ count, int n,
                                                      const int *__restrict__ off,
-                                                     int *__restrict__ fill, int *__restrict__ adj,
-                                                     int *__restrict__ own) {
+                                                     int *__restrict__ fill, int *__restrict__ adj) {
   const int64_t np = min(*count, cap);
   for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < np; e += (int64_t)gridDim.x * kBlock) {
     const int i = pairs[2 * e], j = pairs[2 * e + 1];
     if (i < 0 || j < 0 || i >= n || j >= n || i == j) continue;
     const int si = off[i] + atomicAdd(fill + i, 1), sj = off[j] + atomicAdd(fill + j, 1);
     adj[si] = j;
-    own[si] = i;
     adj[sj] = i;
-    own[sj] = j;
   }
 }
 
@@ -115,54 +112,45 @@ __device__ __forceinline__ void level_K(double r, double rcij, double f_in, doub
   dK = 2.0 * y * (1.0 - y) / (D * D) / span;
 }
 
-// Term of one directed edge (row body i, neighbour j): G m_j (V/r^3 - V'(r)/r^2) d_ij with
-// V = W_{level-1} K_level, into term[slot].
-__global__ __launch_bounds__(kBlock) void k_level_edge(const double4 *__restrict__ xm,
-                                                       const int *__restrict__ adj,
-                                                       const int *__restrict__ own,
-                                                       const int *__restrict__ total,
-                                                       LevelThr lt, int level, double G,
-                                                       double f_in, double4 *__restrict__ term) {
-  const int q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= *total) return;
-  const int i = own[q], j = adj[q];
-  const double4 p = xm[i], pj = xm[j];
-  const double dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
-  const double r2 = dx * dx + dy * dy + dz * dz;
-  const double r = sqrt(r2);
-  double W = 1.0, dW = 0.0;
-  for (int l = 0; l < level; ++l) {
-    const double rcij = fmax(lt.thr[l][i].x, lt.thr[l][j].x);
-    double K, dK;
-    level_K(r, rcij, f_in, K, dK);
-    dW = dW * (1.0 - K) - W * dK;
-    W = W * (1.0 - K);
-  }
-  double K, dK;
-  level_K(r, fmax(lt.thr[level][i].x, lt.thr[level][j].x), f_in, K, dK);
-  const double V = W * K, dV = dW * K + W * dK;
-  const double c = G * pj.w * (V / (r2 * r) - dV / r2);
-  term[q] = make_double4(c * dx, c * dy, c * dz, 0.0);
-}
-
-// v_i += h sum of the row's terms: one wave per row, lane l adding the terms l, l + 64, ... of the
-// sorted row, then a butterfly of commutative additions (the same bits on every lane).
-__global__ __launch_bounds__(kBlock) void k_level_sum(const int *__restrict__ off,
-                                                      const int *__restrict__ deg,
-                                                      const double4 *__restrict__ term, int n,
-                                                      double h, double4 *__restrict__ v) {
+// v_i += h sum over the row's neighbours j (in ascending order) of the terms
+// G m_j (V/r^3 - V'(r)/r^2) d_ij, V = W_{level-1} K_level: one wave per row, lane l computing the
+// terms l, l + 64, ... of the sorted row, then a butterfly of commutative additions (the same bits
+// on every lane).
+__global__ __launch_bounds__(kBlock) void k_level_kick(const double4 *__restrict__ xm,
+                                                       const int *__restrict__ off,
+                                                       const int *__restrict__ deg,
+                                                       const int *__restrict__ adj, LevelThr lt,
+                                                       int level, double G, double f_in, int n,
+                                                       double h, double4 *__restrict__ v) {
   const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
   const int d = deg[i];
   if (d == 0) return;
-  const double4 *t = term + off[i];
+  const int *row = adj + off[i];
+  const double4 p = xm[i];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int q = lane; q < d; q += 64) {
-    const double4 u = t[q];
-    a0 += u.x;
-    a1 += u.y;
-    a2 += u.z;
+    const int j = row[q];
+    const double4 pj = xm[j];
+    const double dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    double W = 1.0, dW = 0.0;
+    for (int l = 0; l < level; ++l) {
+      const double rcij = fmax(lt.thr[l][i].x, lt.thr[l][j].x);
+      double K, dK;
+      level_K(r, rcij, f_in, K, dK);
+      dW = dW * (1.0 - K) - W * dK;
+      W = W * (1.0 - K);
+    }
+    double K, dK;
+    level_K(r, fmax(lt.thr[level][i].x, lt.thr[level][j].x), f_in, K, dK);
+    const double V = W * K, dV = dW * K + W * dK;
+    const double c = G * pj.w * (V / (r2 * r) - dV / r2);
+    a0 += c * dx;
+    a1 += c * dy;
+    a2 += c * dz;
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -211,20 +199,16 @@ hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *co
   hipLaunchKernelGGL(k_adj_alloc, dim3(nblocks(n)), dim3(kBlock), 0, st, g.deg, n, g.off, g.total);
   if (blocks > 0)
     hipLaunchKernelGGL(k_adj_fill, dim3(blocks), dim3(kBlock), 0, st, pairs, cap, count, n, g.off, g.fill,
-                       g.adj, g.own);
+                       g.adj);
   hipLaunchKernelGGL(k_adj_sort, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st, g.off,
                      g.deg, n, g.adj);
   return hipGetLastError();
 }
 
-hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int64_t max_edges, int n,
-                             const LevelThr &lt, int level, double G, double f_in, double h,
-                             hipStream_t st) {
-  if (max_edges > 0)
-    hipLaunchKernelGGL(k_level_edge, dim3(nblocks(max_edges)), dim3(kBlock), 0, st, xm, g.adj, g.own,
-                       g.total, lt, level, G, f_in, g.term);
-  hipLaunchKernelGGL(k_level_sum, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st, g.off,
-                     g.deg, g.term, n, h, v);
+hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int n, const LevelThr &lt,
+                             int level, double G, double f_in, double h, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_kick, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st, xm,
+                     g.off, g.deg, g.adj, lt, level, G, f_in, n, h, v);
   return hipGetLastError();
 }
 
