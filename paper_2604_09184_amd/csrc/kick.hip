@@ -386,8 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
 }
 
 // The one-workgroup emission for n <= kEmitSmall: row totals, their scan and the emission in one
-// launch. Thread t owns the rows [t per, (t + 1) per); the first pass keeps, per row, the mask of
-// its chunks with partners in LDS, so the second pass reads only those chunks' counts.
+// launch. The first pass reads the counts coalesced (thread t takes the rows t, t + 1024, ...,
+// eight chunks of each in flight) and keeps, per row, the total and the mask of its chunks with
+// partners in LDS; thread t then owns the rows [t per, (t + 1) per) for the scan and the emission,
+// which reads only the counts of the masked chunks.
 __global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__ xm,
                                                      const double4 *__restrict__ thr, int n, int S,
                                                      int chunk, const int *__restrict__ cnt,
@@ -396,39 +398,53 @@ __global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__
                                                      int64_t *__restrict__ count,
                                                      unsigned long long *__restrict__ overflow) {
   __shared__ unsigned long long mask[kEmitSmall];
-  __shared__ int64_t lds[1024];
+  __shared__ int rtot[kEmitSmall];
+  __shared__ int64_t lds[16];
   const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int i0 = min(n, t * per), i1 = min(n, i0 + per);
-  int64_t mine = 0;
-  for (int i = i0; i < i1; ++i) {
+  for (int i = t; i < n; i += 1024) {
     unsigned long long m = 0;
+    int tot = 0;
     for (int s0 = 0; s0 < S; s0 += 8) {
       int c[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) c[u] = s0 + u < S ? cnt[(size_t)(s0 + u) * n + i] : 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        mine += c[u];
+        tot += c[u];
         if (c[u] != 0) m |= 1ull << (s0 + u);
       }
     }
     mask[i] = m;
+    rtot[i] = tot;
   }
-  lds[t] = mine;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int64_t add = t >= o ? lds[t - o] : 0;
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
+  const int per = (n + 1023) / 1024;
+  const int i0 = min(n, t * per), i1 = min(n, i0 + per);
+  int64_t mine = 0;
+  for (int i = i0; i < i1; ++i) mine += rtot[i];
+  // inclusive scan: within each wave by lane shifts, then over the sixteen wave totals
+  const int lane = t & 63, w = t >> 6;
+  int64_t inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t up = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += up;
   }
-  if (t == 1023) {
-    *count = lds[1023];
-    if (overflow && lds[1023] > cap) atomicAdd(overflow, 1ull);
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int q = 0; q < 16; ++q) {
+      const int64_t x = lds[q];
+      lds[q] = run;
+      run += x;
+    }
+    *count = run;
+    if (overflow && run > cap) atomicAdd(overflow, 1ull);
   }
+  __syncthreads();
   if (!pairs || mine == 0) return;
-  int64_t off = lds[t] - mine;
+  int64_t off = lds[w] + inc - mine;
   for (int i = i0; i < i1 && off < cap; ++i) {
     unsigned long long m = mask[i];
     while (m && off < cap) {

@@ -199,18 +199,15 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
   }
 }
 
-// Register budget: up to 102 VGPRs (five waves per SIMD in the compiler's model). Measured on
-// gfx950, kernels of 60 to 116 VGPRs all keep four waves per SIMD resident, so the four
-// independent pair chains of the branch-free loop cost no occupancy.
+// The kernel body: one lane per body i of the launch's rows, the j-range of blockIdx.y.
 template <bool FORCE, bool EMIT, bool CE, bool SPLIT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(const double4 *__restrict__ xm,
-                                                  const double4 *__restrict__ thr,
-                                                  const int *__restrict__ perm,
-                                                  const double2 *__restrict__ uni, int n, int chunk,
-                                                  double f_in, double4 *__restrict__ part,
-                                                  double4 *__restrict__ part_ce,
-                                                  int *__restrict__ cnt, int *__restrict__ rowbuf,
-                                                  int R, double c15) {
+__device__ __forceinline__ void pairs_body(const double4 *__restrict__ xm,
+                                           const double4 *__restrict__ thr,
+                                           const int *__restrict__ perm,
+                                           const double2 *__restrict__ uni, int n, int chunk,
+                                           double f_in, double4 *__restrict__ part,
+                                           double4 *__restrict__ part_ce, int *__restrict__ cnt,
+                                           int *__restrict__ rowbuf, int R, double c15) {
   const int lane_body = blockIdx.x * kBlock + threadIdx.x;
   const bool valid = lane_body < n;
   const int lb = valid ? lane_body : n - 1;
@@ -249,12 +246,41 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   if (EMIT) cnt[o] = nc;
 }
 
+// Register budget of the kernels without the close-encounter part: 80 VGPRs (six waves per SIMD
+// in the compiler's model), no spills. Measured resident waves per SIMD on the 32768 disk: 4.1 at
+// 86 VGPRs, 4.9 at 80, 5.6 at 72 and 6.3 at 64 (the last two with spills outside the fast loop),
+// VALU busy 0.88-0.90 in every case: the issue efficiency of this instruction mix does not rise
+// with occupancy beyond five waves. The kernels with the close-encounter part keep five waves in
+// the compiler's model, where they do not spill.
+template <bool FORCE, bool EMIT, bool SPLIT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_pairs(
+    const double4 *__restrict__ xm, const double4 *__restrict__ thr, const int *__restrict__ perm,
+    const double2 *__restrict__ uni, int n, int chunk, double f_in, double4 *__restrict__ part,
+    double4 *__restrict__ part_ce, int *__restrict__ cnt, int *__restrict__ rowbuf, int R,
+    double c15) {
+  pairs_body<FORCE, EMIT, false, SPLIT>(xm, thr, perm, uni, n, chunk, f_in, part, part_ce, cnt,
+                                        rowbuf, R, c15);
+}
+
+template <bool EMIT, bool SPLIT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs_ce(
+    const double4 *__restrict__ xm, const double4 *__restrict__ thr, const int *__restrict__ perm,
+    const double2 *__restrict__ uni, int n, int chunk, double f_in, double4 *__restrict__ part,
+    double4 *__restrict__ part_ce, int *__restrict__ cnt, int *__restrict__ rowbuf, int R,
+    double c15) {
+  pairs_body<true, EMIT, true, SPLIT>(xm, thr, perm, uni, n, chunk, f_in, part, part_ce, cnt,
+                                      rowbuf, R, c15);
+}
 
 template <bool F, bool E, bool C, bool S>
 static void go(const KickArgs &a, hipStream_t st) {
   dim3 grid(nblocks(a.n), a.nchunk);
-  hipLaunchKernelGGL((k_pairs<F, E, C, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.uni,
-                     a.n, a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5);
+  if constexpr (C)
+    hipLaunchKernelGGL((k_pairs_ce<E, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.uni, a.n,
+                       a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5);
+  else
+    hipLaunchKernelGGL((k_pairs<F, E, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.uni, a.n,
+                       a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5);
 }
 
 hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool split,
