@@ -856,8 +856,12 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     }
     // mergers change masses: the equal-mass flag of the pair kernel is taken again
     if (cc.radius) TRY(mass_check(c, N, X, st, &a.uni));
-    HIPCHK(c, launch_momentum(X, Vv, N, momB, st), "momentum");
-    HIPCHK(c, launch_jump(X, momB, nbf, N, h, p.m0, st), "jump");
+    if (N <= kJumpSmall) {
+      HIPCHK(c, launch_momentum_jump_small(X, Vv, N, h, p.m0, st), "momentum + jump");
+    } else {
+      HIPCHK(c, launch_momentum(X, Vv, N, momB, st), "momentum");
+      HIPCHK(c, launch_jump(X, momB, nbf, N, h, p.m0, st), "jump");
+    }
     if (a.perm && s % c->locality_every == 0) TRY(locality(c, N, X, st, &a.perm));
     const bool last = s == nsteps;
     HIPCHK(c, launch_pairs(a, true, !last, false, false, st), "hybrid pairs");

@@ -53,6 +53,11 @@ hipError_t launch_energy(const double4 *xm, const double4 *v, const double4 *thr
 hipError_t launch_momentum(const double4 *xm, const double4 *v, int n, double4 *mom, hipStream_t st);
 hipError_t launch_jump(double4 *xm, const double4 *mom, int nb, int n, double h, double m0,
                        hipStream_t st, double4 *x_rec = nullptr);
+// launch_momentum followed by launch_jump for up to kJumpSmall bodies, in one launch, with the
+// same result bits.
+constexpr int kJumpSmall = 4096;
+hipError_t launch_momentum_jump_small(double4 *xm, const double4 *v, int n, double h, double m0,
+                                      hipStream_t st);
 hipError_t launch_jump_drift(double4 *xm, double4 *v, const double4 *mom_in, int nb, int n,
                              double hjump, double dt, double m0, double mu, uint32_t *status,
                              double4 *mom_out, hipStream_t st, double4 *x_rec = nullptr,

@@ -41,6 +41,37 @@ __global__ __launch_bounds__(64) void k_jump(double4 *__restrict__ xm,
   if (x_rec) x_rec[i] = p;
 }
 
+// Momentum and jump of up to kJumpSmall bodies in one workgroup (16 waves): the per-64-body
+// partials of k_momentum (the same wave butterfly) into LDS, then every wave sums them as k_jump
+// does, so the positions come out bit for bit as from the two launches.
+__global__ __launch_bounds__(1024) void k_momentum_jump_small(double4 *__restrict__ xm,
+                                                              const double4 *__restrict__ v, int n,
+                                                              double h, double m0) {
+  __shared__ double4 mom[kJumpSmall / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nb = (n + 63) / 64;
+  for (int b = w; b < nb; b += 16) {
+    const int i = b * 64 + lane;
+    double P[3] = {0.0, 0.0, 0.0};
+    if (i < n) {
+      const double m = xm[i].w;
+      const double4 q = v[i];
+      P[0] = m * q.x; P[1] = m * q.y; P[2] = m * q.z;
+    }
+    wave_sum<3>(P);
+    if (lane == 0) mom[b] = make_double4(P[0], P[1], P[2], 0.0);
+  }
+  __syncthreads();
+  double P[3];
+  partials_total_wave(mom, nb, P);
+  const double sx = h * (P[0] / m0), sy = h * (P[1] / m0), sz = h * (P[2] / m0);
+  for (int i = t; i < n; i += 1024) {
+    double4 p = xm[i];
+    p.x = p.x + sx; p.y = p.y + sy; p.z = p.z + sz;
+    xm[i] = p;
+  }
+}
+
 // x_rec / v_rec (may be null) receive the positions after the jump (before the drift) and the
 // velocities after the drift. skip (may be null): bodies with skip[i] != 0 get the jump but not
 // the Kepler drift (their drift is the close-encounter integration).
@@ -91,6 +122,12 @@ __global__ __launch_bounds__(64) void k_drift(double4 *__restrict__ xm, double4 
 
 hipError_t launch_momentum(const double4 *xm, const double4 *v, int n, double4 *mom, hipStream_t st) {
   hipLaunchKernelGGL(k_momentum, dim3(fin_blocks(n)), dim3(64), 0, st, xm, v, n, mom);
+  return hipGetLastError();
+}
+
+hipError_t launch_momentum_jump_small(double4 *xm, const double4 *v, int n, double h, double m0,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(k_momentum_jump_small, dim3(1), dim3(1024), 0, st, xm, v, n, h, m0);
   return hipGetLastError();
 }
 
