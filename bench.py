@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch of the binary64 pair kernel from the FETCH_SIZE / WRITE_SIZE passes
 # (calibrated with a plain copy; see profiles/k_pairs_disk32768.md), valid for the kernel source
 # whose hash is stored beside it.
-PAIR_KERNEL_TRAFFIC = {"bytes": 84924434, "source_sha256": "22ac42db6d7a1f97300e7352fffdad184a0e78b848ab8d184ce01e5cb3009aa7"}
+PAIR_KERNEL_TRAFFIC = {"bytes": 84928974, "source_sha256": "319824571e214a287472f068c6fa8383fce672bdf84dceacbdfa65d0b656c1d3"}
 PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/pairs.hip", "paper_2604_09184_amd/csrc/device.hpp"]
 # Binary64 flop the hardware executes per pair, 64 x (ADD + MUL + TRANS + 2 FMA) from the
 # SQ_INSTS_VALU_*_F64 counters of the same profile, for the same kernel source.

@@ -131,11 +131,15 @@ int check_n(nbody_ctx *c, int64_t n) {
     if (r_ != NBODY_OK) return r_; \
   } while (0)
 
-// j-chunking: enough waves to fill the chip, chunks of at least 64 bodies.
+// j-chunking: enough waves to fill the chip, chunks of at least 64 bodies, or 32 for systems of
+// at most 4096 bodies, twice the waves of a launch that otherwise runs one wave per SIMD
+// (measured: 2048-body step 25.0 -> 21.8 us). The chunking depends on n alone, so a launch with
+// the encounter list sums in the same order as one without.
 void plan(const nbody_ctx *c, int n, int &S, int &chunk) {
   const int iwaves = (n + 63) / 64;
   int s = (c->target_waves + iwaves - 1) / iwaves;
-  const int smax = (n + 63) / 64;
+  const int minchunk = n <= 4096 ? 32 : 64;
+  const int smax = (n + minchunk - 1) / minchunk;
   if (s > smax) s = smax;
   if (s < 1) s = 1;
   chunk = (n + s - 1) / s;

@@ -397,12 +397,12 @@ __global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__
                                                      int32_t *__restrict__ pairs, int64_t cap,
                                                      int64_t *__restrict__ count,
                                                      unsigned long long *__restrict__ overflow) {
-  __shared__ unsigned long long mask[kEmitSmall];
+  __shared__ unsigned long long mask[2][kEmitSmall];   // chunks 0..63 and 64..127
   __shared__ int rtot[kEmitSmall];
   __shared__ int64_t lds[16];
   const int t = threadIdx.x;
   for (int i = t; i < n; i += 1024) {
-    unsigned long long m = 0;
+    unsigned long long m[2] = {0, 0};
     int tot = 0;
     for (int s0 = 0; s0 < S; s0 += 8) {
       int c[8];
@@ -411,10 +411,11 @@ __global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         tot += c[u];
-        if (c[u] != 0) m |= 1ull << (s0 + u);
+        if (c[u] != 0) m[(s0 + u) >> 6] |= 1ull << ((s0 + u) & 63);
       }
     }
-    mask[i] = m;
+    mask[0][i] = m[0];
+    mask[1][i] = m[1];
     rtot[i] = tot;
   }
   __syncthreads();
@@ -445,20 +446,21 @@ __global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__
   __syncthreads();
   if (!pairs || mine == 0) return;
   int64_t off = lds[w] + inc - mine;
-  for (int i = i0; i < i1 && off < cap; ++i) {
-    unsigned long long m = mask[i];
-    while (m && off < cap) {
-      const int s = __builtin_ctzll(m);
-      m &= m - 1;
-      emit_chunk(xm, thr, n, chunk, rowbuf, R, i, s, cnt[(size_t)s * n + i], pairs, cap, off);
+  for (int i = i0; i < i1 && off < cap; ++i)
+    for (int h = 0; h < 2; ++h) {
+      unsigned long long m = mask[h][i];
+      while (m && off < cap) {
+        const int s = 64 * h + __builtin_ctzll(m);
+        m &= m - 1;
+        emit_chunk(xm, thr, n, chunk, rowbuf, R, i, s, cnt[(size_t)s * n + i], pairs, cap, off);
+      }
     }
-  }
 }
 
 hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *count,
                        int64_t *rowtot, int64_t *bsum, hipStream_t st,
                        unsigned long long *overflow) {
-  if (a.n <= kEmitSmall && a.nchunk <= 64) {
+  if (a.n <= kEmitSmall && a.nchunk <= 128) {
     hipLaunchKernelGGL(k_emit_small, dim3(1), dim3(1024), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
                        a.cnt, a.rowbuf, a.R, cap > 0 ? pairs : nullptr, cap, count, overflow);
     return hipGetLastError();

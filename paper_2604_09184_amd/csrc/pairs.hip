@@ -77,6 +77,25 @@ __device__ __forceinline__ void pair_far(const double4 &pi, const double4 &pj, d
   a[2] = fma(s, dz, a[2]);
 }
 
+// A block of LEN j-bodies with no pair near enough to need the predicate. No per-j branch; the
+// j-bodies alternate between two pairs of scalar registers, each pair loaded one step ahead of
+// its use (the last step reloads bodies LEN - 2 and LEN - 1, unused).
+template <bool SPLIT, bool UNI, int LEN>
+__device__ __forceinline__ void far_block(const double4 *__restrict__ xb, const double4 &pi,
+                                          double c15, double (&a)[3]) {
+  double4 c0 = xb[0], c1 = xb[1];
+  for (int k = 0; k < LEN; k += 4) {
+    const double4 n0 = xb[k + 2], n1 = xb[k + 3];
+    pair_far<SPLIT, UNI>(pi, c0, c15, a);
+    pair_far<SPLIT, UNI>(pi, c1, c15, a);
+    const int kk = min(k + 4, LEN - 2);
+    c0 = xb[kk];
+    c1 = xb[kk + 1];
+    pair_far<SPLIT, UNI>(pi, n0, c15, a);
+    pair_far<SPLIT, UNI>(pi, n1, c15, a);
+  }
+}
+
 // One pair of the force loop: r^-3 on the fast path; close_part only for a screened-in j.
 template <bool EMIT, bool CE, bool SPLIT, bool UNI>
 __device__ __forceinline__ void pair_force(const double4 *__restrict__ thr, const double4 &pi,
@@ -156,21 +175,13 @@ __device__ __forceinline__ void pairs_loop(const double4 *__restrict__ xm,
       continue;
     }
     if (mask == 0 && je - jb == 64) {
-      // the common case: a whole block with no pair near enough to need the predicate. No
-      // per-j branch; the j-bodies alternate between two pairs of scalar registers, each pair
-      // loaded one step ahead of its use (the last step reloads bodies 62 and 63, unused)
-      const double4 *__restrict__ xb = xm + jb;
-      double4 c0 = xb[0], c1 = xb[1];
-      for (int k = 0; k < 64; k += 4) {
-        const double4 n0 = xb[k + 2], n1 = xb[k + 3];
-        pair_far<SPLIT, UNI>(pi, c0, c15v, a);
-        pair_far<SPLIT, UNI>(pi, c1, c15v, a);
-        const int kk = min(k + 4, 62);
-        c0 = xb[kk];
-        c1 = xb[kk + 1];
-        pair_far<SPLIT, UNI>(pi, n0, c15v, a);
-        pair_far<SPLIT, UNI>(pi, n1, c15v, a);
-      }
+      // the common case: a whole block with no pair near enough to need the predicate
+      far_block<SPLIT, UNI, 64>(xm + jb, pi, c15v, a);
+      continue;
+    }
+    if (mask == 0 && je - jb == 32) {
+      // the half blocks of the chunks of small systems
+      far_block<SPLIT, UNI, 32>(xm + jb, pi, c15v, a);
       continue;
     }
     // a block with screened-in j (or a partial block): j-bodies two at a time, the scalar loads
