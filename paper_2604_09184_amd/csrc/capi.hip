@@ -32,7 +32,7 @@ struct Buf {
   size_t bytes = 0;
 };
 
-enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
+enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_ROWSUM, B_ROWMASK, B_MOM_A, B_MOM_B, B_THR, B_EPARTS,
              B_ADJ_STATES, B_XA, B_VA, B_LSUM, B_B_OFFS, B_B_ORDER,
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GIN, B_GSIZE,
@@ -96,6 +96,17 @@ void *ensure(nbody_ctx *c, BufId id, size_t bytes) {
   }
   b.bytes = bytes;
   return b.p;
+}
+
+// ensure() for a buffer that must be zero when first handed out (hipMemset on (re)allocation;
+// its users leave it zero after every use).
+void *ensure_zeroed(nbody_ctx *c, BufId id, size_t bytes) {
+  Buf &b = c->buf[id];
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return b.p;
+  void *p = ensure(c, id, bytes);
+  if (p && hipMemset(p, 0, bytes) != hipSuccess) return nullptr;
+  return p;
 }
 
 bool params_ok(const nbody_params *p) {
@@ -204,6 +215,16 @@ int make_kick_args(nbody_ctx *c, int n, const double *xm, const double *thr, boo
   a.rowbuf = need_emit ? (int *)ensure(c, B_ROWBUF, sn * (size_t)a.R * sizeof(int)) : nullptr;
   if ((need_force && !a.part) || (need_ce && !a.part_ce) || (need_emit && (!a.cnt || !a.rowbuf)))
     return fail(c, NBODY_E_NOMEM, "workspace allocation failed (n = %d, chunks = %d)", n, a.nchunk);
+  // per-row totals and chunk masks for the emission (zero between uses: set by the pair kernel,
+  // cleared by the emission that follows it)
+  a.rowsum = nullptr;
+  a.rowmask = nullptr;
+  if (need_emit && a.nchunk <= 64 * kRowMaskWords) {
+    a.rowsum = (int *)ensure_zeroed(c, B_ROWSUM, (size_t)n * sizeof(int));
+    a.rowmask = (unsigned long long *)ensure_zeroed(c, B_ROWMASK,
+                                                     (size_t)n * kRowMaskWords * sizeof(unsigned long long));
+    if (!a.rowsum || !a.rowmask) return fail(c, NBODY_E_NOMEM, "workspace allocation failed (row masks)");
+  }
   return NBODY_OK;
 }
 
@@ -617,6 +638,8 @@ int nbody_step(nbody_ctx *c, int64_t n, double *xm, double *v, const double *thr
   KickArgs ac = a;
   ac.R = 0;
   ac.rowbuf = nullptr;
+  ac.rowsum = nullptr;   // no emission follows these launches
+  ac.rowmask = nullptr;
   const bool split = p.precision == NBODY_PREC_SPLIT;
   const double h = 0.5 * p.dt;
   const double mu = p.G * p.m0;

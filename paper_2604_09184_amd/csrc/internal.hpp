@@ -22,7 +22,13 @@ struct KickArgs {
   int *cnt;          // [S][n] close partners j > i per chunk (emission only)
   int *rowbuf;       // [S][R][n] partner indices (emission only)
   int R;
+  // Emission launches followed by launch_emit, S <= 64 kRowMaskWords (may be null): per row the
+  // total of cnt over the chunks and the mask of its chunks with partners, added by integer
+  // atomics in the pair kernel (the same values in any order) and cleared by launch_emit.
+  int *rowsum = nullptr;                 // [n]
+  unsigned long long *rowmask = nullptr; // [n][kRowMaskWords]
 };
+constexpr int kRowMaskWords = 4;
 
 // kick.hip
 hipError_t launch_rcrit(const double4 *xm, const double4 *v, double4 *thr, int n, double m0,

@@ -280,14 +280,25 @@ hipError_t launch_finalize(const double4 *part, const double4 *part_ce, int S, i
 // Rows are emitted in ascending i; within a row the chunks are visited in ascending j and each
 // chunk recorded its partners in ascending j, so the list comes out sorted by (i, j) without a
 // sort. A row-chunk with more partners than the buffer holds is rescanned here.
+// Row totals from the pair kernel's per-row sums when it kept them (rowsum, cleared here; the
+// chunk masks too when no emission follows), else from the counts of every chunk.
 __global__ __launch_bounds__(kBlock) void k_rowtot(const int *__restrict__ cnt, int S, int n,
                                                    int64_t *__restrict__ rowtot,
-                                                   int64_t *__restrict__ bsum) {
+                                                   int64_t *__restrict__ bsum,
+                                                   int *__restrict__ rowsum,
+                                                   unsigned long long *__restrict__ rowmask,
+                                                   bool clear_mask) {
   __shared__ int64_t lds[kBlock];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   int64_t t = 0;
-  if (i < n)
+  if (i < n && rowsum) {
+    t = rowsum[i];
+    rowsum[i] = 0;
+    if (clear_mask)
+      for (int w = 0; w < kRowMaskWords; ++w) rowmask[(size_t)i * kRowMaskWords + w] = 0;
+  } else if (i < n) {
     for (int s = 0; s < S; ++s) t += cnt[(size_t)s * n + i];
+  }
   if (i < n) rowtot[i] = t;
   lds[threadIdx.x] = t;
   __syncthreads();
@@ -364,11 +375,19 @@ __global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
                                                  const int *__restrict__ rowbuf, int R,
                                                  const int64_t *__restrict__ rowtot,
                                                  const int64_t *__restrict__ boff,
-                                                 int32_t *__restrict__ pairs, int64_t cap) {
+                                                 int32_t *__restrict__ pairs, int64_t cap,
+                                                 unsigned long long *__restrict__ rowmask) {
   __shared__ int64_t lds[kBlock];
   const int t = threadIdx.x;
   const int i = blockIdx.x * kBlock + t;
   const int64_t mine = i < n ? rowtot[i] : 0;
+  // the chunks with partners, from the pair kernel's mask (read and cleared) when it kept one
+  unsigned long long m[kRowMaskWords] = {0, 0, 0, 0};
+  if (rowmask && i < n)
+    for (int w = 0; w < kRowMaskWords; ++w) {
+      m[w] = rowmask[(size_t)i * kRowMaskWords + w];
+      if (m[w]) rowmask[(size_t)i * kRowMaskWords + w] = 0;
+    }
   lds[t] = mine;
   __syncthreads();
   for (int o = 1; o < kBlock; o <<= 1) {
@@ -379,6 +398,15 @@ __global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
   }
   if (i >= n || mine == 0) return;
   int64_t off = boff[blockIdx.x] + lds[t] - mine;
+  if (rowmask) {
+    for (int w = 0; w < kRowMaskWords; ++w)
+      while (m[w] && off < cap) {
+        const int s = 64 * w + __builtin_ctzll(m[w]);
+        m[w] &= m[w] - 1;
+        emit_chunk(xm, thr, n, chunk, rowbuf, R, i, s, cnt[(size_t)s * n + i], pairs, cap, off);
+      }
+    return;
+  }
   for (int s = 0; s < S && off < cap; ++s) {
     const int c = cnt[(size_t)s * n + i];
     if (c != 0) emit_chunk(xm, thr, n, chunk, rowbuf, R, i, s, c, pairs, cap, off);
@@ -396,7 +424,9 @@ __global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__
                                                      const int *__restrict__ rowbuf, int R,
                                                      int32_t *__restrict__ pairs, int64_t cap,
                                                      int64_t *__restrict__ count,
-                                                     unsigned long long *__restrict__ overflow) {
+                                                     unsigned long long *__restrict__ overflow,
+                                                     int *__restrict__ rowsum,
+                                                     unsigned long long *__restrict__ rowmask) {
   __shared__ unsigned long long mask[2][kEmitSmall];   // chunks 0..63 and 64..127
   __shared__ int rtot[kEmitSmall];
   __shared__ int64_t lds[16];
@@ -404,6 +434,21 @@ __global__ __launch_bounds__(1024) void k_emit_small(const double4 *__restrict__
   for (int i = t; i < n; i += 1024) {
     unsigned long long m[2] = {0, 0};
     int tot = 0;
+    if (rowsum) {
+      // the pair kernel's per-row total and chunk mask (at most 128 chunks here), read and cleared
+      tot = rowsum[i];
+      if (tot) {
+        rowsum[i] = 0;
+        m[0] = rowmask[(size_t)i * kRowMaskWords];
+        m[1] = rowmask[(size_t)i * kRowMaskWords + 1];
+        rowmask[(size_t)i * kRowMaskWords] = 0;
+        rowmask[(size_t)i * kRowMaskWords + 1] = 0;
+      }
+      mask[0][i] = m[0];
+      mask[1][i] = m[1];
+      rtot[i] = tot;
+      continue;
+    }
     for (int s0 = 0; s0 < S; s0 += 8) {
       int c[8];
 #pragma unroll
@@ -462,15 +507,18 @@ hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *
                        unsigned long long *overflow) {
   if (a.n <= kEmitSmall && a.nchunk <= 128) {
     hipLaunchKernelGGL(k_emit_small, dim3(1), dim3(1024), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
-                       a.cnt, a.rowbuf, a.R, cap > 0 ? pairs : nullptr, cap, count, overflow);
+                       a.cnt, a.rowbuf, a.R, cap > 0 ? pairs : nullptr, cap, count, overflow, a.rowsum,
+                       a.rowmask);
     return hipGetLastError();
   }
   const int nb = nblocks(a.n);
-  hipLaunchKernelGGL(k_rowtot, dim3(nb), dim3(kBlock), 0, st, a.cnt, a.nchunk, a.n, rowtot, bsum);
+  const bool emit = pairs && cap > 0;
+  hipLaunchKernelGGL(k_rowtot, dim3(nb), dim3(kBlock), 0, st, a.cnt, a.nchunk, a.n, rowtot, bsum, a.rowsum,
+                     a.rowmask, !emit);
   hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, count, cap, overflow);
-  if (pairs && cap > 0)
+  if (emit)
     hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kBlock), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
-                       a.cnt, a.rowbuf, a.R, rowtot, bsum, pairs, cap);
+                       a.cnt, a.rowbuf, a.R, rowtot, bsum, pairs, cap, a.rowmask);
   return hipGetLastError();
 }
 

@@ -218,7 +218,9 @@ __device__ __forceinline__ void pairs_body(const double4 *__restrict__ xm,
                                            const double2 *__restrict__ uni, int n, int chunk,
                                            double f_in, double4 *__restrict__ part,
                                            double4 *__restrict__ part_ce, int *__restrict__ cnt,
-                                           int *__restrict__ rowbuf, int R, double c15) {
+                                           int *__restrict__ rowbuf, int R, double c15,
+                                           int *__restrict__ rowsum,
+                                           unsigned long long *__restrict__ rowmask) {
   const int lane_body = blockIdx.x * kBlock + threadIdx.x;
   const bool valid = lane_body < n;
   const int lb = valid ? lane_body : n - 1;
@@ -254,7 +256,13 @@ __device__ __forceinline__ void pairs_body(const double4 *__restrict__ xm,
     if (uniform) { ce[0] *= mu; ce[1] *= mu; ce[2] *= mu; }
     part_ce[o] = make_double4(ce[0], ce[1], ce[2], 0.0);
   }
-  if (EMIT) cnt[o] = nc;
+  if (EMIT) {
+    cnt[o] = nc;
+    if (nc > 0 && rowsum) {
+      atomicAdd(rowsum + ii, nc);
+      atomicOr(rowmask + (size_t)ii * kRowMaskWords + (blockIdx.y >> 6), 1ull << (blockIdx.y & 63));
+    }
+  }
 }
 
 // Register budget of the kernels without the close-encounter part: 80 VGPRs (six waves per SIMD
@@ -268,9 +276,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const double4 *__restrict__ xm, const double4 *__restrict__ thr, const int *__restrict__ perm,
     const double2 *__restrict__ uni, int n, int chunk, double f_in, double4 *__restrict__ part,
     double4 *__restrict__ part_ce, int *__restrict__ cnt, int *__restrict__ rowbuf, int R,
-    double c15) {
+    double c15, int *__restrict__ rowsum, unsigned long long *__restrict__ rowmask) {
   pairs_body<FORCE, EMIT, false, SPLIT>(xm, thr, perm, uni, n, chunk, f_in, part, part_ce, cnt,
-                                        rowbuf, R, c15);
+                                        rowbuf, R, c15, rowsum, rowmask);
 }
 
 template <bool EMIT, bool SPLIT>
@@ -278,9 +286,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const double4 *__restrict__ xm, const double4 *__restrict__ thr, const int *__restrict__ perm,
     const double2 *__restrict__ uni, int n, int chunk, double f_in, double4 *__restrict__ part,
     double4 *__restrict__ part_ce, int *__restrict__ cnt, int *__restrict__ rowbuf, int R,
-    double c15) {
+    double c15, int *__restrict__ rowsum, unsigned long long *__restrict__ rowmask) {
   pairs_body<true, EMIT, true, SPLIT>(xm, thr, perm, uni, n, chunk, f_in, part, part_ce, cnt,
-                                      rowbuf, R, c15);
+                                      rowbuf, R, c15, rowsum, rowmask);
 }
 
 template <bool F, bool E, bool C, bool S>
@@ -288,10 +296,12 @@ static void go(const KickArgs &a, hipStream_t st) {
   dim3 grid(nblocks(a.n), a.nchunk);
   if constexpr (C)
     hipLaunchKernelGGL((k_pairs_ce<E, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.uni, a.n,
-                       a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5);
+                       a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5,
+                       E ? a.rowsum : nullptr, E ? a.rowmask : nullptr);
   else
     hipLaunchKernelGGL((k_pairs<F, E, S>), grid, dim3(kBlock), 0, st, a.xm, a.thr, a.perm, a.uni, a.n,
-                       a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5);
+                       a.chunk, a.f_in, a.part, a.part_ce, a.cnt, a.rowbuf, a.R, 1.5,
+                       E ? a.rowsum : nullptr, E ? a.rowmask : nullptr);
 }
 
 hipError_t launch_pairs(const KickArgs &a, bool force, bool emit, bool ce, bool split,
