@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch of the binary64 pair kernel from the FETCH_SIZE / WRITE_SIZE passes
 # (calibrated with a plain copy; see profiles/k_pairs_disk32768.md), valid for the kernel source
 # whose hash is stored beside it.
-PAIR_KERNEL_TRAFFIC = {"bytes": 84928974, "source_sha256": "319824571e214a287472f068c6fa8383fce672bdf84dceacbdfa65d0b656c1d3"}
+PAIR_KERNEL_TRAFFIC = {"bytes": 84916510, "source_sha256": "e27177fb31e16e1a8b140103e76930b8ad60da34a747f9fc804dd90a7785dd06"}
 PAIR_KERNEL_SOURCES = ["paper_2604_09184_amd/csrc/pairs.hip", "paper_2604_09184_amd/csrc/device.hpp"]
 # Binary64 flop the hardware executes per pair, 64 x (ADD + MUL + TRANS + 2 FMA) from the
 # SQ_INSTS_VALU_*_F64 counters of the same profile, for the same kernel source.

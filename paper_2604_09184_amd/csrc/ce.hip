@@ -446,10 +446,11 @@ __device__ __forceinline__ int ce_contact(const double (&y)[6], double fR, const
 
 // Adaptive integration of y over the time Ltot (macro steps from H = Ltot; halved when rejected,
 // 2.5 H after acceptance at column <= 3, 1.5 H at column 4, 1.2 H at column 5: gentler growth
-// than 4 H / 2 H, which had more than half of the attempts of the hardest groups rejected). With check, every accepted step is
-// followed by a contact test and the integration stops at the first step that ends in contact: y
-// then holds that step's start, done the time covered before it and Hc its length. Returns 0
-// (covered), 1 (contact) or 2 (H halved 60 times in a row, or too many macro steps).
+// than 4 H / 2 H, which had more than half of the attempts of the hardest groups rejected). With
+// check, every accepted step is followed by a contact test and the integration stops at the
+// first step that ends in contact: y then holds that step's start, done the time covered before
+// it and Hc its length. Returns 0 (covered), 1 (contact) or 2 (H halved 60 times in a row, or too
+// many macro steps).
 template <int NL, bool COL, int PT>
 __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool check, bool alive,
                                           double fR, const CeLane &L, CeShared &sh,
