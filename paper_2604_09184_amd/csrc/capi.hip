@@ -37,7 +37,7 @@ enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_ROWSUM, B_R
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GIN, B_GSIZE,
              B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_LTHR, B_ADEG, B_AOFF,
-             B_AFILL, B_ADJ, B_LSKIP, B_ATOT, B_ETHR, B_NUM };
+             B_AFILL, B_ADJ, B_LSKIP, B_ATOT, B_ETHR, B_GSIZE2, B_GCNT2, B_GSLICE, B_NUM };
 
 }  // namespace
 
@@ -789,6 +789,14 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   lt.nl = L + 1;
   LevelAdj la{};
   int *lskip = nullptr;
+  // above kGroupsSmall bodies the deepest level's groups come from the unions of the level kick
+  // before each of its drifts (forest in labels), one flattening launch with member slices of
+  // fixed length, and the drift launch that resets the forest; the group sizes and counters
+  // alternate between two buffers (lgs, lcnt) so that the drift can clear the next pair while it
+  // reads the current one
+  const bool small = N <= kGroupsSmall;
+  int *lgs[2] = {g.gsize, nullptr}, *lcnt[2] = {g.counter, nullptr}, *lslice = nullptr;
+  int lpar = 0;
   if (L > 0) {
     double4 *lthr = (double4 *)ensure(c, B_LTHR, (size_t)L * n * sizeof(double4));
     la.deg = (int *)ensure(c, B_ADEG, (size_t)n * sizeof(int));
@@ -799,6 +807,15 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     lskip = (int *)ensure(c, B_LSKIP, (size_t)n * sizeof(int));
     if (!lthr || !la.deg || !la.off || !la.fill || !la.adj || !la.total || !lskip)
       return fail(c, NBODY_E_NOMEM, "workspace allocation failed (changeover levels)");
+    if (!small) {
+      lgs[1] = (int *)ensure(c, B_GSIZE2, (size_t)n * sizeof(int));
+      lcnt[1] = (int *)ensure(c, B_GCNT2, kGroupCounters * sizeof(int));
+      lslice = (int *)ensure(c, B_GSLICE, (size_t)n * kLevelSlice * sizeof(int));
+      if (!lgs[1] || !lcnt[1] || !lslice)
+        return fail(c, NBODY_E_NOMEM, "workspace allocation failed (changeover levels)");
+      for (int q = 0; q < 2; ++q)
+        HIPCHK(c, launch_groups_init(labels, lgs[q], N, lcnt[q], st), "level forest");
+    }
     const double cH = ((p.n1 * p.n1 * p.n1) * (p.n1 * p.n1 * p.n1)) / 9.0;
     double dtl = p.dt;
     for (int l = 1; l <= L; ++l) {
@@ -811,7 +828,6 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   // groups of the list at the current kick positions (and, with levels, its adjacency); a list
   // longer than cap is counted in stats[5]. Up to kGroupsSmall bodies the groups and their member
   // lists come from one one-workgroup launch.
-  const bool small = N <= kGroupsSmall;
   auto groups_now = [&]() -> int {
     TRY(emit_list(c, a, lpairs, cap, lcount, st, S + 5));
     if (L == 0 && small)
@@ -831,29 +847,36 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
   std::function<int(int, double)> drift_levels = [&](int l, double tau) -> int {
     if (l == L) {
       // the groups, their member lists and the mask of the bodies that drift on Kepler orbits
+      cc.step = step;
       if (small) {
         HIPCHK(c, launch_groups_small(lpairs, cap, lcount, N, labels, g.gsize, nullptr, st, X, lt.thr[L], g.in,
                                       g.gstart, g.gmem, g.groot, g.counter, la.deg, lskip), "level groups");
+        HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G,
+                                  p.m0, p.f_in, tau, kCeTol, S, cc, lt, st), "close-encounter drift");
+        HIPCHK(c, launch_drift(X, Vv, N, tau, mu, nullptr, st, lskip), "level drift");
       } else {
-        HIPCHK(c, launch_groups(lpairs, cap, lcount, N, labels, g.gsize, g.gfill, g.counter, nullptr, ublocks,
-                                st, X, lt.thr[L]), "level groups");
-        HIPCHK(c, launch_group_lists(labels, N, g.in, g.gsize, g.gstart, g.gfill, g.gmem, g.groot, g.counter,
-                                     true, st, la.deg, lskip), "group lists");
+        // the forest in labels holds the unions of the level kick just before
+        HIPCHK(c, launch_level_groups(la.deg, N, labels, lgs[lpar], g.gstart, lslice, g.groot, lcnt[lpar], st),
+               "level groups");
+        HIPCHK(c, launch_ce_drift(X, Vv, T, lslice, g.gstart, lgs[lpar], g.groot, lcnt[lpar], N / 2 + 1, p.G,
+                                  p.m0, p.f_in, tau, kCeTol, S, cc, lt, st, kLevelSlice),
+               "close-encounter drift");
+        HIPCHK(c, launch_level_drift(X, Vv, N, tau, mu, la.deg, labels, lgs[lpar], lgs[lpar ^ 1], lcnt[lpar ^ 1],
+                                     st), "level drift");
+        lpar ^= 1;
       }
-      cc.step = step;
-      HIPCHK(c, launch_ce_drift(X, Vv, T, g.gmem, g.gstart, g.gsize, g.groot, g.counter, N / 2 + 1, p.G, p.m0,
-                                p.f_in, tau, kCeTol, S, cc, lt, st), "close-encounter drift");
-      HIPCHK(c, launch_drift(X, Vv, N, tau, mu, nullptr, st, lskip), "level drift");
       return NBODY_OK;
     }
     // the closing half kick of a substep and the opening half kick of the next act at the same
-    // positions: one kick over the whole substep length
+    // positions: one kick over the whole substep length. A kick followed by a deepest-level drift
+    // also joins that drift's groups (above kGroupsSmall bodies).
     const double ts = tau / sub;
-    HIPCHK(c, launch_level_kick(X, Vv, la, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st), "level kick");
+    int *uf = (l + 1 == L && !small) ? labels : nullptr;
+    HIPCHK(c, launch_level_kick(X, Vv, la, N, lt, l + 1, p.G, p.f_in, 0.5 * ts, st, uf), "level kick");
     for (int k = 0; k < sub; ++k) {
       TRY(drift_levels(l + 1, ts));
-      HIPCHK(c, launch_level_kick(X, Vv, la, N, lt, l + 1, p.G, p.f_in, k + 1 < sub ? ts : 0.5 * ts, st),
-             "level kick");
+      HIPCHK(c, launch_level_kick(X, Vv, la, N, lt, l + 1, p.G, p.f_in, k + 1 < sub ? ts : 0.5 * ts, st,
+                                  k + 1 < sub ? uf : nullptr), "level kick");
     }
     return NBODY_OK;
   };

@@ -95,22 +95,13 @@ constexpr int kMaxMacroSteps = 20000;
 constexpr int kMaxBisections = 80;       // contact-time bisection: at most 80 halvings of a step
 constexpr double kParkRadius = 1e6;      // orbit radius of bodies merged away
 
-// x from the lane that DPP control CTRL names (within a 16-lane row), in two 32-bit moves.
-template <int CTRL>
-__device__ __forceinline__ double ce_dpp(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Largest value over the wave, uniform: DPP maxima inside each 16-lane row, then the four rows
 // through scalar registers.
 __device__ __forceinline__ double wave_max_d(double x) {
-  x = fmax(x, ce_dpp<0xB1>(x));
-  x = fmax(x, ce_dpp<0x4E>(x));
-  x = fmax(x, ce_dpp<0x141>(x));
-  x = fmax(x, ce_dpp<0x140>(x));
+  x = fmax(x, dpp_f64<0xB1>(x));
+  x = fmax(x, dpp_f64<0x4E>(x));
+  x = fmax(x, dpp_f64<0x141>(x));
+  x = fmax(x, dpp_f64<0x140>(x));
   const long long b = __double_as_longlong(x);
   double m = 0.0;
 #pragma unroll
@@ -121,23 +112,6 @@ __device__ __forceinline__ double wave_max_d(double x) {
     m = r == 0 ? q : fmax(m, q);
   }
   return m;
-}
-
-// r^-1 to a few ulp: the hardware reciprocal square root (relative error about 2^-24) refined by
-// the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3), e = 1 - r2 y^2.
-__device__ __forceinline__ double ce_rinv(double r2) {
-  const double y = __builtin_amdgcn_rsq(r2);
-  const double e = fma(-r2, y * y, 1.0);
-  return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-
-// 1/d for d in [1/2, 1] (the changeover's denominator): the hardware reciprocal refined by two
-// Newton steps x <- x + x (1 - d x), each of which squares the relative error.
-__device__ __forceinline__ double ce_recip(double d) {
-  double x = __builtin_amdgcn_rcp(d);
-  x = fma(x, fma(-d, x, 1.0), x);
-  x = fma(x, fma(-d, x, 1.0), x);
-  return x;
 }
 
 // Per-member values in ascending body order: G m, rc, 1/((1 - f_in) rc) and the contact radius
@@ -216,7 +190,7 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
   const double dy = (__shfl(z[1], p.src, 64) - z[1]) + off;
   const double dz = (__shfl(z[2], p.src, 64) - z[2]) + off;
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double ir = ce_rinv(r2);
+  const double ir = rinv_refined(r2);
   const double r = r2 * ir;
   const double f_in = L.f_in;
   double c;
@@ -224,7 +198,7 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
     const double rcij = p.rcij, isp = p.isp;
     const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
     const double omy = 1.0 - y;
-    const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
+    const double iD = recip_refined((2.0 * y * y - 2.0 * y) + 1.0);
     c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
   } else if (NL == 2) {
     // W = [1 - K_0][1 - K_1], the two levels' constants kept with the partner
@@ -235,7 +209,7 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
       const double isp = l == 0 ? p.isp : p.isp1;
       const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
       const double omy = 1.0 - y;
-      const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
+      const double iD = recip_refined((2.0 * y * y - 2.0 * y) + 1.0);
       const double omK = omy * omy * iD, dK = 2.0 * y * omy * iD * iD * isp;
       dW = dW * omK - W * dK;
       W = W * omK;
@@ -250,7 +224,7 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
       const double isp = mine ? sh.lisp[l][L.rank] : sh.lisp[l][p.q];
       const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
       const double omy = 1.0 - y;
-      const double iD = ce_recip((2.0 * y * y - 2.0 * y) + 1.0);
+      const double iD = recip_refined((2.0 * y * y - 2.0 * y) + 1.0);
       const double omK = omy * omy * iD, dK = 2.0 * y * omy * iD * iD * isp;
       dW = dW * omK - W * dK;
       W = W * omK;
@@ -266,9 +240,9 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
 
 template <int CTRL>
 __device__ __forceinline__ void ce_row_add(double &a0, double &a1, double &a2) {
-  a0 += ce_dpp<CTRL>(a0);
-  a1 += ce_dpp<CTRL>(a1);
-  a2 += ce_dpp<CTRL>(a2);
+  a0 += dpp_f64<CTRL>(a0);
+  a1 += dpp_f64<CTRL>(a1);
+  a2 += dpp_f64<CTRL>(a2);
 }
 
 // Partners of a lane kept in registers; members beyond them are read from LDS.
@@ -284,7 +258,7 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
   // the central term first: it does not depend on the partners, so its latency overlaps their
   // exchange
   const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
-  const double ir = ce_rinv(r2);
+  const double ir = rinv_refined(r2);
   const double s = -L.Gm0 * (ir * ir * ir);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (PT > 0 || L.iters == 1) {
@@ -504,14 +478,15 @@ __device__ __forceinline__ void ce_group(
     const double4 *__restrict__ thr, const int *__restrict__ gmem, const int *__restrict__ gstart,
     const int *__restrict__ gsize, const int *__restrict__ groot, double G, double m0, double f_in,
     double h, double tol, unsigned long long *__restrict__ stats, const CeCollide &col,
-    const LevelThr &lt) {
+    const LevelThr &lt, int slice) {
   const int r = groot[w];
   const int k = gsize[r];
   const int base = gstart[r];
   const double Gm0 = G * m0;
   if (k > 64) {
-    // too large for one wave: Kepler orbits only, and reported
-    for (int q = threadIdx.x; q < k; q += 64 * kCeWaves) {
+    // too large for one wave: Kepler orbits only, and reported (with member slices of fixed length
+    // the caller drifts these members itself)
+    for (int q = threadIdx.x; q < (slice ? 0 : k); q += 64 * kCeWaves) {
       const int b = gmem[base + q];
       double4 p = xm[b], u = v[b];
       kepler_advance(p.x, p.y, p.z, u.x, u.y, u.z, Gm0, h);
@@ -684,7 +659,8 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     double4 *__restrict__ xm, double4 *__restrict__ v, const double4 *__restrict__ thr,
     const int *__restrict__ gmem, const int *__restrict__ gstart, const int *__restrict__ gsize,
     const int *__restrict__ groot, int *__restrict__ counter, double G, double m0, double f_in,
-    double h, double tol, unsigned long long *__restrict__ stats, CeCollide col, LevelThr lt) {
+    double h, double tol, unsigned long long *__restrict__ stats, CeCollide col, LevelThr lt,
+    int slice) {
   __shared__ CeShared sh;
   __shared__ int next;
   const int ng = counter[0];
@@ -694,7 +670,8 @@ __global__ __launch_bounds__(64 * kCeWaves) void k_ce_drift(
     const int w = next;
     __syncthreads();
     if (w >= ng) break;
-    ce_group<NL, COL>(w, sh, xm, v, thr, gmem, gstart, gsize, groot, G, m0, f_in, h, tol, stats, col, lt);
+    ce_group<NL, COL>(w, sh, xm, v, thr, gmem, gstart, gsize, groot, G, m0, f_in, h, tol, stats, col, lt,
+                      slice);
     __syncthreads();
   }
 }
@@ -718,7 +695,7 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
                            const int *gstart, const int *gsize, const int *groot, int *counter,
                            int max_groups, double G, double m0, double f_in, double h, double tol,
                            unsigned long long *stats, const CeCollide &col, const LevelThr &lt,
-                           hipStream_t st) {
+                           hipStream_t st, int slice) {
   // resident workgroups only: the queue hands out the groups (the device count is not known here)
   if (max_groups <= 0) return hipSuccess;
   const bool col_on = col.radius != nullptr;
@@ -737,7 +714,7 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
     }                                                                                               \
     hipLaunchKernelGGL((k_ce_drift<A, B>), dim3(std::min(max_groups, resident)), dim3(64 * kCeWaves), \
                        0, st, xm, v, thr, gmem, gstart, gsize, groot, counter, G, m0, f_in, h, tol,  \
-                       stats, col, lt);                                                             \
+                       stats, col, lt, slice);                                                      \
   } while (0)
   if (lt.nl == 1) { if (col_on) NBK_CE(1, true); else NBK_CE(1, false); }
   else if (lt.nl == 2) { if (col_on) NBK_CE(2, true); else NBK_CE(2, false); }

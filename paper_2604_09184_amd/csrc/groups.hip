@@ -3,34 +3,12 @@
 // section "The hybrid symplectic integrator"). Every body is labelled with the smallest index in
 // its component.
 //
-// Lock-free union-find over the pair list: each pair joins the roots of its two bodies by hooking
-// the larger root under the smaller one with a compare-and-swap, so a parent index is never larger
-// than its child and every root is the smallest index of its set. Parent reads and path-halving
-// writes inside the union phase are device-scope atomics (another workgroup's hook must be seen);
-// the final flattening runs as its own kernel, when every hook has completed.
-//
-// Termination: parent[x] <= x at all times and a hook or a halving only lowers it, so every find
-// walks a strictly decreasing chain; a failed compare-and-swap means another thread hooked the same
-// root, which lowers it, so each pair retries at most as often as its roots are lowered.
+// Lock-free union-find over the pair list (uf_unite): each pair joins the roots of its two bodies
+// by hooking the larger root under the smaller one, so every root is the smallest index of its
+// set. The final flattening runs as its own kernel, when every hook has completed.
 #include "internal.hpp"
 
 namespace nbk {
-
-__device__ __forceinline__ int ld_parent(const int *p, int x) {
-  return __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ int find_root(int *p, int x) {
-  int px = ld_parent(p, x);
-  while (px != x) {
-    const int gx = ld_parent(p, px);
-    if (gx != px)   // path halving: point x at its grandparent (still in its set, still smaller)
-      __hip_atomic_store(p + x, gx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    x = px;
-    px = gx;
-  }
-  return x;
-}
 
 // parent[i] = i; the group sizes and fill counters zeroed (when given), the outputs and the list
 // counters zeroed (when given).
@@ -73,15 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_groups_union(const int32_t *__restri
       const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
       if (!nbd::close_exact(r2, ta.y, tb.y, ta.z, tb.z)) continue;
     }
-    int ri = find_root(parent, i), rj = find_root(parent, j);
-    while (ri != rj) {
-      const int lo = ri < rj ? ri : rj, hi = ri < rj ? rj : ri;
-      const int old = atomicCAS(parent + hi, hi, lo);
-      if (old == hi) break;
-      // hi was hooked meanwhile: continue from the roots as they are now
-      ri = find_root(parent, lo);
-      rj = find_root(parent, old);
-    }
+    uf_unite(parent, i, j);
   }
   if (bad && out) atomicAdd(out + 1, bad);
 }
@@ -224,6 +194,12 @@ hipError_t launch_groups_small(const int32_t *pairs, int64_t cap, const int64_t 
                                int *gmem, int *groot, int *counter, const int *deg, int *skip) {
   hipLaunchKernelGGL(k_groups_small, dim3(1), dim3(1024), 0, st, pairs, cap, count, n, labels, gsize,
                      (unsigned long long *)out, xm, thr, in, gstart, gmem, groot, counter, deg, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_groups_init(int *parent, int *gsize, int n, int *counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_groups_init, dim3(nblocks(n > kGroupCounters ? n : kGroupCounters)), dim3(kBlock), 0,
+                     st, parent, gsize, nullptr, n, nullptr, counter);
   return hipGetLastError();
 }
 

@@ -8,6 +8,68 @@
 
 namespace nbk {
 
+// ------------------------------------------------------------------ device helpers
+// x from the lane that DPP control CTRL names (within a 16-lane row), in two 32-bit moves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// r^-1 to a few ulp: the hardware reciprocal square root (relative error about 2^-24) refined by
+// the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3), e = 1 - r2 y^2.
+__device__ __forceinline__ double rinv_refined(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2, y * y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// 1/d for a normal d: the hardware reciprocal refined by two Newton steps x <- x + x (1 - d x),
+// each of which squares the relative error.
+__device__ __forceinline__ double recip_refined(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  x = fma(x, fma(-d, x, 1.0), x);
+  x = fma(x, fma(-d, x, 1.0), x);
+  return x;
+}
+
+// Lock-free union-find on a forest in global memory where a parent index is never larger than its
+// child (every root is the smallest index of its set). Reads, and the path-halving writes of find,
+// are device-scope atomics: a hook made by another workgroup must be seen.
+__device__ __forceinline__ int uf_parent(const int *p, int x) {
+  return __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int uf_find(int *p, int x) {
+  int px = uf_parent(p, x);
+  while (px != x) {
+    const int gx = uf_parent(p, px);
+    if (gx != px)   // path halving: point x at its grandparent (still in its set, still smaller)
+      __hip_atomic_store(p + x, gx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = px;
+    px = gx;
+  }
+  return x;
+}
+
+// Joins the sets of i and j by hooking the larger root under the smaller with a compare-and-swap.
+// Termination: parent[x] <= x always and a hook or a halving only lowers it, so every find walks a
+// strictly decreasing chain; a failed compare-and-swap means another thread hooked the same root,
+// which lowers it, so a pair retries at most as often as its roots are lowered.
+__device__ __forceinline__ void uf_unite(int *p, int i, int j) {
+  int ri = uf_find(p, i), rj = uf_find(p, j);
+  while (ri != rj) {
+    const int lo = ri < rj ? ri : rj, hi = ri < rj ? rj : ri;
+    const int old = atomicCAS(p + hi, hi, lo);
+    if (old == hi) break;
+    // hi was hooked meanwhile: continue from the roots as they are now
+    ri = uf_find(p, lo);
+    rj = uf_find(p, old);
+  }
+}
+
 struct KickArgs {
   const double4 *xm;
   const double4 *thr;
@@ -104,13 +166,15 @@ struct LevelThr {
 };
 
 // counter [kGroupCounters]: [0] groups, [1] member slots allocated, [2] queue of the drift kernel
-// (zeroed by launch_groups or launch_group_lists).
+// (zeroed by launch_groups, launch_group_lists or launch_level_drift).
+// slice > 0: member lists of launch_level_groups (slices of fixed length); the members of a group
+// above 64 bodies are then not drifted here (launch_level_drift drifts them).
 constexpr int kGroupCounters = 8;
 hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const int *gmem,
                            const int *gstart, const int *gsize, const int *groot, int *counter,
                            int max_groups, double G, double m0, double f_in, double h, double tol,
                            unsigned long long *stats, const CeCollide &col, const LevelThr &lt,
-                           hipStream_t st);
+                           hipStream_t st, int slice = 0);
 
 // levels.hip: symmetric adjacency of a pair list (rows sorted by neighbour index), the level kicks
 // over it and the masks of the level drifts.
@@ -120,8 +184,25 @@ struct LevelAdj {
 };
 hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
                             const LevelAdj &g, hipStream_t st);
+// With parent given, the kick also joins (uf_unite on parent, which must hold a forest) every
+// listed pair that is close under level `level`'s exact predicate at the kick's positions: the
+// groups of the deepest level's drift that follows.
 hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int n, const LevelThr &lt,
-                             int level, double G, double f_in, double h, hipStream_t st);
+                             int level, double G, double f_in, double h, hipStream_t st,
+                             int *parent = nullptr);
+// Deepest-level groups from the forest of the kick's unions, for n above kGroupsSmall: every body
+// with listed partners is flattened onto its root (parent becomes the labels) and counted in
+// gsize; member slices of kLevelSlice slots at gstart[r] = r kLevelSlice (gmem [n kLevelSlice]);
+// the roots of groups (two or more bodies) into groot, their number into counter[0].
+constexpr int kLevelSlice = 64;
+hipError_t launch_level_groups(const int *deg, int n, int *parent, int *gsize, int *gstart, int *gmem,
+                               int *groot, int *counter, hipStream_t st);
+// Kepler drift over dt of the bodies with listed partners outside the groups of 2..64 bodies
+// (gsize of their label), then the forest reset for the next deepest-level drift: parent[i] = i,
+// gsize_next and counter_next zeroed.
+hipError_t launch_level_drift(double4 *xm, double4 *v, int n, double dt, double mu, const int *deg,
+                              int *parent, const int *gsize, int *gsize_next, int *counter_next,
+                              hipStream_t st);
 // skip[i] = 1 unless body i has a listed partner (deg > 0) and is outside the groups (in == 0);
 // with in null: skip[i] = (deg[i] > 0).
 hipError_t launch_level_mask(const int *deg, const int *in, int n, int *skip, hipStream_t st);
@@ -144,6 +225,8 @@ hipError_t launch_groups(const int32_t *pairs, int64_t cap, const int64_t *count
                          int32_t *labels, int *gsize, int *gfill, int *counter, int64_t *out,
                          int union_blocks, hipStream_t st, const double4 *xm = nullptr,
                          const double4 *thr = nullptr);
+// parent[i] = i, gsize zeroed and counter zeroed (a forest of singletons for launch_level_kick).
+hipError_t launch_groups_init(int *parent, int *gsize, int n, int *counter, hipStream_t st);
 // The same for n <= kGroupsSmall in one workgroup and one launch; with in non-null also the member
 // lists of launch_group_lists (in, gstart, gmem, groot, counter). out (may be null) is written,
 // not accumulated.

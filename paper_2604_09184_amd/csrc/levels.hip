@@ -6,6 +6,7 @@
 // W_l = prod_{i <= l} [1 - K_i]. This file holds the kick and its bookkeeping; the orchestration
 // is on the host and the deepest level runs the close-encounter integrator.
 #include "internal.hpp"
+#include "kepler_core.hpp"
 
 namespace nbk {
 
@@ -102,69 +103,133 @@ __global__ __launch_bounds__(kBlock) void k_adj_sort(const int *__restrict__ off
 }
 
 // ------------------------------------------------------------------ level kick
-// Changeover K and dK/dr for a pair at distance r with critical radius rcij.
+// Changeover K and dK/dr for a pair at distance r with critical radius rcij, from refined hardware
+// reciprocals (a few ulp; no division): y = (r - f_in rcij)/((1 - f_in) rcij) clamped to [0, 1],
+// D = 2y^2 - 2y + 1 in [1/2, 1], K = y^2/D, dK/dr = 2y(1 - y)/(D^2 (1 - f_in) rcij).
 __device__ __forceinline__ void level_K(double r, double rcij, double f_in, double &K, double &dK) {
-  const double span = (1.0 - f_in) * rcij;
-  double y = (r - f_in * rcij) / span;
-  y = fmin(fmax(y, 0.0), 1.0);
-  const double D = 2.0 * y * y - 2.0 * y + 1.0;
-  K = y * y / D;
-  dK = 2.0 * y * (1.0 - y) / (D * D) / span;
+  const double isp = recip_refined((1.0 - f_in) * rcij);
+  const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
+  const double iD = recip_refined((2.0 * y * y - 2.0 * y) + 1.0);
+  K = y * y * iD;
+  dK = 2.0 * y * (1.0 - y) * (iD * iD) * isp;
 }
 
+// Lanes per body row of the level kick: one 16-lane DPP row, four body rows per wave (the rows of
+// the close-pair adjacency hold about 20 entries on the planetesimal disks).
+constexpr int kKickLanes = 16;
+
 // v_i += h sum over the row's neighbours j (in ascending order) of the terms
-// G m_j (V/r^3 - V'(r)/r^2) d_ij, V = W_{level-1} K_level: one wave per row, lane l computing the
-// terms l, l + 64, ... of the sorted row, then a butterfly of commutative additions (the same bits
-// on every lane).
+// G m_j (V/r^3 - V'(r)/r^2) d_ij, V = W_{level-1} K_level: lane l of the body's 16-lane row
+// computes the terms l, l + 16, ..., then a butterfly of commutative additions inside the row.
+// UNION: the pairs (i < j) close under level `level`'s exact predicate at these positions are also
+// joined in the forest parent.
+template <bool UNION>
 __global__ __launch_bounds__(kBlock) void k_level_kick(const double4 *__restrict__ xm,
                                                        const int *__restrict__ off,
                                                        const int *__restrict__ deg,
                                                        const int *__restrict__ adj, LevelThr lt,
                                                        int level, double G, double f_in, int n,
-                                                       double h, double4 *__restrict__ v) {
-  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+                                                       double h, double4 *__restrict__ v,
+                                                       int *parent) {
+  const int i = blockIdx.x * (kBlock / kKickLanes) + (int)(threadIdx.x / kKickLanes);
+  const int lane = threadIdx.x & (kKickLanes - 1);
+  // both exits are uniform over a 16-lane row, so the row's DPP exchanges below see only its own
+  // active lanes
   if (i >= n) return;
   const int d = deg[i];
   if (d == 0) return;
   const int *row = adj + off[i];
   const double4 p = xm[i];
+  const double4 ti = lt.thr[level][i];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int q = lane; q < d; q += 64) {
+  for (int q = lane; q < d; q += kKickLanes) {
     const int j = row[q];
     const double4 pj = xm[j];
     const double dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    double W = 1.0, dW = 0.0;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (UNION && j > i) {
+      const double4 tj = lt.thr[level][j];
+      if (nbd::close_exact(r2, ti.y, tj.y, ti.z, tj.z)) uf_unite(parent, i, j);
+    }
+    const double ir = rinv_refined(r2);
+    const double r = r2 * ir;
+    double W = 1.0, dW = 0.0, K, dK;
     for (int l = 0; l < level; ++l) {
-      const double rcij = fmax(lt.thr[l][i].x, lt.thr[l][j].x);
-      double K, dK;
-      level_K(r, rcij, f_in, K, dK);
+      level_K(r, fmax(lt.thr[l][i].x, lt.thr[l][j].x), f_in, K, dK);
       dW = dW * (1.0 - K) - W * dK;
       W = W * (1.0 - K);
     }
-    double K, dK;
-    level_K(r, fmax(lt.thr[level][i].x, lt.thr[level][j].x), f_in, K, dK);
+    level_K(r, fmax(ti.x, lt.thr[level][j].x), f_in, K, dK);
     const double V = W * K, dV = dW * K + W * dK;
-    const double c = G * pj.w * (V / (r2 * r) - dV / r2);
-    a0 += c * dx;
-    a1 += c * dy;
-    a2 += c * dz;
+    const double c = (G * pj.w) * (ir * ir) * (V * ir - dV);
+    a0 = fma(c, dx, a0);
+    a1 = fma(c, dy, a1);
+    a2 = fma(c, dz, a2);
   }
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    a0 += __shfl_xor(a0, o, 64);
-    a1 += __shfl_xor(a1, o, 64);
-    a2 += __shfl_xor(a2, o, 64);
-  }
+  a0 += dpp_f64<0xB1>(a0);    // quad_perm [1, 0, 3, 2]: lane xor 1
+  a1 += dpp_f64<0xB1>(a1);
+  a2 += dpp_f64<0xB1>(a2);
+  a0 += dpp_f64<0x4E>(a0);    // quad_perm [2, 3, 0, 1]: lane xor 2
+  a1 += dpp_f64<0x4E>(a1);
+  a2 += dpp_f64<0x4E>(a2);
+  a0 += dpp_f64<0x141>(a0);   // half-row mirror
+  a1 += dpp_f64<0x141>(a1);
+  a2 += dpp_f64<0x141>(a2);
+  a0 += dpp_f64<0x140>(a0);   // row mirror
+  a1 += dpp_f64<0x140>(a1);
+  a2 += dpp_f64<0x140>(a2);
   if (lane == 0) {
     double4 u = v[i];
-    u.x += h * a0;
-    u.y += h * a1;
-    u.z += h * a2;
+    u.x = fma(h, a0, u.x);
+    u.y = fma(h, a1, u.y);
+    u.z = fma(h, a2, u.z);
     v[i] = u;
   }
+}
+
+// ------------------------------------------------------------------ deepest-level groups
+// Every body with listed partners walks to its root (the unions have all completed; a value read
+// while another thread flattens is the root or an ancestor on the way to it), takes it as its
+// label and a slot in its root's slice; the second member to arrive registers the root as a group.
+__global__ __launch_bounds__(kBlock) void k_level_groups(const int *__restrict__ deg, int n,
+                                                         int *parent, int *__restrict__ gsize,
+                                                         int *__restrict__ gstart,
+                                                         int *__restrict__ gmem,
+                                                         int *__restrict__ groot,
+                                                         int *__restrict__ counter) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n || deg[i] == 0) return;
+  int r = i;
+  for (int pr = parent[r]; pr != r; pr = parent[r]) r = pr;
+  parent[i] = r;
+  const int pos = atomicAdd(gsize + r, 1);
+  if (pos < kLevelSlice) gmem[(size_t)r * kLevelSlice + pos] = i;
+  if (pos == 1) {
+    gstart[r] = r * kLevelSlice;
+    groot[atomicAdd(counter, 1)] = r;
+  }
+}
+
+// Kepler drift of the bodies with listed partners that the close-encounter drift did not move
+// (no group, or a group above 64 bodies), then the reset for the next deepest-level drift.
+__global__ __launch_bounds__(kBlock) void k_level_drift(double4 *__restrict__ xm,
+                                                        double4 *__restrict__ v, int n, double dt,
+                                                        double mu, const int *__restrict__ deg,
+                                                        int *__restrict__ parent,
+                                                        const int *__restrict__ gsize,
+                                                        int *__restrict__ gsize_next,
+                                                        int *__restrict__ counter_next) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < kGroupCounters) counter_next[i] = 0;
+  if (i >= n) return;
+  const int k = gsize[parent[i]];   // read by this thread only, before its reset
+  parent[i] = i;
+  gsize_next[i] = 0;
+  if (deg[i] == 0 || (k >= 2 && k <= 64)) return;
+  double4 p = xm[i], q = v[i];
+  nbd::kepler_advance(p.x, p.y, p.z, q.x, q.y, q.z, mu, dt);
+  xm[i] = p;
+  v[i] = q;
 }
 
 __global__ __launch_bounds__(kBlock) void k_level_mask(const int *__restrict__ deg,
@@ -206,9 +271,29 @@ hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *co
 }
 
 hipError_t launch_level_kick(const double4 *xm, double4 *v, const LevelAdj &g, int n, const LevelThr &lt,
-                             int level, double G, double f_in, double h, hipStream_t st) {
-  hipLaunchKernelGGL(k_level_kick, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st, xm,
-                     g.off, g.deg, g.adj, lt, level, G, f_in, n, h, v);
+                             int level, double G, double f_in, double h, hipStream_t st, int *parent) {
+  const dim3 grid((n + kBlock / kKickLanes - 1) / (kBlock / kKickLanes));
+  if (parent)
+    hipLaunchKernelGGL(k_level_kick<true>, grid, dim3(kBlock), 0, st, xm, g.off, g.deg, g.adj, lt, level, G,
+                       f_in, n, h, v, parent);
+  else
+    hipLaunchKernelGGL(k_level_kick<false>, grid, dim3(kBlock), 0, st, xm, g.off, g.deg, g.adj, lt, level, G,
+                       f_in, n, h, v, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_groups(const int *deg, int n, int *parent, int *gsize, int *gstart, int *gmem,
+                               int *groot, int *counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_groups, dim3(nblocks(n)), dim3(kBlock), 0, st, deg, n, parent, gsize, gstart,
+                     gmem, groot, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_drift(double4 *xm, double4 *v, int n, double dt, double mu, const int *deg,
+                              int *parent, const int *gsize, int *gsize_next, int *counter_next,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_level_drift, dim3(nblocks(n > kGroupCounters ? n : kGroupCounters)), dim3(kBlock), 0,
+                     st, xm, v, n, dt, mu, deg, parent, gsize, gsize_next, counter_next);
   return hipGetLastError();
 }
 

@@ -151,3 +151,50 @@ def test_levels_with_mergers_match_oracle(ctx):
     ex, ev = rel_err(X[torch.tensor(live, device=DEV)], V[torch.tensor(live, device=DEV)], ox[live], ov[live])
     say(f"  state rel err x {ex:.2e} v {ev:.2e}")
     assert ex < 1e-10 and ev < 1e-10
+
+
+@pytest.mark.parametrize("L,s,steps", [(1, 4, 3), (2, 2, 2)])
+def test_levels_above_one_workgroup_match_oracle(ctx, L, s, steps):
+    """Above 4096 bodies the deepest level's groups are built by several launches (the unions inside
+    the level kick, a flattening launch with member slices, the drift that resets the forest, with
+    two alternating size and counter buffers): the 32768 disk's recipe at 8192 bodies against the
+    oracle's recursion."""
+    say(f"levels L={L} s={s} disk8192 x{steps}")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk32768", n=8192)
+    X, V = dev_state(d)
+    thr = ctx.rcrit(X, V)
+    stats = ctx.step_hybrid(X, V, steps, thr=thr, levels=L, substeps=s, margin=0.5)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov, om, oR, st, ostats, _, _ = oracle.step_levels(d["x"], d["v"], d["m"], p, steps, L, s, thr=othr,
+                                                          margin=0.5)
+    ex, ev = rel_err(X, V, ox, ov)
+    say(f"  {stats}; oracle {ostats}; state rel err x {ex:.2e} v {ev:.2e}")
+    assert st == 0 and stats["unfinished"] == 0 and stats["too_large"] == 0
+    assert (stats["groups"], stats["largest"], stats["bodies"]) == ostats
+    assert ex < 1e-10 and ev < 1e-10
+
+
+def test_levels_above_one_workgroup_with_mergers_match_oracle(ctx):
+    """Mergers at the deepest level built by several launches (8192 bodies, one level, s = 4,
+    f = 300, 4 steps): the same mergers as the oracle, masses bit-exact, states 1e-10."""
+    say("levels L=1 s=4 with mergers f=300 disk8192 x4")
+    p = diskgen.PARAMS
+    d = diskgen.workload("disk32768", n=8192)
+    X, V = dev_state(d)
+    thr = ctx.rcrit(X, V)
+    R = torch.tensor(d["radius"], device=DEV)
+    out = ctx.step_hybrid(X, V, 4, thr=thr, levels=1, substeps=4, radius=R, f=300.0, margin=0.5)
+    othr = oracle.thresholds(d["x"], d["v"], d["m"], p)
+    ox, ov, om, oR, st, ostats, omg, omt = oracle.step_levels(d["x"], d["v"], d["m"], p, 4, 1, 4, thr=othr,
+                                                              R=d["radius"], f=300.0, margin=0.5)
+    srt = lambda mg: np.asarray(mg).reshape(-1, 3)[np.lexsort(np.asarray(mg).reshape(-1, 3).T[::-1])]
+    say(f"  gpu {out['mergers']} mergers; oracle {len(omg)}")
+    assert st == 0 and out["unfinished"] == 0
+    assert out["mergers"] == len(omg) >= 10
+    np.testing.assert_array_equal(srt(out["merges"]), srt(omg))
+    np.testing.assert_array_equal(X.cpu().numpy()[:, 3], om)
+    live = om > 0
+    ex, ev = rel_err(X[torch.tensor(live, device=DEV)], V[torch.tensor(live, device=DEV)], ox[live], ov[live])
+    say(f"  state rel err x {ex:.2e} v {ev:.2e}")
+    assert ex < 1e-10 and ev < 1e-10
