@@ -6,7 +6,7 @@
 //   dv_i/dt = -G m0 x_i/|x_i|^3 + G sum_{j in group, j != i} m_j ((1 - K)/r^3 + K'(r)/r^2) d_ij,
 // d_ij = x_j - x_i: minus the gradient of the [1 - K] part of the pair potential, which vanishes
 // for r >= rc_ij. They are integrated with the Gragg-Bulirsch-Stoer method: modified-midpoint
-// sweeps with 2, 4, ..., 16 substeps over a macro step H, extrapolated to zero substep length as a
+// sweeps with 2, 4, ..., 10 substeps over a macro step H, extrapolated to zero substep length as a
 // polynomial in (H/n)^2 (Aitken-Neville); a macro step is accepted when the last two extrapolants
 // agree to the tolerance relative to the group's largest position and velocity, and halved
 // otherwise. With intermediate changeover levels the [1 - K] factor becomes the product of the
@@ -78,11 +78,19 @@ __global__ __launch_bounds__(kBlock) void k_gfill(const int *__restrict__ label,
 
 // ------------------------------------------------------------------ integrator
 // Work layout. A group of k <= 64 bodies is integrated by one workgroup of kCeWaves = 4 waves.
-// The eight modified-midpoint sweeps of a macro step (n = 2, 4, ..., 16 substeps) are independent
-// of one another, so wave w runs the sweeps n = 2w + 2 and n = 16 - 2w: 20 evaluations of the
-// right-hand side per wave, against 80 for all eight in a row. Their end values meet in LDS, and
-// every wave then forms the same extrapolation tableau, takes the same decision and updates the
-// same state, so the waves stay in step without further exchange.
+// A macro step extrapolates kCols = 5 modified-midpoint sweeps (n = 2, 4, ..., 10 substeps; a
+// sweep costs n evaluations of the right-hand side after the f(y) it starts from, plus one for
+// the smoothing). The sweeps are independent of one another, so waves 0, 1 and 3 run the sweeps
+// n = 10, 8 and 4 and wave 2 the sweeps n = 6 and 2 (f(y) shared): 11, 9, 9 and 5 evaluations, 11
+// on the longest path against 31 for all five in a row. Their end values meet in LDS, and every
+// wave then forms the same extrapolation tableau, takes the same decision and updates the same
+// state, so the waves stay in step without further exchange.
+//
+// Five columns rather than eight (n up to 16, 19 evaluations on the longest path with the same
+// pairing): the extrapolation order is lower, so a macro step is shorter and more of them are
+// needed, but each costs 11 instead of 19 evaluations, and the drift's length is that of its
+// slowest group's chain of macro steps. On the 2048- and 32768-body disks the slowest group then
+// takes 20-25 % more macro steps for a 40 % cheaper step.
 //
 // Within a wave, body slot s (0 <= s < k) sits on the P lanes s P + r, r = 0 .. P - 1, with
 // P = min(kp, 64/kp) and kp the power of two at or above k: replica r sums the pair terms of every
@@ -91,6 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_gfill(const int *__restrict__ label,
 // of two equal-sized partial sums in either order, so every replica ends with the same bits. A group
 // of up to 8 bodies thus needs one pair term per replica and log2(kp) butterfly stages.
 constexpr int kCeWaves = 4;
+constexpr int kCols = 5;
 constexpr int kMaxMacroSteps = 20000;
 constexpr int kMaxBisections = 80;       // contact-time bisection: at most 80 halvings of a step
 constexpr double kParkRadius = 1e6;      // orbit radius of bodies merged away
@@ -124,7 +133,7 @@ struct CeMember {
 // slot of each member rank, the member values, masses, radii and body indices by rank, and the
 // critical radii rc_l and 1/((1 - f_in) rc_l) of the changeover levels by rank.
 struct CeShared {
-  double est[2][8][6][64];
+  double est[2][kCols][6][64];
   CeMember mem[64];
   double mass[64], rad[64];
   double lrc[kMaxLevels][64], lisp[kMaxLevels][64];
@@ -288,18 +297,19 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
   f[5] = alive ? s * z[2] + a2 : 0.0;
 }
 
-// Modified-midpoint sweep of ns substeps over H from y: the end value (z_n + z_{n-1} + hs f(z_n))/2.
+// Modified-midpoint sweep of ns substeps over H from y, with f0 = f(y): the end value
+// (z_n + z_{n-1} + hs f(z_n))/2.
 template <int NL, int PT>
-__device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns, const CeLane &L,
-                                         const CeShared &sh, const CePartner (&pr)[kCeRegPartners],
-                                         bool alive, double (&est)[6]) {
+__device__ __forceinline__ void ce_sweep(const double (&y)[6], const double (&f0)[6], double H, int ns,
+                                         const CeLane &L, const CeShared &sh,
+                                         const CePartner (&pr)[kCeRegPartners], bool alive,
+                                         double (&est)[6]) {
   const double hs = H / ns;
   double zm[6], zc[6], f[6];
-  ce_rhs<NL, PT>(y, L, sh, pr, alive, f);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
-    zc[i] = y[i] + hs * f[i];
+    zc[i] = y[i] + hs * f0[i];
   }
   // z_{m+1} = z_{m-1} + 2 hs f(z_m), m = 1 .. ns - 1, two steps per iteration so that the two state
   // arrays trade roles without copies (ns is even: one step is left over at the end)
@@ -321,14 +331,14 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], double H, int ns,
   for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zm[i] + zc[i] + hs * f[i]);
 }
 
-// Aitken-Neville over the eight sweeps (substep counts 2c + 2) of one component: T[c][0] = e[c],
-// T[c][j] = T[c][j-1] + (T[c][j-1] - T[c-1][j-1]) / ((n_c/n_{c-j})^2 - 1). Returns T[want][want]
-// and, in err[c], max(err[c], |T[c][c] - T[c][c-1]| iscale) for c >= 2.
-__device__ __forceinline__ double ce_tableau(const double (&e)[8], double iscale, int want,
-                                             double (&err)[8]) {
-  double prev[8], cur[8], out = e[0];
+// Aitken-Neville over the kCols sweeps (substep counts 2c + 2) of one component:
+// T[c][0] = e[c], T[c][j] = T[c][j-1] + (T[c][j-1] - T[c-1][j-1]) / ((n_c/n_{c-j})^2 - 1).
+// Returns T[want][want] and, in err[c], max(err[c], |T[c][c] - T[c][c-1]| iscale) for c >= 2.
+__device__ __forceinline__ double ce_tableau(const double (&e)[kCols], double iscale, int want,
+                                             double (&err)[kCols]) {
+  double prev[kCols], cur[kCols], out = e[0];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < kCols; ++c) {
     cur[0] = e[c];
 #pragma unroll
     for (int j = 1; j <= c; ++j) {
@@ -354,35 +364,41 @@ __device__ __forceinline__ int ce_attempt(const double (&y)[6], double H, bool a
   const double sx = wave_max_d(live ? fmax(fabs(y[0]), fmax(fabs(y[1]), fabs(y[2]))) : 0.0);
   const double sv = wave_max_d(live ? fmax(fabs(y[3]), fmax(fabs(y[4]), fabs(y[5]))) : 0.0);
   const double isx = 1.0 / sx, isv = 1.0 / sv;
+  // f(y) starts every sweep of the wave: evaluated once
+  double f0[6];
+  ce_rhs<NL, PT>(y, L, sh, pr, alive, f0);
+  // the wave's columns: kCols - 1 - w, and column 0 for wave 2 (wave-uniform)
+  static_assert(kCols == 5 && kCeWaves == 4, "the column split below is for 5 columns on 4 waves");
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc) {
-    const int c = cc == 0 ? L.wv : 7 - L.wv;
+    const int c = cc == 0 ? kCols - 1 - L.wv : (L.wv == 2 ? 0 : -1);
+    if (c < 0) continue;
     double est[6];
-    ce_sweep<NL, PT>(y, H, 2 * c + 2, L, sh, pr, alive, est);
+    ce_sweep<NL, PT>(y, f0, H, 2 * c + 2, L, sh, pr, alive, est);
     if (L.rep == 0)
 #pragma unroll
       for (int i = 0; i < 6; ++i) sh.est[buf][c][i][L.slot] = est[i];
   }
   __syncthreads();
   // tableau of every component; the first pass finds the accepted column
-  double err[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double err[kCols] = {};
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    double e[8];
+    double e[kCols];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) e[c] = sh.est[buf][c][i][L.slot];
+    for (int c = 0; c < kCols; ++c) e[c] = sh.est[buf][c][i][L.slot];
     (void)ce_tableau(e, i < 3 ? isx : isv, -1, err);
   }
   int accepted = -1;
 #pragma unroll
-  for (int c = 2; c < 8; ++c)
+  for (int c = 2; c < kCols; ++c)
     if (accepted < 0 && __ballot(live && !(err[c] <= L.tol)) == 0) accepted = c;
   if (accepted >= 0) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      double e[8], dummy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      double e[kCols], dummy[kCols] = {};
 #pragma unroll
-      for (int c = 0; c < 8; ++c) e[c] = sh.est[buf][c][i][L.slot];
+      for (int c = 0; c < kCols; ++c) e[c] = sh.est[buf][c][i][L.slot];
       y1[i] = ce_tableau(e, 1.0, accepted, dummy);
     }
   }
@@ -419,8 +435,7 @@ __device__ __forceinline__ int ce_contact(const double (&y)[6], double fR, const
 }
 
 // Adaptive integration of y over the time Ltot (macro steps from H = Ltot; halved when rejected,
-// 2.5 H after acceptance at column <= 3, 1.5 H at column 4, 1.2 H at column 5: gentler growth
-// than 4 H / 2 H, which had more than half of the attempts of the hardest groups rejected). With
+// 2.5 H after acceptance at column <= 2, 1.5 H at column 3, 1.2 H at column 4). With
 // check, every accepted step is followed by a contact test and the integration stops at the
 // first step that ends in contact: y then holds that step's start, done the time covered before
 // it and Hc its length. Returns 0 (covered), 1 (contact) or 2 (H halved 60 times in a row, or too
@@ -452,9 +467,9 @@ __device__ __forceinline__ int ce_advance(double (&y)[6], double Ltot, bool chec
     for (int i = 0; i < 6; ++i) y[i] = y1[i];
     if (t + H == t) break;   // the remaining interval is below the resolution of t
     t = t + H;
-    if (c <= 3) H = H * 2.5;
-    else if (c == 4) H = H * 1.5;
-    else if (c == 5) H = H * 1.2;
+    if (c <= 2) H = H * 2.5;
+    else if (c == 3) H = H * 1.5;
+    else H = H * 1.2;
   }
   return 0;
 }
