@@ -198,3 +198,38 @@ def test_levels_above_one_workgroup_with_mergers_match_oracle(ctx):
     ex, ev = rel_err(X[torch.tensor(live, device=DEV)], V[torch.tensor(live, device=DEV)], ox[live], ov[live])
     say(f"  state rel err x {ex:.2e} v {ev:.2e}")
     assert ex < 1e-10 and ev < 1e-10
+
+
+def test_levels_above_one_workgroup_oversized_group(nb, ctx):
+    """A 300-body clump in an 8192-body disk stays one group above 64 bodies at the deepest level
+    (one level, s = 2): reported, and its members drift on Kepler orbits, by the level drift of the
+    several-launch path. Against the plain step from the same state: the members move as a Kepler
+    drift does (left in place or drifted twice they would be ~0.1 AU off), and the bodies far from
+    the clump with no close partner at the step's start drift at level 0 as in the plain step;
+    their last kick feels the neighbours whose close encounters the levels integrate (measured
+    1e-18 in x and 1.6e-13 in v relative; bars 1e-14 and 1e-11)."""
+    say("levels L=1 s=2 disk8192 with a 300-body clump")
+    d = diskgen.workload("disk2048", n=8192)
+    rng = np.random.default_rng(11)
+    c0 = d["x"][0].copy()
+    d["x"][:300] = c0 + 0.004 * rng.standard_normal((300, 3))
+    d["v"][:300] = d["v"][0] + 1e-3 * rng.standard_normal((300, 3))
+    X, V = dev_state(d)
+    thr = ctx.rcrit(X, V)
+    pairs, cnt = ctx.encounters(X, thr)
+    listed = np.zeros(8192, dtype=bool)
+    listed[pairs[:cnt].cpu().numpy().ravel()] = True
+    Xp, Vp = X.clone(), V.clone()
+    ctx.step(Xp, Vp, 1, thr=thr)
+    with pytest.warns(nb.NBodyWarning, match="Kepler orbits only"):
+        stats = ctx.step_hybrid(X, V, 1, thr=thr, levels=1, substeps=2, margin=0.0)
+    x, v = X.cpu().numpy(), V.cpu().numpy()
+    xp, vp = Xp.cpu().numpy(), Vp.cpu().numpy()
+    dxm = np.abs(x[:300, :3] - xp[:300, :3]).max()
+    far = (np.linalg.norm(d["x"] - c0, axis=1) > 0.5) & ~listed
+    evf = (np.abs(v[far, :3] - vp[far, :3]).max(1) / np.linalg.norm(vp[far, :3], axis=1)).max()
+    exf = (np.abs(x[far, :3] - xp[far, :3]).max(1) / np.linalg.norm(xp[far, :3], axis=1)).max()
+    say(f"  {stats}; clump |dx| {dxm:.2e} AU; {far.sum()} far free bodies rel x {exf:.2e} v {evf:.2e}")
+    assert stats["too_large"] >= 1 and np.isfinite(x).all() and np.isfinite(v).all()
+    assert dxm < 1e-3
+    assert far.sum() > 4000 and exf < 1e-14 and evf < 1e-11
