@@ -369,17 +369,20 @@ __device__ __forceinline__ void emit_chunk(const double4 *__restrict__ xm,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
-                                                 const double4 *__restrict__ thr, int n, int S,
-                                                 int chunk, const int *__restrict__ cnt,
-                                                 const int *__restrict__ rowbuf, int R,
-                                                 const int64_t *__restrict__ rowtot,
-                                                 const int64_t *__restrict__ boff,
-                                                 int32_t *__restrict__ pairs, int64_t cap,
-                                                 unsigned long long *__restrict__ rowmask) {
-  __shared__ int64_t lds[kBlock];
+// One wave per workgroup, 64 rows: the row offsets come per kBlock rows (boff), so a wave adds
+// the totals of the rows before its own within that block, then its own exclusive scan.
+__global__ __launch_bounds__(64) void k_emit(const double4 *__restrict__ xm,
+                                             const double4 *__restrict__ thr, int n, int S,
+                                             int chunk, const int *__restrict__ cnt,
+                                             const int *__restrict__ rowbuf, int R,
+                                             const int64_t *__restrict__ rowtot,
+                                             const int64_t *__restrict__ boff,
+                                             int32_t *__restrict__ pairs, int64_t cap,
+                                             unsigned long long *__restrict__ rowmask) {
+  constexpr int kQuarters = kBlock / 64;
   const int t = threadIdx.x;
-  const int i = blockIdx.x * kBlock + t;
+  const int i = blockIdx.x * 64 + t;
+  const int blk = blockIdx.x / kQuarters, q = blockIdx.x % kQuarters;
   const int64_t mine = i < n ? rowtot[i] : 0;
   // the chunks with partners, from the pair kernel's mask (read and cleared) when it kept one
   unsigned long long m[kRowMaskWords] = {0, 0, 0, 0};
@@ -388,23 +391,66 @@ __global__ __launch_bounds__(kBlock) void k_emit(const double4 *__restrict__ xm,
       m[w] = rowmask[(size_t)i * kRowMaskWords + w];
       if (m[w]) rowmask[(size_t)i * kRowMaskWords + w] = 0;
     }
-  lds[t] = mine;
-  __syncthreads();
-  for (int o = 1; o < kBlock; o <<= 1) {
-    int64_t add = t >= o ? lds[t - o] : 0;
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
+  // rows of the block before this wave's (all below n: only the last block is partial)
+  int64_t before = 0;
+  for (int qq = 0; qq < q; ++qq) before += rowtot[(size_t)blk * kBlock + qq * 64 + t];
+  int64_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t up = __shfl_up(incl, o, 64);
+    if (t >= o) incl += up;
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
   if (i >= n || mine == 0) return;
-  int64_t off = boff[blockIdx.x] + lds[t] - mine;
+  int64_t off = boff[blk] + before + incl - mine;
   if (rowmask) {
-    for (int w = 0; w < kRowMaskWords; ++w)
-      while (m[w] && off < cap) {
-        const int s = 64 * w + __builtin_ctzll(m[w]);
-        m[w] &= m[w] - 1;
-        emit_chunk(xm, thr, n, chunk, rowbuf, R, i, s, cnt[(size_t)s * n + i], pairs, cap, off);
+    // up to kBatch masked chunks at a time: their counts, then the first kSlots partners of each,
+    // are loaded before any of them is stored, so that a row waits for a few memory round trips
+    // rather than one per chunk and per partner; the stores keep chunk and slot order
+    constexpr int kBatch = 8, kSlots = 4;
+    static_assert(kRowMaskWords == 4, "the word selection below");
+    int w = 0;
+    unsigned long long cur = m[0];
+    while (off < cap) {
+      int sidx[kBatch], c[kBatch], pj[kBatch][kSlots];
+      int nb = 0;
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        while (cur == 0 && w < kRowMaskWords - 1) {
+          ++w;
+          cur = w == 1 ? m[1] : w == 2 ? m[2] : m[3];
+        }
+        sidx[b] = 0;
+        if (cur != 0) {
+          sidx[b] = 64 * w + __builtin_ctzll(cur);
+          cur &= cur - 1;
+          nb = b + 1;
+        }
       }
+      if (nb == 0) break;
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) c[b] = b < nb ? cnt[(size_t)sidx[b] * n + i] : 0;
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+          pj[b][k] = (k < c[b] && c[b] <= R) ? rowbuf[((size_t)sidx[b] * R + k) * n + i] : 0;
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (b >= nb) break;
+        if (c[b] <= kSlots && c[b] <= R) {
+#pragma unroll
+          for (int k = 0; k < kSlots; ++k)
+            if (k < c[b] && off < cap) {
+              reinterpret_cast<int2 *>(pairs)[off] = make_int2(i, pj[b][k]);
+              ++off;
+            }
+        } else {
+          emit_chunk(xm, thr, n, chunk, rowbuf, R, i, sidx[b], c[b], pairs, cap, off);
+        }
+      }
+    }
     return;
   }
   for (int s = 0; s < S && off < cap; ++s) {
@@ -517,7 +563,7 @@ hipError_t launch_emit(const KickArgs &a, int32_t *pairs, int64_t cap, int64_t *
                      a.rowmask, !emit);
   hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, count, cap, overflow);
   if (emit)
-    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kBlock), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
+    hipLaunchKernelGGL(k_emit, dim3((a.n + 63) / 64), dim3(64), 0, st, a.xm, a.thr, a.n, a.nchunk, a.chunk,
                        a.cnt, a.rowbuf, a.R, rowtot, bsum, pairs, cap, a.rowmask);
   return hipGetLastError();
 }
