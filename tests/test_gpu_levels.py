@@ -153,15 +153,15 @@ def test_levels_with_mergers_match_oracle(ctx):
     assert ex < 1e-10 and ev < 1e-10
 
 
-@pytest.mark.parametrize("L,s,steps", [(1, 4, 3), (2, 2, 2)])
-def test_levels_above_one_workgroup_match_oracle(ctx, L, s, steps):
+@pytest.mark.parametrize("n,L,s,steps", [(8192, 1, 4, 3), (8192, 2, 2, 2), (5003, 1, 4, 2)])
+def test_levels_above_one_workgroup_match_oracle(ctx, n, L, s, steps):
     """Above 4096 bodies the deepest level's groups are built by several launches (the unions inside
     the level kick, a flattening launch with member slices, the drift that resets the forest, with
-    two alternating size and counter buffers): the 32768 disk's recipe at 8192 bodies against the
-    oracle's recursion."""
-    say(f"levels L={L} s={s} disk8192 x{steps}")
+    two alternating size and counter buffers): the 32768 disk's recipe at 8192 bodies, and at a
+    ragged 5003, against the oracle's recursion."""
+    say(f"levels L={L} s={s} disk{n} x{steps}")
     p = diskgen.PARAMS
-    d = diskgen.workload("disk32768", n=8192)
+    d = diskgen.workload("disk32768", n=n)
     X, V = dev_state(d)
     thr = ctx.rcrit(X, V)
     stats = ctx.step_hybrid(X, V, steps, thr=thr, levels=L, substeps=s, margin=0.5)
