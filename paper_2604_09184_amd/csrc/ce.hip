@@ -198,17 +198,20 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
   const double dx = (__shfl(z[0], p.src, 64) - z[0]) + off;
   const double dy = (__shfl(z[1], p.src, 64) - z[1]) + off;
   const double dz = (__shfl(z[2], p.src, 64) - z[2]) + off;
-  const double r2 = dx * dx + dy * dy + dz * dz;
+  // (the library builds with contraction off: products that feed a sum are fused explicitly)
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   const double ir = rinv_refined(r2);
   const double r = r2 * ir;
   const double f_in = L.f_in;
   double c;
   if (NL == 1) {
     const double rcij = p.rcij, isp = p.isp;
-    const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
-    const double omy = 1.0 - y;
-    const double iD = recip_refined((2.0 * y * y - 2.0 * y) + 1.0);
-    c = ir * ir * (omy * omy * iD * ir + 2.0 * y * omy * iD * iD * isp);
+    const double y = fmin(fmax(fma(-f_in, rcij, r) * isp, 0.0), 1.0);
+    const double omy = 1.0 - y, y2 = 2.0 * y;
+    const double iD = recip_refined(fma(y2, y - 1.0, 1.0));
+    const double u = omy * iD;
+    // (1 - K) ir + K', times ir^2
+    c = (ir * ir) * fma(u * omy, ir, ((y2 * u) * iD) * isp);
   } else if (NL == 2) {
     // W = [1 - K_0][1 - K_1], the two levels' constants kept with the partner
     double W = 1.0, dW = 0.0;
@@ -216,14 +219,15 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
     for (int l = 0; l < 2; ++l) {
       const double rcij = l == 0 ? p.rcij : p.rcij1;
       const double isp = l == 0 ? p.isp : p.isp1;
-      const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
-      const double omy = 1.0 - y;
-      const double iD = recip_refined((2.0 * y * y - 2.0 * y) + 1.0);
-      const double omK = omy * omy * iD, dK = 2.0 * y * omy * iD * iD * isp;
-      dW = dW * omK - W * dK;
+      const double y = fmin(fmax(fma(-f_in, rcij, r) * isp, 0.0), 1.0);
+      const double omy = 1.0 - y, y2 = 2.0 * y;
+      const double iD = recip_refined(fma(y2, y - 1.0, 1.0));
+      const double u = omy * iD;
+      const double omK = u * omy, dK = ((y2 * u) * iD) * isp;
+      dW = fma(dW, omK, -(W * dK));
       W = W * omK;
     }
-    c = ir * ir * (W * ir - dW);
+    c = (ir * ir) * fma(W, ir, -dW);
   } else {
     double W = 1.0, dW = 0.0;
     for (int l = 0; l < L.nl; ++l) {
@@ -231,14 +235,15 @@ __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p
       const bool mine = rci > rcj;
       const double rcij = mine ? rci : rcj;
       const double isp = mine ? sh.lisp[l][L.rank] : sh.lisp[l][p.q];
-      const double y = fmin(fmax((r - f_in * rcij) * isp, 0.0), 1.0);
-      const double omy = 1.0 - y;
-      const double iD = recip_refined((2.0 * y * y - 2.0 * y) + 1.0);
-      const double omK = omy * omy * iD, dK = 2.0 * y * omy * iD * iD * isp;
-      dW = dW * omK - W * dK;
+      const double y = fmin(fmax(fma(-f_in, rcij, r) * isp, 0.0), 1.0);
+      const double omy = 1.0 - y, y2 = 2.0 * y;
+      const double iD = recip_refined(fma(y2, y - 1.0, 1.0));
+      const double u = omy * iD;
+      const double omK = u * omy, dK = ((y2 * u) * iD) * isp;
+      dW = fma(dW, omK, -(W * dK));
       W = W * omK;
     }
-    c = ir * ir * (W * ir - dW);
+    c = (ir * ir) * fma(W, ir, -dW);
   }
   const double cm = c * p.m.Gm;
   a0 = fma(cm, dx, a0);
@@ -266,7 +271,7 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
   const int P = PT > 0 ? PT : L.P;
   // the central term first: it does not depend on the partners, so its latency overlaps their
   // exchange
-  const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+  const double r2 = fma(z[2], z[2], fma(z[1], z[1], z[0] * z[0]));
   const double ir = rinv_refined(r2);
   const double s = -L.Gm0 * (ir * ir * ir);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -292,9 +297,9 @@ __device__ __forceinline__ void ce_rhs(const double (&z)[6], const CeLane &L, co
   f[0] = alive ? z[3] : 0.0;
   f[1] = alive ? z[4] : 0.0;
   f[2] = alive ? z[5] : 0.0;
-  f[3] = alive ? s * z[0] + a0 : 0.0;
-  f[4] = alive ? s * z[1] + a1 : 0.0;
-  f[5] = alive ? s * z[2] + a2 : 0.0;
+  f[3] = alive ? fma(s, z[0], a0) : 0.0;
+  f[4] = alive ? fma(s, z[1], a1) : 0.0;
+  f[5] = alive ? fma(s, z[2], a2) : 0.0;
 }
 
 // Modified-midpoint sweep of ns substeps over H from y, with f0 = f(y): the end value
@@ -309,7 +314,7 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], const double (&f0
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     zm[i] = y[i];
-    zc[i] = y[i] + hs * f0[i];
+    zc[i] = fma(hs, f0[i], y[i]);
   }
   // z_{m+1} = z_{m-1} + 2 hs f(z_m), m = 1 .. ns - 1, two steps per iteration so that the two state
   // arrays trade roles without copies (ns is even: one step is left over at the end)
@@ -317,18 +322,18 @@ __device__ __forceinline__ void ce_sweep(const double (&y)[6], const double (&f0
   for (int s = 1; s + 1 < ns; s += 2) {
     ce_rhs<NL, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) zm[i] = zm[i] + h2 * f[i];
+    for (int i = 0; i < 6; ++i) zm[i] = fma(h2, f[i], zm[i]);
     ce_rhs<NL, PT>(zm, L, sh, pr, alive, f);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) zc[i] = zc[i] + h2 * f[i];
+    for (int i = 0; i < 6; ++i) zc[i] = fma(h2, f[i], zc[i]);
   }
   ce_rhs<NL, PT>(zc, L, sh, pr, alive, f);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) zm[i] = zm[i] + h2 * f[i];
+  for (int i = 0; i < 6; ++i) zm[i] = fma(h2, f[i], zm[i]);
   // now zm = z_ns and zc = z_{ns-1}
   ce_rhs<NL, PT>(zm, L, sh, pr, alive, f);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) est[i] = 0.5 * (zm[i] + zc[i] + hs * f[i]);
+  for (int i = 0; i < 6; ++i) est[i] = 0.5 * fma(hs, f[i], zm[i] + zc[i]);
 }
 
 // Aitken-Neville over the kCols sweeps (substep counts 2c + 2) of one component:
@@ -344,7 +349,7 @@ __device__ __forceinline__ double ce_tableau(const double (&e)[kCols], double is
     for (int j = 1; j <= c; ++j) {
       // 1/((n_c/n_{c-j})^2 - 1) is a constant once the loops are unrolled: a multiplication
       const double ratio = (double)(c + 1) / (double)(c + 1 - j);
-      cur[j] = cur[j - 1] + (cur[j - 1] - prev[j - 1]) * (1.0 / (ratio * ratio - 1.0));
+      cur[j] = fma(cur[j - 1] - prev[j - 1], 1.0 / (ratio * ratio - 1.0), cur[j - 1]);
     }
     if (c >= 2) err[c] = fmax(err[c], fabs(cur[c] - cur[c - 1]) * iscale);
     if (c == want) out = cur[c];
