@@ -190,14 +190,14 @@ __device__ __forceinline__ CePartner ce_partner(int q, const CeLane &L, const Ce
 template <int NL>
 __device__ __forceinline__ void ce_pair(const double (&z)[6], const CePartner &p, const CeLane &L,
                                         const CeShared &sh, double &a0, double &a1, double &a2) {
-  // a term that does not count (no member, or the lane's own body) is moved 1e30 away: there the
-  // changeover weight is exactly zero, so the term adds exactly zero with no branch. The exchange
-  // runs on every lane (a lane shuffle reads only from active lanes), and the offset is added to
-  // its result
+  // a term that does not count (no member, or the lane's own body) is moved 1e30 away along x:
+  // there the changeover weight is exactly zero, so the term adds exactly zero (times finite
+  // offsets) with no branch. The exchange runs on every lane (a lane shuffle reads only from
+  // active lanes), and the offset is added to its result
   const double off = p.use ? 0.0 : 1e30;
   const double dx = (__shfl(z[0], p.src, 64) - z[0]) + off;
-  const double dy = (__shfl(z[1], p.src, 64) - z[1]) + off;
-  const double dz = (__shfl(z[2], p.src, 64) - z[2]) + off;
+  const double dy = __shfl(z[1], p.src, 64) - z[1];
+  const double dz = __shfl(z[2], p.src, 64) - z[2];
   // (the library builds with contraction off: products that feed a sum are fused explicitly)
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   const double ir = rinv_refined(r2);
