@@ -369,6 +369,64 @@ __device__ __forceinline__ void emit_chunk(const double4 *__restrict__ xm,
   }
 }
 
+// The partners of row i in the chunks its mask m names, appended at off (up to cap) in chunk and
+// slot order. Up to kBatch masked chunks at a time: their counts and their first kSlots slots are
+// loaded together before anything is stored (a masked chunk has at least one recorded partner,
+// and every slot below R lies inside the buffer, so the slots need not wait for the counts), so
+// a row waits for one memory round trip per batch rather than one per chunk and per partner.
+__device__ __forceinline__ void emit_row_masked(const double4 *__restrict__ xm,
+                                                const double4 *__restrict__ thr, int n, int chunk,
+                                                const int *__restrict__ cnt,
+                                                const int *__restrict__ rowbuf, int R, int i,
+                                                const unsigned long long (&m)[kRowMaskWords],
+                                                int32_t *__restrict__ pairs, int64_t cap,
+                                                int64_t &off) {
+  constexpr int kBatch = 8, kSlots = 4;
+  static_assert(kRowMaskWords == 4, "the word selection below");
+  const int ks = R < kSlots ? R : kSlots;
+  int w = 0;
+  unsigned long long cur = m[0];
+  while (off < cap) {
+    int sidx[kBatch], c[kBatch], pj[kBatch][kSlots];
+    int nb = 0;
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      while (cur == 0 && w < kRowMaskWords - 1) {
+        ++w;
+        cur = w == 1 ? m[1] : w == 2 ? m[2] : m[3];
+      }
+      sidx[b] = 0;
+      if (cur != 0) {
+        sidx[b] = 64 * w + __builtin_ctzll(cur);
+        cur &= cur - 1;
+        nb = b + 1;
+      }
+    }
+    if (nb == 0) break;
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      c[b] = b < nb ? cnt[(size_t)sidx[b] * n + i] : 0;
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k)
+        pj[b][k] = (b < nb && k < ks) ? rowbuf[((size_t)sidx[b] * R + k) * n + i] : 0;
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (b >= nb) break;
+      if (c[b] <= ks) {
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+          if (k < c[b] && off < cap) {
+            reinterpret_cast<int2 *>(pairs)[off] = make_int2(i, pj[b][k]);
+            ++off;
+          }
+      } else {
+        emit_chunk(xm, thr, n, chunk, rowbuf, R, i, sidx[b], c[b], pairs, cap, off);
+      }
+    }
+  }
+}
+
 // One wave per workgroup, 64 rows: the row offsets come per kBlock rows (boff), so a wave adds
 // the totals of the rows before its own within that block, then its own exclusive scan.
 __global__ __launch_bounds__(64) void k_emit(const double4 *__restrict__ xm,
@@ -405,52 +463,7 @@ __global__ __launch_bounds__(64) void k_emit(const double4 *__restrict__ xm,
   if (i >= n || mine == 0) return;
   int64_t off = boff[blk] + before + incl - mine;
   if (rowmask) {
-    // up to kBatch masked chunks at a time: their counts, then the first kSlots partners of each,
-    // are loaded before any of them is stored, so that a row waits for a few memory round trips
-    // rather than one per chunk and per partner; the stores keep chunk and slot order
-    constexpr int kBatch = 8, kSlots = 4;
-    static_assert(kRowMaskWords == 4, "the word selection below");
-    int w = 0;
-    unsigned long long cur = m[0];
-    while (off < cap) {
-      int sidx[kBatch], c[kBatch], pj[kBatch][kSlots];
-      int nb = 0;
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        while (cur == 0 && w < kRowMaskWords - 1) {
-          ++w;
-          cur = w == 1 ? m[1] : w == 2 ? m[2] : m[3];
-        }
-        sidx[b] = 0;
-        if (cur != 0) {
-          sidx[b] = 64 * w + __builtin_ctzll(cur);
-          cur &= cur - 1;
-          nb = b + 1;
-        }
-      }
-      if (nb == 0) break;
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) c[b] = b < nb ? cnt[(size_t)sidx[b] * n + i] : 0;
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b)
-#pragma unroll
-        for (int k = 0; k < kSlots; ++k)
-          pj[b][k] = (k < c[b] && c[b] <= R) ? rowbuf[((size_t)sidx[b] * R + k) * n + i] : 0;
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        if (b >= nb) break;
-        if (c[b] <= kSlots && c[b] <= R) {
-#pragma unroll
-          for (int k = 0; k < kSlots; ++k)
-            if (k < c[b] && off < cap) {
-              reinterpret_cast<int2 *>(pairs)[off] = make_int2(i, pj[b][k]);
-              ++off;
-            }
-        } else {
-          emit_chunk(xm, thr, n, chunk, rowbuf, R, i, sidx[b], c[b], pairs, cap, off);
-        }
-      }
-    }
+    emit_row_masked(xm, thr, n, chunk, cnt, rowbuf, R, i, m, pairs, cap, off);
     return;
   }
   for (int s = 0; s < S && off < cap; ++s) {
