@@ -37,7 +37,7 @@ enum BufId { B_PART, B_PART_CE, B_CNT, B_ROWBUF, B_ROWTOT, B_BSUM, B_ROWSUM, B_R
              B_B_CFG, B_B_THR, B_B_QUEUE, B_T_XM, B_T_V, B_B_PART, B_PERM, B_CELL,
              B_RANGE, B_CCOUNT, B_CCURSOR, B_MPART, B_UNI, B_VKEY, B_GIN, B_GSIZE,
              B_GSTART, B_GFILL, B_GMEM, B_GROOT, B_GCNT, B_HPAIRS, B_HCOUNT, B_HLAB, B_LTHR, B_ADEG, B_AOFF,
-             B_AFILL, B_ADJ, B_LSKIP, B_ATOT, B_ETHR, B_GSIZE2, B_GCNT2, B_GSLICE, B_NUM };
+             B_AFILL, B_ADJ, B_LSKIP, B_ATOT, B_ETHR, B_GSIZE2, B_GCNT2, B_GSLICE, B_ALONG, B_NUM };
 
 }  // namespace
 
@@ -803,9 +803,10 @@ int nbody_step_hybrid(nbody_ctx *c, int64_t n, double *xm, double *v, const doub
     la.off = (int *)ensure(c, B_AOFF, (size_t)n * sizeof(int));
     la.fill = (int *)ensure(c, B_AFILL, (size_t)n * sizeof(int));
     la.adj = (int *)ensure(c, B_ADJ, (size_t)cap * 2 * sizeof(int));
-    la.total = (int *)ensure(c, B_ATOT, sizeof(int));
+    la.total = (int *)ensure(c, B_ATOT, 2 * sizeof(int));
+    la.longv = (int *)ensure(c, B_ALONG, (size_t)n * sizeof(int));
     lskip = (int *)ensure(c, B_LSKIP, (size_t)n * sizeof(int));
-    if (!lthr || !la.deg || !la.off || !la.fill || !la.adj || !la.total || !lskip)
+    if (!lthr || !la.deg || !la.off || !la.fill || !la.adj || !la.total || !la.longv || !lskip)
       return fail(c, NBODY_E_NOMEM, "workspace allocation failed (changeover levels)");
     if (!small) {
       lgs[1] = (int *)ensure(c, B_GSIZE2, (size_t)n * sizeof(int));

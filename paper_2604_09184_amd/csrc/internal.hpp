@@ -178,9 +178,10 @@ hipError_t launch_ce_drift(double4 *xm, double4 *v, const double4 *thr, const in
 
 // levels.hip: symmetric adjacency of a pair list (rows sorted by neighbour index), the level kicks
 // over it and the masks of the level drifts.
-// deg/off/fill [n]; adj [2 cap] (the neighbour per slot); total: slots used.
+// deg/off/fill [n]; adj [2 cap] (the neighbour per slot); total [2]: slots used and the number of
+// rows in longv [n] (the rows the level kick gives a whole wave).
 struct LevelAdj {
-  int *deg, *off, *fill, *adj, *total;
+  int *deg, *off, *fill, *adj, *total, *longv;
 };
 hipError_t launch_adjacency(const int32_t *pairs, int64_t cap, const int64_t *count, int n,
                             const LevelAdj &g, hipStream_t st);
