@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sort(const int *__restrict__ off
       if (c2 * 64 >= d) break;
       const int lim = min(64, d - c2 * 64);
       for (int m = 0; m < lim; ++m) {
-        const int x = __shfl(a[c2], m, 64);
+        const int x = __builtin_amdgcn_readlane(a[c2], m);   // m is wave-uniform: a broadcast
 #pragma unroll
         for (int c = 0; c < kSortChunks; ++c) rank[c] += x < a[c];
       }
