@@ -50,11 +50,19 @@ __global__ __launch_bounds__(1024) void k_momentum_jump_small(double4 *__restric
   __shared__ double4 mom[kJumpSmall / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int nb = (n + 63) / 64;
-  for (int b = w; b < nb; b += 16) {
+  // block b = w + 16 u holds body t + 1024 u: the positions read for the momentum are the ones
+  // this thread jumps, kept in registers
+  constexpr int kPer = kJumpSmall / 1024;
+  double4 pos[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int b = w + 16 * u;
+    if (b >= nb) break;
     const int i = b * 64 + lane;
     double P[3] = {0.0, 0.0, 0.0};
     if (i < n) {
-      const double m = xm[i].w;
+      pos[u] = xm[i];
+      const double m = pos[u].w;
       const double4 q = v[i];
       P[0] = m * q.x; P[1] = m * q.y; P[2] = m * q.z;
     }
@@ -65,8 +73,11 @@ __global__ __launch_bounds__(1024) void k_momentum_jump_small(double4 *__restric
   double P[3];
   partials_total_wave(mom, nb, P);
   const double sx = h * (P[0] / m0), sy = h * (P[1] / m0), sz = h * (P[2] / m0);
-  for (int i = t; i < n; i += 1024) {
-    double4 p = xm[i];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = t + 1024 * u;
+    if (i >= n) break;
+    double4 p = pos[u];
     p.x = p.x + sx; p.y = p.y + sy; p.z = p.z + sz;
     xm[i] = p;
   }
